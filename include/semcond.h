@@ -1,0 +1,233 @@
+/*
+ * semcond.h -- C ABI of the MI355X (gfx950) statically condensed spectral-element
+ * Helmholtz solver.
+ *
+ * Problem (Huismann, Stiller & Froehlich, "Factorizing the factorization",
+ * arXiv 1601.08179, Sec. 3, eq. helmholtz_equation):  lambda*u - Laplace(u) = f
+ * on a box meshed by n1 x n2 x n3 Cartesian elements with per-axis widths, GLL
+ * degree p in every direction, lambda >= 0, Dirichlet or natural conditions per
+ * domain face.  The library solves the statically condensed system of Sec. 4
+ * (eq. condensation_system) for the element skeleton, with the operator applied
+ * in the fast-diagonalisation ("transformed") basis of Sec. 6 (Table 2,
+ * Algorithm 4), preconditioned conjugate gradients with the preconditioner that
+ * is diagonal in that basis (the "BT" solver of Sec. 8).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Element (e1,e2,e3) has linear number e = e1 + n1*(e2 + n2*e3).
+ * - Global GLL node (I1,I2,I3), 0 <= I_a <= n_a*p, has nodal number
+ *   I1 + (n1*p+1)*(I2 + (n2*p+1)*I3).  N = prod(n_a*p+1).  "Nodal" arrays are
+ *   [k][N] (right-hand side major), FP64 unless stated.
+ * - "Skeleton" arrays hold the N_s nodes on element faces, edges and vertices,
+ *   entity-major with the right-hand-side index innermost: [N_s][k].  The order
+ *   of skeleton slots is fixed by the library; semcond_skeleton_coords() gives
+ *   the global (I1,I2,I3) of every slot.  Slots on Dirichlet faces exist and
+ *   are ignored on input and written as 0 on output.
+ * - A skeleton array is either in the PHYSICAL basis (nodal values) or in the
+ *   TRANSFORMED basis of Sec. 6: per face u~ = (S^-1 (x) S^-1) u over its two
+ *   interior directions, per edge u~ = S^-1 u, vertices unchanged, where the
+ *   n_I x n_I matrix S (n_I = p-1) satisfies S^T M_II S = I, S^T K_II S = Lambda
+ *   (Sec. 5, eq. generalized_eigenvalues, in the transpose convention that
+ *   makes H_II^-1 = (S(x)S(x)S) D^-1 (S(x)S(x)S)^T hold).
+ * - Device pointers are owned by the caller; the library never frees them.
+ *   All device work is stream-ordered on the given HIP stream (hipStream_t
+ *   passed as void*, NULL = default stream) and asynchronous unless stated.
+ * - Every entry point returns an int status.  No C++ exception or abort
+ *   crosses the ABI.  semcond_last_error() describes the last failure.
+ * - A context may be used by one host thread at a time.
+ */
+#ifndef SEMCOND_H
+#define SEMCOND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define SEMCOND_OK          0   /* success                                         */
+#define SEMCOND_ENOTCONV    1   /* solve hit max_iter; best iterate returned       */
+#define SEMCOND_EINVAL     -1   /* invalid argument                                */
+#define SEMCOND_ENOMEM     -2   /* device or host allocation failed                */
+#define SEMCOND_EDEVICE    -3   /* HIP runtime error                               */
+#define SEMCOND_EBREAKDOWN -4   /* p^T A p <= 0 in CG: operator not positive       */
+#define SEMCOND_ENONFINITE -5   /* NaN or Inf met in the iteration                 */
+
+/* Scalar type of device arrays. */
+#define SEMCOND_F64 0
+#define SEMCOND_F32 1
+
+/* Basis of skeleton arrays. */
+#define SEMCOND_PHYSICAL    0
+#define SEMCOND_TRANSFORMED 1
+
+/* semcond_transform directions (per skeleton entity, see conventions). */
+#define SEMCOND_COEF_TO_TRANSFORMED    0  /* u~ = T^-1 u   (S^-1 = S^T M_II per axis) */
+#define SEMCOND_COEF_TO_PHYSICAL       1  /* u  = T u~     (S per axis)               */
+#define SEMCOND_DUAL_TO_TRANSFORMED    2  /* r~ = T^T r    (S^T per axis)             */
+#define SEMCOND_DUAL_TO_PHYSICAL       3  /* r  = T^-T r~  (M_II S per axis)          */
+
+/* Solver precision modes. */
+#define SEMCOND_PREC_F64      0   /* FP64 operator and CG                          */
+#define SEMCOND_PREC_F32      1   /* FP32 operator and CG vectors, FP64 dots       */
+#define SEMCOND_PREC_MIXED_IR 2   /* FP32 inner CG, FP64 iterative refinement      */
+
+typedef struct semcond_ctx semcond_ctx;
+
+/*
+ * Mesh and problem (Sec. 3: element widths h_{e,1..3}, degree p, lambda; the
+ * metric coefficients d_e = (h1 h2 h3/8)(lambda, 4/h1^2, 4/h2^2, 4/h3^2),
+ * eq. metriccoeffelement).  All pointers are HOST pointers, copied at create.
+ *   p               2 <= p <= 32
+ *   n[3]            elements per axis, each >= 1, n1*n2*n3 <= 2^26
+ *   widths[a]       n[a] positive finite widths along axis a
+ *   lambda          Helmholtz parameter >= 0 (used when lambda_e is NULL)
+ *   lambda_e        optional per-element lambda (n_e entries, >= 0), or NULL
+ *   dcoef_e         optional per-element metric override d_e (n_e x 4, row
+ *                   per element, entries 1..3 > 0, entry 0 >= 0), or NULL;
+ *                   when given it replaces widths/lambda in the operator (the
+ *                   RHS mass matrix still uses the widths)
+ *   dirichlet_mask  bit 0: x1-low face, 1: x1-high, 2: x2-low, 3: x2-high,
+ *                   4: x3-low, 5: x3-high.  Set bits carry homogeneous
+ *                   Dirichlet conditions, clear bits natural ones.  With
+ *                   lambda = 0 at least one bit must be set.
+ */
+typedef struct {
+    int p;
+    int n[3];
+    const double* widths[3];
+    double lambda;
+    const double* lambda_e;
+    const double* dcoef_e;
+    unsigned dirichlet_mask;
+} semcond_mesh;
+
+/* Options of semcond_solve.  semcond_solve_opts_default() fills defaults. */
+typedef struct {
+    double tol;             /* stop at ||r~||_2 <= tol*||F^~||_2 (Sec. 8), default 1e-10  */
+    int max_iter;           /* CG iterations per RHS (inner for MIXED_IR), default 20000  */
+    int precision;          /* SEMCOND_PREC_*, default F64                                */
+    int check_every;        /* host polls convergence every this many iterations, def. 8  */
+    int recover_interior;   /* 1: also write interior nodes of u_nodal (Alg. 4), def. 1   */
+    const void* x0;         /* optional initial guess, TRANSFORMED skeleton [N_s][k] FP64 */
+    void* skel_out;         /* optional out: TRANSFORMED skeleton solution [N_s][k] FP64  */
+    double inner_tol;       /* MIXED_IR: relative tolerance of each FP32 inner solve      */
+    int max_outer;          /* MIXED_IR: refinement steps, default 30                     */
+} semcond_solve_opts;
+
+/* Per right-hand-side result of semcond_solve (host array of k entries). */
+typedef struct {
+    int iters;              /* CG iterations (summed over refinement steps)   */
+    int outer;              /* refinement steps (MIXED_IR), else 0            */
+    double rel_res;         /* final ||r~||_2 / ||F^~||_2 in FP64             */
+    int status;             /* SEMCOND_OK / ENOTCONV / EBREAKDOWN / ENONFINITE */
+} semcond_solve_info;
+
+/* Library version string (static storage). */
+const char* semcond_version(void);
+
+/* Message of the last failure on ctx (or of the last failed create when ctx
+ * is NULL).  Valid until the next call on the same context. */
+const char* semcond_last_error(const semcond_ctx* ctx);
+
+/*
+ * Host-only 1D tables of degree p (no device needed).  Any output pointer may
+ * be NULL.  Arrays are row-major.
+ *   x[p+1], w[p+1]     GLL nodes and weights (Sec. 3)
+ *   K[(p+1)^2]         stiffness matrix K_ij = int phi_i' phi_j' (Sec. 3)
+ *   S[(p-1)^2]         generalized eigenvectors, column m = eigenvector m,
+ *                      S^T M_II S = I, S^T K_II S = Lambda (Sec. 5)
+ *   lam[p-1]           eigenvalues Lambda in ascending order
+ * Returns EINVAL unless 2 <= p <= 32.
+ */
+int semcond_host_tables(int p, double* x, double* w, double* K, double* S, double* lam);
+
+/*
+ * Create a context: validates the mesh, builds the 1D tables on the host,
+ * uploads tables, metric data and the preconditioner diagonal (Sec. 8: exact
+ * inverse of each face/edge/vertex self-block, diagonal in the transformed
+ * basis) to the current HIP device.  stream: where set-up work is queued; the
+ * call synchronises it before returning.  *out receives the context.
+ * Errors: EINVAL (bad mesh), ENOMEM, EDEVICE.
+ */
+int semcond_create(const semcond_mesh* mesh, void* stream, semcond_ctx** out);
+
+/* Release a context and its device memory (synchronises the device). */
+int semcond_destroy(semcond_ctx* ctx);
+
+/* Sizes: total nodes N, skeleton nodes N_s (layout length), free (unconstrained)
+ * skeleton nodes, elements.  Any pointer may be NULL. */
+int semcond_sizes(const semcond_ctx* ctx, int64_t* N, int64_t* N_s, int64_t* N_free,
+                  int64_t* n_e);
+
+/* Host array ijk[N_s*3] receives (I1,I2,I3) of every skeleton slot, and the
+ * optional host array free_mask[N_s] receives 1 for unconstrained slots. */
+int semcond_skeleton_coords(const semcond_ctx* ctx, int32_t* ijk, uint8_t* free_mask);
+
+/*
+ * Condensed operator apply  v = R H^_L R^T u  on the skeleton (Sec. 4), via the
+ * tensor-product factorisation in the transformed basis (Sec. 6, Table 2,
+ * Algorithm 3 in transformed form): primary part from the transformed 1D
+ * matrices, face -> inner eigenspace, diagonal scaling D^-1, eigenspace -> face.
+ *   u, v   device [N_s][k], scalar type dtype (SEMCOND_F64 or SEMCOND_F32),
+ *          u and v must not overlap
+ *   basis  SEMCOND_TRANSFORMED: u, v in the transformed basis (the operator
+ *          T^T H^ T).  SEMCOND_PHYSICAL: u, v nodal (the operator H^ itself;
+ *          the library transforms in and out using its workspace).
+ * Constrained slots of u are ignored; those of v are written 0.
+ */
+int semcond_apply(semcond_ctx* ctx, const void* u, void* v, int k, int dtype, int basis,
+                  void* stream);
+
+/* Basis change of skeleton arrays (direction: SEMCOND_COEF_TO_TRANSFORMED, ...).
+ * in, out: device [N_s][k] of dtype, must not overlap. */
+int semcond_transform(semcond_ctx* ctx, const void* in, void* out, int k, int dtype,
+                      int direction, void* stream);
+
+/* Diagonal of the transformed condensed operator restricted to free slots,
+ * diag(R H~^_L R^T) (Sec. 8: the BT preconditioner), device [N_s] of dtype;
+ * constrained slots receive 0. */
+int semcond_precond_diag(semcond_ctx* ctx, void* diag, int dtype, void* stream);
+
+/*
+ * Condensed right-hand side in the transformed basis (Algorithm 4, first loop):
+ * F_e = J_e (W(x)W(x)W) f_e (GLL-lumped mass, J_e = h1 h2 h3/8), F~_e = T^T F_e,
+ * F^~ = R (F~_B - H~_BI H~_II^-1 F~_I).
+ *   f_nodal  device [k][N] FP64, nodal right-hand sides
+ *   fhat     device [N_s][k] of dtype, TRANSFORMED basis
+ */
+int semcond_condense_rhs(semcond_ctx* ctx, const void* f_nodal, void* fhat, int k, int dtype,
+                         void* stream);
+
+/* Copy skeleton values into a nodal array (skeleton nodes only; other entries
+ * of nodal untouched), or gather them from a nodal array.  FP64.
+ *   skel device [N_s][k], nodal device [k][N]. */
+int semcond_skeleton_to_nodal(semcond_ctx* ctx, const void* skel, void* nodal, int k,
+                              void* stream);
+int semcond_nodal_to_skeleton(semcond_ctx* ctx, const void* nodal, void* skel, int k,
+                              void* stream);
+
+/* Fill *opts with the defaults documented in semcond_solve_opts. */
+void semcond_solve_opts_default(semcond_solve_opts* opts);
+
+/*
+ * Solve lambda*u - Laplace(u) = f for k right-hand sides (Algorithm 4 with the
+ * BT conjugate-gradient solver of Sec. 8, x0 = 0 unless opts->x0).
+ *   f_nodal  device [k][N] FP64
+ *   u_nodal  device [k][N] FP64; skeleton nodes always written (physical
+ *            basis), interior nodes too when opts->recover_interior
+ *   opts     host, NULL = defaults
+ *   info     host array of k entries, may be NULL
+ * Synchronises the stream before returning.  Returns OK when every RHS
+ * converged, ENOTCONV when some hit max_iter (their best iterate is returned),
+ * EBREAKDOWN / ENONFINITE on numerical failure.
+ */
+int semcond_solve(semcond_ctx* ctx, const void* f_nodal, void* u_nodal, int k,
+                  const semcond_solve_opts* opts, semcond_solve_info* info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEMCOND_H */

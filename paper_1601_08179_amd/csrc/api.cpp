@@ -1,0 +1,638 @@
+// C ABI of the condensed spectral-element Helmholtz solver (see include/semcond.h).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/semcond.h"
+#include "kernels.h"
+#include "layout.h"
+#include "tables.h"
+
+using namespace semcond;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+// Device copy of the 1D tables of one scalar type.
+template <typename T>
+struct DevTables {
+    T* buf = nullptr;
+    DevTab<T> tab{};
+};
+
+struct Buffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct semcond_ctx {
+    int p = 0;
+    int n[3] = {0, 0, 0};
+    int64_t n_e = 0, N = 0, N_s = 0, N_free = 0;
+    Layout L{};
+    Tables1D t;
+    std::string err;
+    // device data
+    DevTables<double> t64;
+    DevTables<float> t32;
+    double* d_widths = nullptr;  // n1 + n2 + n3
+    double* d_lam_e = nullptr;
+    double* d_dcoef = nullptr;
+    double* d_diag = nullptr;    // [N_s]
+    double* d_pinv64 = nullptr;  // [N_s]
+    float* d_pinv32 = nullptr;   // [N_s]
+    Geo geo{};
+    // workspace (grown on demand)
+    Buffer ws_vec;      // vectors for apply / solve
+    Buffer ws_scratch;  // element cubes for large p
+    Buffer ws_state;    // CG scalars (device)
+    int* h_active = nullptr;  // pinned host copy of CG activity flags
+    int h_active_cap = 0;
+};
+
+namespace {
+
+int fail(semcond_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    g_last_error = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e__ = (call);                                                            \
+        if (e__ != hipSuccess)                                                              \
+            return fail((ctx), SEMCOND_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e__)); \
+    } while (0)
+
+int grow(semcond_ctx* c, Buffer& b, size_t bytes) {
+    if (b.bytes >= bytes) return SEMCOND_OK;
+    if (b.ptr) {
+        hipDeviceSynchronize();
+        hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    if (hipMalloc(&b.ptr, bytes) != hipSuccess) {
+        b.ptr = nullptr;
+        return fail(c, SEMCOND_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    b.bytes = bytes;
+    return SEMCOND_OK;
+}
+
+template <typename T>
+int upload_tables(semcond_ctx* c, DevTables<T>& d) {
+    const Tables1D& t = c->t;
+    const int NI = t.NI, n = t.p + 1;
+    const size_t count = 3 * NI + 4 * (size_t)NI * NI + n;
+    std::vector<T> h(count);
+    size_t o = 0;
+    auto put = [&](const std::vector<double>& v) {
+        for (double x : v) h[o++] = (T)x;
+    };
+    put(t.lam);
+    put(t.a);
+    put(t.b);
+    put(t.S);
+    for (int i = 0; i < NI; ++i)
+        for (int m = 0; m < NI; ++m) h[o++] = (T)t.S[(size_t)m * NI + i];  // S^T
+    put(t.Sinv);
+    put(t.SinvT);
+    put(t.w);
+    HIPCHK(c, hipMalloc(&d.buf, count * sizeof(T)));
+    HIPCHK(c, hipMemcpy(d.buf, h.data(), count * sizeof(T), hipMemcpyHostToDevice));
+    T* b = d.buf;
+    d.tab.lam = b;
+    d.tab.a = b + NI;
+    d.tab.b = b + 2 * NI;
+    d.tab.S = b + 3 * NI;
+    d.tab.St = d.tab.S + NI * NI;
+    d.tab.Sinv = d.tab.St + NI * NI;
+    d.tab.SinvT = d.tab.Sinv + NI * NI;
+    d.tab.w = d.tab.SinvT + NI * NI;
+    d.tab.m0 = (T)t.m0;
+    d.tab.K00 = (T)t.K00;
+    d.tab.K0p = (T)t.K0p;
+    return SEMCOND_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int check_dtype(semcond_ctx* c, int dtype) {
+    if (dtype != SEMCOND_F64 && dtype != SEMCOND_F32) return fail(c, SEMCOND_EINVAL, "dtype must be F64 or F32");
+    return SEMCOND_OK;
+}
+
+int check_k(semcond_ctx* c, int k) {
+    if (k < 1 || k > 256) return fail(c, SEMCOND_EINVAL, "k must be in [1, 256]");
+    return SEMCOND_OK;
+}
+
+template <typename T>
+const DevTab<T>& tabs(semcond_ctx* c);
+template <>
+const DevTab<double>& tabs<double>(semcond_ctx* c) { return c->t64.tab; }
+template <>
+const DevTab<float>& tabs<float>(semcond_ctx* c) { return c->t32.tab; }
+
+template <typename T>
+const T* pinv(semcond_ctx* c);
+template <>
+const double* pinv<double>(semcond_ctx* c) { return c->d_pinv64; }
+template <>
+const float* pinv<float>(semcond_ctx* c) { return c->d_pinv32; }
+
+// v = H~^ u (transformed).  v is zeroed first.  energy: optional [n_e][k].
+template <typename T>
+int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, double* energy, hipStream_t st) {
+    HIPCHK(c, launch_fill<T>(v, c->N_s * k, (T)0, st));
+    ApplyArgs<T> a;
+    a.g = c->geo;
+    a.tab = tabs<T>(c);
+    a.u = u;
+    a.v = v;
+    a.k = k;
+    a.energy = energy;
+    a.e_begin = 0;
+    HIPCHK(c, launch_apply_tpt<T>(a, c->n_e, st));
+    return SEMCOND_OK;
+}
+
+template <typename T>
+const T* transform_matrix(semcond_ctx* c, int direction) {
+    const DevTab<T>& t = tabs<T>(c);
+    switch (direction) {
+        case SEMCOND_COEF_TO_TRANSFORMED: return t.Sinv;
+        case SEMCOND_COEF_TO_PHYSICAL: return t.S;
+        case SEMCOND_DUAL_TO_TRANSFORMED: return t.St;
+        case SEMCOND_DUAL_TO_PHYSICAL: return t.SinvT;
+        default: return nullptr;
+    }
+}
+
+int scratch_for_cubes(semcond_ctx* c, int* grid, double** scratch) {
+    bool need = false;
+    *grid = rhs_grid_for_scratch(c->p, c->n_e, &need);
+    *scratch = nullptr;
+    if (need) {
+        const size_t n = (size_t)(c->p + 1);
+        int rc = grow(c, c->ws_scratch, (size_t)(*grid) * n * n * n * sizeof(double));
+        if (rc) return rc;
+        *scratch = (double*)c->ws_scratch.ptr;
+    }
+    return SEMCOND_OK;
+}
+
+// fhat (FP64, transformed) = condensed RHS of nodal f.
+int condense_rhs64(semcond_ctx* c, const double* f, double* fhat, int k, hipStream_t st) {
+    int grid;
+    double* scratch;
+    int rc = scratch_for_cubes(c, &grid, &scratch);
+    if (rc) return rc;
+    HIPCHK(c, launch_fill<double>(fhat, c->N_s * k, 0.0, st));
+    HIPCHK(c, launch_condense_rhs(c->geo, c->t64.tab, f, c->N, fhat, k, scratch, grid, st));
+    return SEMCOND_OK;
+}
+
+struct CgWork {
+    CgState s;
+    double* partials;  // [3][kVecBlocks][k]
+    double* energy;    // [n_e][k]
+};
+
+// Device state layout inside ws_state.
+int cg_state(semcond_ctx* c, int k, CgWork* w) {
+    const size_t nd = 7 * (size_t)k + 1;               // rho pq alpha beta rr bb (6k) + spare k + tol2
+    const size_t ni = 3 * (size_t)k;                    // active iters status
+    const size_t np = 3 * (size_t)kVecBlocks * k;
+    const size_t ne = (size_t)c->n_e * k;
+    const size_t bytes = (nd + np + ne) * sizeof(double) + ni * sizeof(int) + 256;
+    int rc = grow(c, c->ws_state, bytes);
+    if (rc) return rc;
+    double* d = (double*)c->ws_state.ptr;
+    w->s.rho = d;
+    w->s.pq = d + k;
+    w->s.alpha = d + 2 * k;
+    w->s.beta = d + 3 * k;
+    w->s.rr = d + 4 * k;
+    w->s.bb = d + 5 * k;
+    w->s.tol2 = d + 7 * k;
+    w->partials = d + nd;
+    w->energy = w->partials + np;
+    int* ip = (int*)(w->energy + ne);
+    w->s.active = ip;
+    w->s.iters = ip + k;
+    w->s.status = ip + 2 * k;
+    if (c->h_active_cap < 3 * k) {
+        if (c->h_active) hipHostFree(c->h_active);
+        c->h_active = nullptr;
+        c->h_active_cap = 0;
+        if (hipHostMalloc((void**)&c->h_active, 3 * k * sizeof(int)) != hipSuccess)
+            return fail(c, SEMCOND_ENOMEM, "pinned host allocation failed");
+        c->h_active_cap = 3 * k;
+    }
+    return SEMCOND_OK;
+}
+
+// Preconditioned CG on the transformed condensed system, k RHS, type T.
+// b, x, r, p, q: [N_s][k] of T.  x holds the initial guess on entry (x0_given)
+// or is zeroed.  Returns per-RHS iterations/status through the state.
+template <typename T>
+int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol, int max_iter,
+           int check_every, bool x0_given, CgWork& w, hipStream_t st) {
+    const int64_t Ns = c->N_s;
+    const double tol2 = tol * tol;
+    HIPCHK(c, hipMemcpyAsync(w.s.tol2, &tol2, sizeof(double), hipMemcpyHostToDevice, st));
+    if (x0_given) {
+        int rc = apply_transformed<T>(c, x, q, k, nullptr, st);
+        if (rc) return rc;
+        HIPCHK(c, launch_cg_init<T>(b, q, pinv<T>(c), r, p, Ns, k, w.partials, st));
+    } else {
+        HIPCHK(c, launch_fill<T>(x, Ns * k, (T)0, st));
+        HIPCHK(c, launch_cg_init<T>(b, nullptr, pinv<T>(c), r, p, Ns, k, w.partials, st));
+    }
+    HIPCHK(c, launch_cg_reduce(w.partials, kVecBlocks, 3, k, w.s, RED_INIT, st));
+    if (check_every < 1) check_every = 1;
+    for (int it = 0; it < max_iter; ++it) {
+        if (it % check_every == 0) {
+            HIPCHK(c, hipMemcpyAsync(c->h_active, w.s.active, k * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            bool any = false;
+            for (int i = 0; i < k; ++i) any |= c->h_active[i] != 0;
+            if (!any) break;
+        }
+        int rc = apply_transformed<T>(c, p, q, k, w.energy, st);
+        if (rc) return rc;
+        HIPCHK(c, launch_cg_reduce(w.energy, c->n_e, 1, k, w.s, RED_PQ, st));
+        HIPCHK(c, launch_cg_update<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, st));
+        HIPCHK(c, launch_cg_reduce(w.partials, kVecBlocks, 2, k, w.s, RED_RZ, st));
+        HIPCHK(c, launch_cg_direction<T>(p, r, pinv<T>(c), Ns, k, w.s, st));
+    }
+    return SEMCOND_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* semcond_version(void) { return "semcond 0.1 (gfx950)"; }
+
+const char* semcond_last_error(const semcond_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_last_error.c_str();
+}
+
+int semcond_host_tables(int p, double* x, double* w, double* K, double* Sm, double* lam) {
+    Tables1D t;
+    if (!build_tables(p, &t)) return fail(nullptr, SEMCOND_EINVAL, "p must be in [2, 32]");
+    if (x) std::memcpy(x, t.x.data(), t.x.size() * sizeof(double));
+    if (w) std::memcpy(w, t.w.data(), t.w.size() * sizeof(double));
+    if (K) std::memcpy(K, t.K.data(), t.K.size() * sizeof(double));
+    if (Sm) std::memcpy(Sm, t.S.data(), t.S.size() * sizeof(double));
+    if (lam) std::memcpy(lam, t.lam.data(), t.lam.size() * sizeof(double));
+    return SEMCOND_OK;
+}
+
+int semcond_destroy(semcond_ctx* c) {
+    if (!c) return SEMCOND_OK;
+    hipDeviceSynchronize();
+    hipFree(c->t64.buf);
+    hipFree(c->t32.buf);
+    hipFree(c->d_widths);
+    hipFree(c->d_lam_e);
+    hipFree(c->d_dcoef);
+    hipFree(c->d_diag);
+    hipFree(c->d_pinv64);
+    hipFree(c->d_pinv32);
+    hipFree(c->ws_vec.ptr);
+    hipFree(c->ws_scratch.ptr);
+    hipFree(c->ws_state.ptr);
+    if (c->h_active) hipHostFree(c->h_active);
+    delete c;
+    return SEMCOND_OK;
+}
+
+int semcond_create(const semcond_mesh* m, void* stream, semcond_ctx** out) {
+    if (!out) return fail(nullptr, SEMCOND_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!m) return fail(nullptr, SEMCOND_EINVAL, "mesh is NULL");
+    if (m->p < 2 || m->p > kMaxP) return fail(nullptr, SEMCOND_EINVAL, "p must be in [2, 32]");
+    int64_t ne = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (m->n[a] < 1) return fail(nullptr, SEMCOND_EINVAL, "n[a] must be >= 1");
+        if (!m->widths[a]) return fail(nullptr, SEMCOND_EINVAL, "widths[a] is NULL");
+        for (int i = 0; i < m->n[a]; ++i)
+            if (!finite_pos(m->widths[a][i])) return fail(nullptr, SEMCOND_EINVAL, "widths must be positive and finite");
+        ne *= m->n[a];
+    }
+    if (ne > (int64_t(1) << 26)) return fail(nullptr, SEMCOND_EINVAL, "too many elements (max 2^26)");
+    if (m->dirichlet_mask > 63u) return fail(nullptr, SEMCOND_EINVAL, "dirichlet_mask has bits above 5");
+    if (!m->lambda_e && !m->dcoef_e && !(std::isfinite(m->lambda) && m->lambda >= 0.0))
+        return fail(nullptr, SEMCOND_EINVAL, "lambda must be finite and >= 0");
+    bool any_d0 = !m->lambda_e && !m->dcoef_e && m->lambda > 0.0;
+    if (m->lambda_e)
+        for (int64_t e = 0; e < ne; ++e) {
+            if (!(std::isfinite(m->lambda_e[e]) && m->lambda_e[e] >= 0.0))
+                return fail(nullptr, SEMCOND_EINVAL, "lambda_e must be finite and >= 0");
+            any_d0 |= m->lambda_e[e] > 0.0;
+        }
+    if (m->dcoef_e) {
+        any_d0 = false;
+        for (int64_t e = 0; e < ne; ++e) {
+            const double* d = m->dcoef_e + 4 * e;
+            if (!(std::isfinite(d[0]) && d[0] >= 0.0) || !finite_pos(d[1]) || !finite_pos(d[2]) || !finite_pos(d[3]))
+                return fail(nullptr, SEMCOND_EINVAL, "dcoef_e entries invalid");
+            any_d0 |= d[0] > 0.0;
+        }
+    }
+    if (!any_d0 && m->dirichlet_mask == 0)
+        return fail(nullptr, SEMCOND_EINVAL, "lambda = 0 everywhere needs at least one Dirichlet face");
+
+    semcond_ctx* c = new (std::nothrow) semcond_ctx();
+    if (!c) return fail(nullptr, SEMCOND_ENOMEM, "host allocation failed");
+    c->p = m->p;
+    for (int a = 0; a < 3; ++a) c->n[a] = m->n[a];
+    c->n_e = ne;
+    if (!build_tables(m->p, &c->t)) {
+        delete c;
+        return fail(nullptr, SEMCOND_EINVAL, "table construction failed");
+    }
+    c->L = make_layout(m->p, m->n, m->dirichlet_mask);
+    c->N_s = c->L.Ns;
+    c->N = (int64_t)(m->n[0] * (int64_t)m->p + 1) * (m->n[1] * (int64_t)m->p + 1) * (m->n[2] * (int64_t)m->p + 1);
+    int64_t nfree = 0;
+    for (int64_t s = 0; s < c->N_s; ++s) {
+        int I1, I2, I3;
+        bool con;
+        skeleton_node(c->L, s, &I1, &I2, &I3, &con);
+        nfree += con ? 0 : 1;
+    }
+    c->N_free = nfree;
+    hipStream_t st = S(stream);
+    auto bail = [&](int rc) {
+        std::string msg = c->err;
+        semcond_destroy(c);
+        g_last_error = msg;
+        return rc;
+    };
+    int rc = upload_tables<double>(c, c->t64);
+    if (!rc) rc = upload_tables<float>(c, c->t32);
+    if (rc) return bail(rc);
+    const int nw = m->n[0] + m->n[1] + m->n[2];
+    std::vector<double> hw;
+    for (int a = 0; a < 3; ++a) hw.insert(hw.end(), m->widths[a], m->widths[a] + m->n[a]);
+#define CHK(call)                                                                          \
+    do {                                                                                   \
+        hipError_t e__ = (call);                                                           \
+        if (e__ != hipSuccess) {                                                           \
+            fail(c, SEMCOND_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e__));  \
+            return bail(SEMCOND_EDEVICE);                                                  \
+        }                                                                                  \
+    } while (0)
+    CHK(hipMalloc(&c->d_widths, nw * sizeof(double)));
+    CHK(hipMemcpy(c->d_widths, hw.data(), nw * sizeof(double), hipMemcpyHostToDevice));
+    if (m->lambda_e) {
+        CHK(hipMalloc(&c->d_lam_e, ne * sizeof(double)));
+        CHK(hipMemcpy(c->d_lam_e, m->lambda_e, ne * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (m->dcoef_e) {
+        CHK(hipMalloc(&c->d_dcoef, 4 * ne * sizeof(double)));
+        CHK(hipMemcpy(c->d_dcoef, m->dcoef_e, 4 * ne * sizeof(double), hipMemcpyHostToDevice));
+    }
+    c->geo.L = c->L;
+    c->geo.hx = c->d_widths;
+    c->geo.hy = c->d_widths + m->n[0];
+    c->geo.hz = c->d_widths + m->n[0] + m->n[1];
+    c->geo.lam = m->lambda;
+    c->geo.lam_e = c->d_lam_e;
+    c->geo.dcoef = c->d_dcoef;
+    CHK(hipMalloc(&c->d_diag, c->N_s * sizeof(double)));
+    CHK(hipMalloc(&c->d_pinv64, c->N_s * sizeof(double)));
+    CHK(hipMalloc(&c->d_pinv32, c->N_s * sizeof(float)));
+    CHK(launch_fill<double>(c->d_diag, c->N_s, 0.0, st));
+    CHK(launch_precond_diag(c->geo, c->t64.tab, c->d_diag, st));
+    CHK(launch_precond_invert<double>(c->L, c->d_diag, c->d_pinv64, st));
+    CHK(launch_precond_invert<float>(c->L, c->d_diag, c->d_pinv32, st));
+    CHK(hipStreamSynchronize(st));
+#undef CHK
+    *out = c;
+    return SEMCOND_OK;
+}
+
+int semcond_sizes(const semcond_ctx* c, int64_t* N, int64_t* N_s, int64_t* N_free, int64_t* n_e) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (N) *N = c->N;
+    if (N_s) *N_s = c->N_s;
+    if (N_free) *N_free = c->N_free;
+    if (n_e) *n_e = c->n_e;
+    return SEMCOND_OK;
+}
+
+int semcond_skeleton_coords(const semcond_ctx* c, int32_t* ijk, uint8_t* free_mask) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    for (int64_t s = 0; s < c->N_s; ++s) {
+        int I1, I2, I3;
+        bool con;
+        skeleton_node(c->L, s, &I1, &I2, &I3, &con);
+        if (ijk) {
+            ijk[3 * s] = I1;
+            ijk[3 * s + 1] = I2;
+            ijk[3 * s + 2] = I3;
+        }
+        if (free_mask) free_mask[s] = con ? 0 : 1;
+    }
+    return SEMCOND_OK;
+}
+
+int semcond_apply(semcond_ctx* c, const void* u, void* v, int k, int dtype, int basis, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!u || !v) return fail(c, SEMCOND_EINVAL, "u and v must be device pointers");
+    if (u == v) return fail(c, SEMCOND_EINVAL, "u and v must not overlap");
+    int rc = check_dtype(c, dtype);
+    if (!rc) rc = check_k(c, k);
+    if (rc) return rc;
+    if (basis != SEMCOND_PHYSICAL && basis != SEMCOND_TRANSFORMED) return fail(c, SEMCOND_EINVAL, "bad basis");
+    hipStream_t st = S(stream);
+    const size_t es = dtype == SEMCOND_F64 ? sizeof(double) : sizeof(float);
+    if (basis == SEMCOND_TRANSFORMED) {
+        if (dtype == SEMCOND_F64) return apply_transformed<double>(c, (const double*)u, (double*)v, k, nullptr, st);
+        return apply_transformed<float>(c, (const float*)u, (float*)v, k, nullptr, st);
+    }
+    rc = grow(c, c->ws_vec, 2 * es * (size_t)c->N_s * k);
+    if (rc) return rc;
+    if (dtype == SEMCOND_F64) {
+        double* t1 = (double*)c->ws_vec.ptr;
+        double* t2 = t1 + c->N_s * k;
+        HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.Sinv, (const double*)u, t1, k, st));
+        rc = apply_transformed<double>(c, t1, t2, k, nullptr, st);
+        if (rc) return rc;
+        HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.SinvT, t2, (double*)v, k, st));
+    } else {
+        float* t1 = (float*)c->ws_vec.ptr;
+        float* t2 = t1 + c->N_s * k;
+        HIPCHK(c, launch_transform<float>(c->L, c->t32.tab.Sinv, (const float*)u, t1, k, st));
+        rc = apply_transformed<float>(c, t1, t2, k, nullptr, st);
+        if (rc) return rc;
+        HIPCHK(c, launch_transform<float>(c->L, c->t32.tab.SinvT, t2, (float*)v, k, st));
+    }
+    return SEMCOND_OK;
+}
+
+int semcond_transform(semcond_ctx* c, const void* in, void* out, int k, int dtype, int direction, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!in || !out || in == out) return fail(c, SEMCOND_EINVAL, "in/out must be distinct device pointers");
+    int rc = check_dtype(c, dtype);
+    if (!rc) rc = check_k(c, k);
+    if (rc) return rc;
+    if (direction < 0 || direction > 3) return fail(c, SEMCOND_EINVAL, "bad direction");
+    hipStream_t st = S(stream);
+    if (dtype == SEMCOND_F64)
+        HIPCHK(c, launch_transform<double>(c->L, transform_matrix<double>(c, direction), (const double*)in,
+                                           (double*)out, k, st));
+    else
+        HIPCHK(c, launch_transform<float>(c->L, transform_matrix<float>(c, direction), (const float*)in,
+                                          (float*)out, k, st));
+    return SEMCOND_OK;
+}
+
+int semcond_precond_diag(semcond_ctx* c, void* diag, int dtype, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!diag) return fail(c, SEMCOND_EINVAL, "diag is NULL");
+    int rc = check_dtype(c, dtype);
+    if (rc) return rc;
+    hipStream_t st = S(stream);
+    if (dtype == SEMCOND_F64)
+        HIPCHK(c, hipMemcpyAsync(diag, c->d_diag, c->N_s * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else
+        HIPCHK(c, (launch_convert<double, float>(c->d_diag, (float*)diag, c->N_s, st)));
+    return SEMCOND_OK;
+}
+
+int semcond_condense_rhs(semcond_ctx* c, const void* f, void* fhat, int k, int dtype, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!f || !fhat) return fail(c, SEMCOND_EINVAL, "f and fhat must be device pointers");
+    int rc = check_dtype(c, dtype);
+    if (!rc) rc = check_k(c, k);
+    if (rc) return rc;
+    hipStream_t st = S(stream);
+    if (dtype == SEMCOND_F64) return condense_rhs64(c, (const double*)f, (double*)fhat, k, st);
+    rc = grow(c, c->ws_vec, sizeof(double) * (size_t)c->N_s * k);
+    if (rc) return rc;
+    double* t = (double*)c->ws_vec.ptr;
+    rc = condense_rhs64(c, (const double*)f, t, k, st);
+    if (rc) return rc;
+    HIPCHK(c, (launch_convert<double, float>(t, (float*)fhat, c->N_s * k, st)));
+    return SEMCOND_OK;
+}
+
+int semcond_skeleton_to_nodal(semcond_ctx* c, const void* skel, void* nodal, int k, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!skel || !nodal) return fail(c, SEMCOND_EINVAL, "NULL pointer");
+    int rc = check_k(c, k);
+    if (rc) return rc;
+    HIPCHK(c, launch_skel_to_nodal(c->L, (const double*)skel, (double*)nodal, c->N, k, S(stream)));
+    return SEMCOND_OK;
+}
+
+int semcond_nodal_to_skeleton(semcond_ctx* c, const void* nodal, void* skel, int k, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!skel || !nodal) return fail(c, SEMCOND_EINVAL, "NULL pointer");
+    int rc = check_k(c, k);
+    if (rc) return rc;
+    HIPCHK(c, launch_nodal_to_skel(c->L, (const double*)nodal, (double*)skel, c->N, k, S(stream)));
+    return SEMCOND_OK;
+}
+
+void semcond_solve_opts_default(semcond_solve_opts* o) {
+    if (!o) return;
+    o->tol = 1e-10;
+    o->max_iter = 20000;
+    o->precision = SEMCOND_PREC_F64;
+    o->check_every = 8;
+    o->recover_interior = 1;
+    o->x0 = nullptr;
+    o->skel_out = nullptr;
+    o->inner_tol = 1e-5;
+    o->max_outer = 30;
+}
+
+int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_solve_opts* opts,
+                  semcond_solve_info* info, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!f || !u) return fail(c, SEMCOND_EINVAL, "f and u must be device pointers");
+    int rc = check_k(c, k);
+    if (rc) return rc;
+    semcond_solve_opts o;
+    if (opts)
+        o = *opts;
+    else
+        semcond_solve_opts_default(&o);
+    if (!(o.tol > 0.0) || o.max_iter < 0) return fail(c, SEMCOND_EINVAL, "tol must be > 0 and max_iter >= 0");
+    if (o.precision != SEMCOND_PREC_F64) return fail(c, SEMCOND_EINVAL, "precision mode not available");
+    hipStream_t st = S(stream);
+    const int64_t Ns = c->N_s;
+    const size_t nv = (size_t)Ns * k;
+    rc = grow(c, c->ws_vec, 5 * nv * sizeof(double));
+    if (rc) return rc;
+    double* b = (double*)c->ws_vec.ptr;
+    double* x = b + nv;
+    double* r = x + nv;
+    double* p = r + nv;
+    double* q = p + nv;
+    CgWork w;
+    rc = cg_state(c, k, &w);
+    if (rc) return rc;
+    rc = condense_rhs64(c, (const double*)f, b, k, st);
+    if (rc) return rc;
+    if (o.x0) HIPCHK(c, hipMemcpyAsync(x, o.x0, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+    rc = run_cg<double>(c, b, x, r, p, q, k, o.tol, o.max_iter, o.check_every, o.x0 != nullptr, w, st);
+    if (rc) return rc;
+    // back to the physical basis and the nodal array (Algorithm 4, second loop)
+    HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.S, x, p, k, st));
+    HIPCHK(c, launch_skel_to_nodal(c->L, p, (double*)u, c->N, k, st));
+    if (o.recover_interior) {
+        int grid;
+        double* scratch;
+        rc = scratch_for_cubes(c, &grid, &scratch);
+        if (rc) return rc;
+        HIPCHK(c, launch_recover_interior(c->geo, c->t64.tab, (const double*)f, c->N, x, (double*)u, k, scratch,
+                                          grid, st));
+    }
+    if (o.skel_out) HIPCHK(c, hipMemcpyAsync(o.skel_out, x, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+    std::vector<double> rr(k), bb(k);
+    std::vector<int> iters(k), status(k), active(k);
+    HIPCHK(c, hipMemcpyAsync(rr.data(), w.s.rr, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(bb.data(), w.s.bb, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(iters.data(), w.s.iters, k * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(status.data(), w.s.status, k * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(active.data(), w.s.active, k * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    int worst = SEMCOND_OK;
+    for (int i = 0; i < k; ++i) {
+        int s = status[i];
+        if (s == 0 && active[i]) s = SEMCOND_ENOTCONV;
+        if (info) {
+            info[i].iters = iters[i];
+            info[i].outer = 0;
+            info[i].rel_res = bb[i] > 0 ? std::sqrt(rr[i] / bb[i]) : 0.0;
+            info[i].status = s;
+        }
+        if (s < 0) worst = s;
+        else if (s == SEMCOND_ENOTCONV && worst == SEMCOND_OK) worst = s;
+    }
+    if (worst != SEMCOND_OK) fail(c, worst, "solve did not converge for every right-hand side");
+    return worst;
+}
+
+}  // extern "C"

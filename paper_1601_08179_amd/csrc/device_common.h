@@ -1,0 +1,83 @@
+// Device-side parameter structs shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.h"
+
+namespace semcond {
+
+// 1D tables of one scalar type, on the device (see tables.h):
+//   lam, a, b: n_I; S, St (= S^T), Sinv, SinvT: n_I x n_I row-major;
+//   w: p+1 GLL weights.
+// The scalars M_00, K_00, K_0p are passed by value.
+template <typename T>
+struct DevTab {
+    const T* lam;
+    const T* a;
+    const T* b;
+    const T* S;
+    const T* St;
+    const T* Sinv;
+    const T* SinvT;
+    const T* w;
+    T m0, K00, K0p;
+};
+
+// Mesh metric data.  d_e = (h1 h2 h3/8)(lambda, 4/h1^2, 4/h2^2, 4/h3^2)
+// (Sec. 3, eq. metriccoeffelement) from per-axis widths and lambda, unless a
+// per-element table dcoef[n_e][4] is given.
+struct Geo {
+    Layout L;
+    const double* hx;
+    const double* hy;
+    const double* hz;
+    double lam;
+    const double* lam_e;  // nullable, n_e
+    const double* dcoef;  // nullable, n_e x 4
+};
+
+__device__ inline void elem_index(const Layout& L, int64_t e, int* e1, int* e2, int* e3) {
+    *e1 = (int)(e % L.n1);
+    int64_t r = e / L.n1;
+    *e2 = (int)(r % L.n2);
+    *e3 = (int)(r / L.n2);
+}
+
+__device__ inline void elem_metric(const Geo& g, int64_t e, int e1, int e2, int e3, double d[4]) {
+    if (g.dcoef) {
+        d[0] = g.dcoef[4 * e + 0];
+        d[1] = g.dcoef[4 * e + 1];
+        d[2] = g.dcoef[4 * e + 2];
+        d[3] = g.dcoef[4 * e + 3];
+        return;
+    }
+    const double h1 = g.hx[e1], h2 = g.hy[e2], h3 = g.hz[e3];
+    const double J = h1 * h2 * h3 / 8.0;
+    const double lam = g.lam_e ? g.lam_e[e] : g.lam;
+    d[0] = J * lam;
+    d[1] = J * 4.0 / (h1 * h1);
+    d[2] = J * 4.0 / (h2 * h2);
+    d[3] = J * 4.0 / (h3 * h3);
+}
+
+// J_e = h1 h2 h3 / 8 (factor of the GLL-lumped element mass matrix).
+__device__ inline double elem_jacobian(const Geo& g, int e1, int e2, int e3) {
+    return g.hx[e1] * g.hy[e2] * g.hz[e3] / 8.0;
+}
+
+template <typename T>
+__device__ inline void atomic_add(T* p, T v) {
+    unsafeAtomicAdd(p, v);
+}
+
+// Wave64 sum.
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace semcond

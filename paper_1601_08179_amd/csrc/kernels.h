@@ -1,0 +1,100 @@
+// Kernel launchers (host-callable) and their argument structs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace semcond {
+
+template <typename T>
+struct ApplyArgs {
+    Geo g;
+    DevTab<T> tab;
+    const T* u;       // [N_s][k] transformed basis
+    T* v;             // [N_s][k], accumulated into (zero it first)
+    int k;
+    double* energy;   // nullable, [n_elem][k]: element energies u_e . (H~^ u)_e
+    int64_t e_begin;  // first element of this launch
+};
+
+template <typename T>
+hipError_t launch_apply_tpt(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t st);
+
+// Basis change of skeleton arrays: per face out = A in A^T over the face's two
+// interior axes, per edge out = A in, vertices copied.  A is n_I x n_I row-major.
+template <typename T>
+hipError_t launch_transform(const Layout& L, const T* A, const T* in, T* out, int k, hipStream_t st);
+
+// diag(R H~^_L R^T) accumulated into diag (FP64, zeroed first).
+hipError_t launch_precond_diag(const Geo& g, const DevTab<double>& tab, double* diag, hipStream_t st);
+// pinv[s] = 1/diag[s] on free slots, 0 on constrained ones (type T).
+template <typename T>
+hipError_t launch_precond_invert(const Layout& L, const double* diag, T* pinv, hipStream_t st);
+
+// Condensed transformed RHS, accumulated into fhat (zeroed first).  The element
+// cube of (p+1)^3 values lives in LDS when it fits, else in `scratch`
+// (grid x (p+1)^3 doubles, grid = number of workgroups used).
+hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
+                               double* fhat, int k, double* scratch, int grid, hipStream_t st);
+int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch);
+
+// Interior recovery (Algorithm 4, second loop): u_I = (S(x)S(x)S) D^-1 (F~_I - H~_IB u~_B),
+// written into the interior nodes of the nodal array u [k][N].
+hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
+                                   const double* xskel, double* u, int k, double* scratch, int grid,
+                                   hipStream_t st);
+
+// Skeleton <-> nodal copies (FP64).
+hipError_t launch_skel_to_nodal(const Layout& L, const double* skel, double* nodal, int64_t N, int k,
+                                hipStream_t st);
+hipError_t launch_nodal_to_skel(const Layout& L, const double* nodal, double* skel, int64_t N, int k,
+                                hipStream_t st);
+
+template <typename T>
+hipError_t launch_fill(T* x, int64_t n, T val, hipStream_t st);
+template <typename Tin, typename Tout>
+hipError_t launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Conjugate gradients (BT solver, Sec. 8) on [N_s][k] multivectors.
+// Device state holds per-RHS scalars; reductions are two-stage and in a fixed
+// order, so results do not depend on scheduling.
+// ---------------------------------------------------------------------------
+struct CgState {
+    double* rho;     // r.z
+    double* pq;      // p.q
+    double* alpha;
+    double* beta;
+    double* rr;      // r.r
+    double* bb;      // b.b
+    double* tol2;    // tol^2 (same for all RHS)
+    int* active;     // 1 while iterating
+    int* iters;
+    int* status;
+};
+
+constexpr int kVecBlocks = 512;  // fixed grid of the vector kernels (partials per RHS)
+
+int vec_block_threads(int k);
+
+// r = b - q0 (q0 nullable: then r = b), x = x0 or 0, p = pinv r,
+// partials[0]: r.z, [1]: r.r, [2]: b.b  ([3][kVecBlocks][k] doubles).
+template <typename T>
+hipError_t launch_cg_init(const T* b, const T* q0, const T* pinv, T* r, T* p, int64_t Ns, int k,
+                          double* partials, hipStream_t st);
+// Reduce [nparts][k] partials of `nq` quantities; mode selects the CG step logic.
+enum ReduceMode { RED_INIT = 0, RED_PQ = 1, RED_RZ = 2 };
+hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int k, CgState s, int mode,
+                            hipStream_t st);
+// x += alpha p; r -= alpha q; partials[0] r.z (z = pinv r), [1] r.r.
+template <typename T>
+hipError_t launch_cg_update(T* x, T* r, const T* p, const T* q, const T* pinv, int64_t Ns, int k,
+                            CgState s, double* partials, hipStream_t st);
+// p = pinv r + beta p.
+template <typename T>
+hipError_t launch_cg_direction(T* p, const T* r, const T* pinv, int64_t Ns, int k, CgState s,
+                               hipStream_t st);
+
+}  // namespace semcond

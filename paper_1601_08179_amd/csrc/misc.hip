@@ -1,0 +1,689 @@
+// Basis changes, preconditioner diagonal, right-hand-side condensation,
+// interior recovery, nodal/skeleton copies and the conjugate-gradient vector
+// kernels of the BT solver.
+
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "kernels.h"
+#include "tables.h"
+
+namespace semcond {
+
+// ---------------------------------------------------------------------------
+// Basis change of skeleton arrays (Sec. 6: T = S1(x)S1(x)S1, S1 = diag(1,S,1),
+// acts on a face through its two interior axes and on an edge through one).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_transform_faces(Layout L, const T* __restrict__ A,
+                                                          const T* __restrict__ in, T* __restrict__ out,
+                                                          int k, int fpb, int64_t nfaces) {
+    extern __shared__ unsigned char smem_raw[];
+    T* X = reinterpret_cast<T*>(smem_raw);
+    const int NI = L.NI, NI2 = NI * NI;
+    T* Y = X + fpb * NI2;
+    const int t = threadIdx.x;
+    const int lf = t / NI2, loc = t - lf * NI2;
+    const int64_t face = (int64_t)blockIdx.x * fpb + lf;
+    const bool valid = lf < fpb && face < nfaces;
+    const int s1 = loc / NI, s2 = loc - (loc / NI) * NI;
+    const int64_t node = face * NI2 + loc;  // faces are contiguous from oFx = 0
+    for (int r = 0; r < k; ++r) {
+        if (valid) X[t] = in[node * k + r];
+        __syncthreads();
+        if (valid) {  // along the fast axis: Y(s1, c) = sum_c' A[c][c'] X(s1, c')
+            T acc = 0;
+            for (int m = 0; m < NI; ++m) acc += A[s2 * NI + m] * X[lf * NI2 + s1 * NI + m];
+            Y[t] = acc;
+        }
+        __syncthreads();
+        if (valid) {  // along the slow axis
+            T acc = 0;
+            for (int m = 0; m < NI; ++m) acc += A[s1 * NI + m] * Y[lf * NI2 + m * NI + s2];
+            out[node * k + r] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void k_transform_edges(Layout L, const T* __restrict__ A, const T* __restrict__ in,
+                                  T* __restrict__ out, int k) {
+    const int64_t nval = (L.Ns - L.oEx) * k;
+    const int NI = L.NI;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nval;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = L.oEx + idx / k;
+        const int r = (int)(idx % k);
+        if (s >= L.oV) {
+            out[s * k + r] = in[s * k + r];
+        } else {
+            const int64_t t = s - L.oEx;
+            const int64_t base = L.oEx + (t / NI) * NI;
+            const int m = (int)(t % NI);
+            T acc = 0;
+            for (int m2 = 0; m2 < NI; ++m2) acc += A[m * NI + m2] * in[(base + m2) * k + r];
+            out[s * k + r] = acc;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_transform(const Layout& L, const T* A, const T* in, T* out, int k, hipStream_t st) {
+    const int NI2 = L.NI * L.NI;
+    const int64_t nfaces = L.oEx / NI2;
+    int fpb = 1024 / NI2;
+    if (fpb < 1) fpb = 1;
+    if (fpb > 64) fpb = 64;
+    int threads = ((fpb * NI2 + 63) / 64) * 64;
+    int64_t blocks = (nfaces + fpb - 1) / fpb;
+    size_t shm = 2 * (size_t)fpb * NI2 * sizeof(T);
+    if (blocks > 0)
+        hipLaunchKernelGGL(k_transform_faces<T>, dim3((unsigned)blocks), dim3(threads), shm, st, L, A, in,
+                           out, k, fpb, nfaces);
+    int64_t nval = (L.Ns - L.oEx) * k;
+    int eb = (int)((nval + 255) / 256);
+    if (eb > 65536) eb = 65536;
+    if (eb > 0) hipLaunchKernelGGL(k_transform_edges<T>, dim3(eb), dim3(256), 0, st, L, A, in, out, k);
+    return hipGetLastError();
+}
+
+template hipError_t launch_transform<double>(const Layout&, const double*, const double*, double*, int,
+                                             hipStream_t);
+template hipError_t launch_transform<float>(const Layout&, const float*, const float*, float*, int,
+                                            hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Preconditioner: diagonal of the transformed condensed operator (Sec. 8: the
+// block preconditioner is diagonal in the transformed system).  Per element:
+//   face w (k,j): d0 M00 + d1 K00 + d2 M00 L_j + d3 M00 L_k - d1^2 sum_i a_i^2 / D_kji
+//   (e: b_i; s/n and b/t analogous along j and k)
+//   edge along x1 (i): d0 M00^2 + d1 M00^2 L_i + (d2+d3) M00 K00 (others analogous)
+//   vertex: d0 M00^3 + (d1+d2+d3) M00^2 K00
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_precond_diag(Geo g, DevTab<double> tab, double* __restrict__ diag) {
+    const Layout& L = g.L;
+    const int NI = L.NI, NI2 = NI * NI;
+    const int64_t e = blockIdx.x;
+    int e1, e2, e3;
+    elem_index(L, e, &e1, &e2, &e3);
+    double d[4];
+    elem_metric(g, e, e1, e2, e3, d);
+    const double m0 = tab.m0, K00 = tab.K00;
+    const int nslot = 6 * NI2 + 12 * NI + 8;
+    for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
+        int ent, loc;
+        double val;
+        if (s < 6 * NI2) {
+            const int f = s / NI2;
+            loc = s - f * NI2;
+            ent = f;
+            const int s1 = loc / NI, s2 = loc % NI;
+            const double* c = (f & 1) ? tab.b : tab.a;
+            double cond = 0.0;
+            if (f < 2) {  // (k, j), line along i
+                for (int m = 0; m < NI; ++m)
+                    cond += c[m] * c[m] / (d[0] + d[1] * tab.lam[m] + d[2] * tab.lam[s2] + d[3] * tab.lam[s1]);
+                val = d[0] * m0 + d[1] * K00 + d[2] * m0 * tab.lam[s2] + d[3] * m0 * tab.lam[s1] - d[1] * d[1] * cond;
+            } else if (f < 4) {  // (k, i), line along j
+                for (int m = 0; m < NI; ++m)
+                    cond += c[m] * c[m] / (d[0] + d[1] * tab.lam[s2] + d[2] * tab.lam[m] + d[3] * tab.lam[s1]);
+                val = d[0] * m0 + d[2] * K00 + d[1] * m0 * tab.lam[s2] + d[3] * m0 * tab.lam[s1] - d[2] * d[2] * cond;
+            } else {  // (j, i), line along k
+                for (int m = 0; m < NI; ++m)
+                    cond += c[m] * c[m] / (d[0] + d[1] * tab.lam[s2] + d[2] * tab.lam[s1] + d[3] * tab.lam[m]);
+                val = d[0] * m0 + d[3] * K00 + d[1] * m0 * tab.lam[s2] + d[2] * m0 * tab.lam[s1] - d[3] * d[3] * cond;
+            }
+        } else if (s < 6 * NI2 + 12 * NI) {
+            const int q = (s - 6 * NI2) / NI;
+            loc = s - 6 * NI2 - q * NI;
+            ent = 6 + q;
+            const double l = tab.lam[loc];
+            if (q < 4)
+                val = d[0] * m0 * m0 + d[1] * m0 * m0 * l + (d[2] + d[3]) * m0 * K00;
+            else if (q < 8)
+                val = d[0] * m0 * m0 + d[2] * m0 * m0 * l + (d[1] + d[3]) * m0 * K00;
+            else
+                val = d[0] * m0 * m0 + d[3] * m0 * m0 * l + (d[1] + d[2]) * m0 * K00;
+        } else {
+            ent = 18 + (s - 6 * NI2 - 12 * NI);
+            loc = 0;
+            val = d[0] * m0 * m0 * m0 + (d[1] + d[2] + d[3]) * m0 * m0 * K00;
+        }
+        int64_t base;
+        bool con;
+        element_entity(L, e1, e2, e3, ent, &base, &con);
+        if (!con) atomic_add(&diag[base + loc], val);
+    }
+}
+
+hipError_t launch_precond_diag(const Geo& g, const DevTab<double>& tab, double* diag, hipStream_t st) {
+    const int64_t ne = (int64_t)g.L.n1 * g.L.n2 * g.L.n3;
+    hipLaunchKernelGGL(k_precond_diag, dim3((unsigned)ne), dim3(256), 0, st, g, tab, diag);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_precond_invert(Layout L, const double* __restrict__ diag, T* __restrict__ pinv) {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < L.Ns;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        int I1, I2, I3;
+        bool con;
+        skeleton_node(L, s, &I1, &I2, &I3, &con);
+        pinv[s] = con ? (T)0 : (T)(1.0 / diag[s]);
+    }
+}
+
+template <typename T>
+hipError_t launch_precond_invert(const Layout& L, const double* diag, T* pinv, hipStream_t st) {
+    int blocks = (int)((L.Ns + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_precond_invert<T>, dim3(blocks), dim3(256), 0, st, L, diag, pinv);
+    return hipGetLastError();
+}
+template hipError_t launch_precond_invert<double>(const Layout&, const double*, double*, hipStream_t);
+template hipError_t launch_precond_invert<float>(const Layout&, const double*, float*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Element cube helpers: 1D transforms along the lines of a (p+1)^3 cube,
+// acting on the interior indices 1..n_I of each line.
+// ---------------------------------------------------------------------------
+
+// axis 0: lines along i (fixed kk, jj); 1: along j; 2: along k.
+// interior_only: restrict to lines whose two fixed indices are interior.
+__device__ void cube_lines(double* cube, int p, int axis, const double* __restrict__ A, bool interior_only) {
+    const int n = p + 1, NI = p - 1;
+    const int nl = interior_only ? NI * NI : n * n;
+    const int stride = axis == 0 ? 1 : (axis == 1 ? n : n * n);
+    for (int l = threadIdx.x; l < nl; l += blockDim.x) {
+        int u = l / (interior_only ? NI : n), w = l % (interior_only ? NI : n);
+        if (interior_only) { u += 1; w += 1; }
+        // (u, w) are the two fixed indices in (slow, fast) order of the remaining axes
+        int base;
+        if (axis == 0) base = (u * n + w) * n;       // (kk, jj)
+        else if (axis == 1) base = u * n * n + w;     // (kk, ii)
+        else base = u * n + w;                        // (jj, ii)
+        double x[kMaxNI];
+#pragma unroll
+        for (int m = 0; m < kMaxNI; ++m)
+            if (m < NI) x[m] = cube[base + (1 + m) * stride];
+        for (int m = 0; m < NI; ++m) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m2 = 0; m2 < kMaxNI; ++m2)
+                if (m2 < NI) acc += A[m * NI + m2] * x[m2];
+            cube[base + (1 + m) * stride] = acc;
+        }
+    }
+}
+
+// cube(kk,jj,ii) = J w_ii w_jj w_kk f(node) then F~ = (S1^T (x) S1^T (x) S1^T) F.
+__device__ void cube_transformed_rhs(double* cube, const Geo& g, const DevTab<double>& tab,
+                                     const double* __restrict__ St, const double* __restrict__ f, int64_t N,
+                                     int r, int e1, int e2, int e3) {
+    const Layout& L = g.L;
+    const int p = L.p, n = p + 1;
+    const int64_t N1 = (int64_t)L.n1 * p + 1, N2 = (int64_t)L.n2 * p + 1;
+    const double J = elem_jacobian(g, e1, e2, e3);
+    for (int idx = threadIdx.x; idx < n * n * n; idx += blockDim.x) {
+        const int ii = idx % n, jj = (idx / n) % n, kk = idx / (n * n);
+        const int64_t node = ((int64_t)e1 * p + ii) + N1 * (((int64_t)e2 * p + jj) + N2 * ((int64_t)e3 * p + kk));
+        cube[idx] = J * tab.w[ii] * tab.w[jj] * tab.w[kk] * f[(int64_t)r * N + node];
+    }
+    __syncthreads();
+    cube_lines(cube, p, 0, St, false);
+    __syncthreads();
+    cube_lines(cube, p, 1, St, false);
+    __syncthreads();
+    cube_lines(cube, p, 2, St, false);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Condensed transformed right-hand side (Algorithm 4, first loop):
+//   F^~_f = F~_f - H~_FI D^-1 F~_I on the six faces, F~ on edges and vertices.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_condense_rhs(Geo g, DevTab<double> tab, const double* __restrict__ f,
+                                                      int64_t N,
+                                                      double* __restrict__ fhat, int k, double* scratch) {
+    extern __shared__ double cube_lds[];
+    const Layout& L = g.L;
+    const int p = L.p, n = p + 1, NI = L.NI, NI2 = NI * NI;
+    const int64_t ne = (int64_t)L.n1 * L.n2 * L.n3;
+    double* cube = scratch ? scratch + (int64_t)blockIdx.x * n * n * n : cube_lds;
+    const int nslot = 6 * NI2 + 12 * NI + 8;
+#define C(kk, jj, ii) cube[((kk) * n + (jj)) * n + (ii)]
+    for (int64_t e = blockIdx.x; e < ne; e += gridDim.x) {
+        int e1, e2, e3;
+        elem_index(L, e, &e1, &e2, &e3);
+        double d[4];
+        elem_metric(g, e, e1, e2, e3, d);
+        for (int r = 0; r < k; ++r) {
+            cube_transformed_rhs(cube, g, tab, tab.St, f, N, r, e1, e2, e3);
+            for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
+                int ent, loc;
+                double val;
+                if (s < 6 * NI2) {
+                    const int fc = s / NI2;
+                    loc = s - fc * NI2;
+                    ent = fc;
+                    const int s1 = loc / NI, s2 = loc % NI;
+                    const double* c = (fc & 1) ? tab.b : tab.a;
+                    const int side = (fc & 1) ? p : 0;
+                    double acc = 0.0;
+                    if (fc < 2) {  // (k, j), sum over i
+                        for (int m = 0; m < NI; ++m)
+                            acc += c[m] * C(1 + s1, 1 + s2, 1 + m) /
+                                   (d[0] + d[1] * tab.lam[m] + d[2] * tab.lam[s2] + d[3] * tab.lam[s1]);
+                        val = C(1 + s1, 1 + s2, side) - d[1] * acc;
+                    } else if (fc < 4) {  // (k, i), sum over j
+                        for (int m = 0; m < NI; ++m)
+                            acc += c[m] * C(1 + s1, 1 + m, 1 + s2) /
+                                   (d[0] + d[1] * tab.lam[s2] + d[2] * tab.lam[m] + d[3] * tab.lam[s1]);
+                        val = C(1 + s1, side, 1 + s2) - d[2] * acc;
+                    } else {  // (j, i), sum over k
+                        for (int m = 0; m < NI; ++m)
+                            acc += c[m] * C(1 + m, 1 + s1, 1 + s2) /
+                                   (d[0] + d[1] * tab.lam[s2] + d[2] * tab.lam[s1] + d[3] * tab.lam[m]);
+                        val = C(side, 1 + s1, 1 + s2) - d[3] * acc;
+                    }
+                } else if (s < 6 * NI2 + 12 * NI) {
+                    const int q = (s - 6 * NI2) / NI;
+                    loc = s - 6 * NI2 - q * NI;
+                    ent = 6 + q;
+                    if (q < 4) {
+                        const int jb = q & 1, kb = q >> 1;
+                        val = C(kb * p, jb * p, 1 + loc);
+                    } else if (q < 8) {
+                        const int ib = (q - 4) & 1, kb = (q - 4) >> 1;
+                        val = C(kb * p, 1 + loc, ib * p);
+                    } else {
+                        const int ib = (q - 8) & 1, jb = (q - 8) >> 1;
+                        val = C(1 + loc, jb * p, ib * p);
+                    }
+                } else {
+                    const int q = s - 6 * NI2 - 12 * NI;
+                    ent = 18 + q;
+                    loc = 0;
+                    val = C((q >> 2) * p, ((q >> 1) & 1) * p, (q & 1) * p);
+                }
+                int64_t base;
+                bool con;
+                element_entity(L, e1, e2, e3, ent, &base, &con);
+                if (!con) atomic_add(&fhat[(base + loc) * k + r], val);
+            }
+            __syncthreads();
+        }
+    }
+#undef C
+}
+
+int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch) {
+    const size_t bytes = (size_t)(p + 1) * (p + 1) * (p + 1) * sizeof(double);
+    *needs_scratch = bytes > 64 * 1024;
+    int64_t grid = n_e;
+    if (*needs_scratch && grid > 2048) grid = 2048;
+    if (grid > (1 << 30)) grid = 1 << 30;
+    return (int)grid;
+}
+
+hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
+                               double* fhat, int k, double* scratch, int grid, hipStream_t st) {
+    const int n = g.L.p + 1;
+    const size_t shm = scratch ? 0 : (size_t)n * n * n * sizeof(double);
+    hipLaunchKernelGGL(k_condense_rhs, dim3(grid), dim3(256), shm, st, g, tab, f, N, fhat, k, scratch);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Interior recovery and back-transform (Algorithm 4, second loop):
+//   u~_I = D^-1 (F~_I - H~_IB u~_B),  u_I = (S(x)S(x)S) u~_I,
+// with H~_IB u~_B = d1 (a_i U_w + b_i U_e) + d2 (a_j U_s + b_j U_n) + d3 (a_k U_b + b_k U_t)
+// (Table 2).  Writes the interior nodes of the element into u [k][N].
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_recover_interior(Geo g, DevTab<double> tab, const double* __restrict__ f,
+                                                          int64_t N, const double* __restrict__ xs,
+                                                          double* __restrict__ u, int k, double* scratch) {
+    extern __shared__ double cube_lds[];
+    __shared__ int64_t fb[6];
+    __shared__ int fc[6];
+    const Layout& L = g.L;
+    const int p = L.p, n = p + 1, NI = L.NI, NI2 = NI * NI;
+    const int64_t ne = (int64_t)L.n1 * L.n2 * L.n3;
+    const int64_t N1 = (int64_t)L.n1 * p + 1, N2 = (int64_t)L.n2 * p + 1;
+    double* cube = scratch ? scratch + (int64_t)blockIdx.x * n * n * n : cube_lds;
+#define C(kk, jj, ii) cube[((kk) * n + (jj)) * n + (ii)]
+    for (int64_t e = blockIdx.x; e < ne; e += gridDim.x) {
+        int e1, e2, e3;
+        elem_index(L, e, &e1, &e2, &e3);
+        double d[4];
+        elem_metric(g, e, e1, e2, e3, d);
+        if (threadIdx.x < 6) {
+            bool c;
+            element_entity(L, e1, e2, e3, threadIdx.x, &fb[threadIdx.x], &c);
+            fc[threadIdx.x] = c ? 1 : 0;
+        }
+        for (int r = 0; r < k; ++r) {
+            cube_transformed_rhs(cube, g, tab, tab.St, f, N, r, e1, e2, e3);
+#define UF(face, s1, s2) (fc[face] ? 0.0 : xs[(fb[face] + (int64_t)(s1) * NI + (s2)) * k + r])
+            for (int idx = threadIdx.x; idx < NI2 * NI; idx += blockDim.x) {
+                const int i = idx % NI, j = (idx / NI) % NI, kk = idx / NI2;
+                const double uc = d[1] * (tab.a[i] * UF(0, kk, j) + tab.b[i] * UF(1, kk, j)) +
+                                  d[2] * (tab.a[j] * UF(2, kk, i) + tab.b[j] * UF(3, kk, i)) +
+                                  d[3] * (tab.a[kk] * UF(4, j, i) + tab.b[kk] * UF(5, j, i));
+                const double D = d[0] + d[1] * tab.lam[i] + d[2] * tab.lam[j] + d[3] * tab.lam[kk];
+                C(1 + kk, 1 + j, 1 + i) = (C(1 + kk, 1 + j, 1 + i) - uc) / D;
+            }
+#undef UF
+            __syncthreads();
+            cube_lines(cube, p, 0, tab.S, true);
+            __syncthreads();
+            cube_lines(cube, p, 1, tab.S, true);
+            __syncthreads();
+            cube_lines(cube, p, 2, tab.S, true);
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < NI2 * NI; idx += blockDim.x) {
+                const int i = idx % NI, j = (idx / NI) % NI, kk = idx / NI2;
+                const int64_t node = ((int64_t)e1 * p + 1 + i) +
+                                     N1 * (((int64_t)e2 * p + 1 + j) + N2 * ((int64_t)e3 * p + 1 + kk));
+                u[(int64_t)r * N + node] = C(1 + kk, 1 + j, 1 + i);
+            }
+            __syncthreads();
+        }
+    }
+#undef C
+}
+
+hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
+                                   const double* xskel, double* u, int k, double* scratch, int grid,
+                                   hipStream_t st) {
+    const int n = g.L.p + 1;
+    const size_t shm = scratch ? 0 : (size_t)n * n * n * sizeof(double);
+    hipLaunchKernelGGL(k_recover_interior, dim3(grid), dim3(256), shm, st, g, tab, f, N, xskel, u, k, scratch);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Skeleton <-> nodal copies.
+// ---------------------------------------------------------------------------
+
+__device__ inline int64_t skel_nodal_index(const Layout& L, int64_t s, bool* con) {
+    int I1, I2, I3;
+    skeleton_node(L, s, &I1, &I2, &I3, con);
+    const int64_t N1 = (int64_t)L.n1 * L.p + 1, N2 = (int64_t)L.n2 * L.p + 1;
+    return I1 + N1 * (I2 + N2 * (int64_t)I3);
+}
+
+__global__ void k_skel_to_nodal(Layout L, const double* __restrict__ skel, double* __restrict__ nodal, int64_t N,
+                                int k) {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < L.Ns; s += (int64_t)gridDim.x * blockDim.x) {
+        bool con;
+        const int64_t g = skel_nodal_index(L, s, &con);
+        for (int r = 0; r < k; ++r) nodal[(int64_t)r * N + g] = con ? 0.0 : skel[s * k + r];
+    }
+}
+
+__global__ void k_nodal_to_skel(Layout L, const double* __restrict__ nodal, double* __restrict__ skel, int64_t N,
+                                int k) {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < L.Ns; s += (int64_t)gridDim.x * blockDim.x) {
+        bool con;
+        const int64_t g = skel_nodal_index(L, s, &con);
+        for (int r = 0; r < k; ++r) skel[s * k + r] = nodal[(int64_t)r * N + g];
+    }
+}
+
+static int grid_for(int64_t n, int threads) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+hipError_t launch_skel_to_nodal(const Layout& L, const double* skel, double* nodal, int64_t N, int k,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_skel_to_nodal, dim3(grid_for(L.Ns, 256)), dim3(256), 0, st, L, skel, nodal, N, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_nodal_to_skel(const Layout& L, const double* nodal, double* skel, int64_t N, int k,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_nodal_to_skel, dim3(grid_for(L.Ns, 256)), dim3(256), 0, st, L, nodal, skel, N, k);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fill and convert.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, int64_t n, T val) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = val;
+}
+
+template <typename T>
+hipError_t launch_fill(T* x, int64_t n, T val, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, 256)), dim3(256), 0, st, x, n, val);
+    return hipGetLastError();
+}
+template hipError_t launch_fill<double>(double*, int64_t, double, hipStream_t);
+template hipError_t launch_fill<float>(float*, int64_t, float, hipStream_t);
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (Tout)in[i];
+}
+
+template <typename Tin, typename Tout>
+hipError_t launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(grid_for(n, 256)), dim3(256), 0, st, in, out, n);
+    return hipGetLastError();
+}
+template hipError_t launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template hipError_t launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
+template hipError_t launch_convert<double, double>(const double*, double*, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Conjugate-gradient vector kernels.  Block size B = k * floor(256/k): every
+// thread keeps one right-hand side r = t mod k for the whole grid-stride loop,
+// so per-RHS block sums are formed in a fixed order.
+// ---------------------------------------------------------------------------
+
+int vec_block_threads(int k) { return k * (256 / k); }
+
+template <int NQ>
+__device__ inline void block_partials(double (&acc)[NQ], int k, double* __restrict__ partials) {
+    __shared__ double sh[NQ][256];
+    const int t = threadIdx.x, B = blockDim.x;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sh[q][t] = acc[q];
+    __syncthreads();
+    if (t < k) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double s = 0.0;
+            for (int m = t; m < B; m += k) s += sh[q][m];
+            partials[((int64_t)q * gridDim.x + blockIdx.x) * k + t] = s;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_init(const T* __restrict__ b, const T* __restrict__ q0,
+                                                 const T* __restrict__ pinv, T* __restrict__ r, T* __restrict__ p,
+                                                 int64_t Ns, int k, double* __restrict__ partials) {
+    const int64_t n = Ns * k;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+        const T bv = b[idx];
+        const T rv = q0 ? (T)(bv - q0[idx]) : bv;
+        const T z = pinv[idx / k] * rv;
+        r[idx] = rv;
+        p[idx] = z;
+        acc[0] += (double)rv * (double)z;
+        acc[1] += (double)rv * (double)rv;
+        acc[2] += (double)bv * (double)bv;
+    }
+    block_partials<3>(acc, k, partials);
+}
+
+template <typename T>
+hipError_t launch_cg_init(const T* b, const T* q0, const T* pinv, T* r, T* p, int64_t Ns, int k, double* partials,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(kVecBlocks), dim3(vec_block_threads(k)), 0, st, b, q0, pinv, r, p, Ns, k,
+                       partials);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_init<double>(const double*, const double*, const double*, double*, double*, int64_t,
+                                           int, double*, hipStream_t);
+template hipError_t launch_cg_init<float>(const float*, const float*, const float*, float*, float*, int64_t, int,
+                                          double*, hipStream_t);
+
+// One block: totals of nq quantities per RHS, then the CG scalar step.
+__global__ __launch_bounds__(256) void k_cg_reduce(const double* __restrict__ partials, int64_t nparts, int nq,
+                                                   int k, CgState s, int mode) {
+    __shared__ double sh[256];
+    __shared__ double tot[3 * 256];
+    const int t = threadIdx.x;
+    for (int q = 0; q < nq; ++q) {
+        for (int r = 0; r < k; ++r) {
+            double acc = 0.0;
+            for (int64_t m = t; m < nparts; m += 256) acc += partials[((int64_t)q * nparts + m) * k + r];
+            sh[t] = acc;
+            __syncthreads();
+            for (int w = 128; w > 0; w >>= 1) {
+                if (t < w) sh[t] += sh[t + w];
+                __syncthreads();
+            }
+            if (t == 0) tot[q * 256 + r] = sh[0];
+            __syncthreads();
+        }
+    }
+    for (int r = t; r < k; r += 256) {
+        if (mode == RED_INIT) {
+            const double rz = tot[r], rr = tot[256 + r], bb = tot[512 + r];
+            s.rho[r] = rz;
+            s.rr[r] = rr;
+            s.bb[r] = bb;
+            s.iters[r] = 0;
+            s.status[r] = 0;
+            s.alpha[r] = 0.0;
+            s.beta[r] = 0.0;
+            if (!isfinite(rr) || !isfinite(rz)) {
+                s.status[r] = -5;
+                s.active[r] = 0;
+            } else {
+                s.active[r] = (rr > s.tol2[0] * bb) ? 1 : 0;
+            }
+        } else if (mode == RED_PQ) {
+            const double pq = tot[r];
+            s.pq[r] = pq;
+            if (s.active[r]) {
+                if (!isfinite(pq)) {
+                    s.status[r] = -5;
+                    s.active[r] = 0;
+                    s.alpha[r] = 0.0;
+                } else if (!(pq > 0.0)) {
+                    s.status[r] = -4;
+                    s.active[r] = 0;
+                    s.alpha[r] = 0.0;
+                } else {
+                    s.alpha[r] = s.rho[r] / pq;
+                }
+            } else {
+                s.alpha[r] = 0.0;
+            }
+        } else {  // RED_RZ
+            const double rz = tot[r], rr = tot[256 + r];
+            if (s.active[r]) {
+                s.iters[r] += 1;
+                s.rr[r] = rr;
+                if (!isfinite(rr) || !isfinite(rz)) {
+                    s.status[r] = -5;
+                    s.active[r] = 0;
+                    s.beta[r] = 0.0;
+                } else if (rr <= s.tol2[0] * s.bb[r]) {
+                    s.active[r] = 0;
+                    s.beta[r] = 0.0;
+                } else {
+                    s.beta[r] = rz / s.rho[r];
+                    s.rho[r] = rz;
+                }
+            } else {
+                s.beta[r] = 0.0;
+            }
+        }
+    }
+}
+
+hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int k, CgState s, int mode,
+                            hipStream_t st) {
+    if (k > 256 || nq > 3) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(256), 0, st, partials, nparts, nq, k, s, mode);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                                                   const T* __restrict__ q, const T* __restrict__ pinv, int64_t Ns,
+                                                   int k, CgState s, double* __restrict__ partials) {
+    const int64_t n = Ns * k;
+    const int rhs = threadIdx.x % k;
+    const T alpha = (T)s.alpha[rhs];
+    const bool act = s.active[rhs] != 0;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+        T rv = r[idx];
+        if (act) {
+            x[idx] += alpha * p[idx];
+            rv -= alpha * q[idx];
+            r[idx] = rv;
+        }
+        const T z = pinv[idx / k] * rv;
+        acc[0] += (double)rv * (double)z;
+        acc[1] += (double)rv * (double)rv;
+    }
+    block_partials<2>(acc, k, partials);
+}
+
+template <typename T>
+hipError_t launch_cg_update(T* x, T* r, const T* p, const T* q, const T* pinv, int64_t Ns, int k, CgState s,
+                            double* partials, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(kVecBlocks), dim3(vec_block_threads(k)), 0, st, x, r, p, q, pinv, Ns, k,
+                       s, partials);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_update<double>(double*, double*, const double*, const double*, const double*, int64_t,
+                                             int, CgState, double*, hipStream_t);
+template hipError_t launch_cg_update<float>(float*, float*, const float*, const float*, const float*, int64_t, int,
+                                            CgState, double*, hipStream_t);
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_direction(T* __restrict__ p, const T* __restrict__ r,
+                                                      const T* __restrict__ pinv, int64_t Ns, int k, CgState s) {
+    const int64_t n = Ns * k;
+    const int rhs = threadIdx.x % k;
+    const T beta = (T)s.beta[rhs];
+    if (!s.active[rhs]) return;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x)
+        p[idx] = pinv[idx / k] * r[idx] + beta * p[idx];
+}
+
+template <typename T>
+hipError_t launch_cg_direction(T* p, const T* r, const T* pinv, int64_t Ns, int k, CgState s, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_direction<T>, dim3(kVecBlocks), dim3(vec_block_threads(k)), 0, st, p, r, pinv, Ns, k, s);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_direction<double>(double*, const double*, const double*, int64_t, int, CgState,
+                                                hipStream_t);
+template hipError_t launch_cg_direction<float>(float*, const float*, const float*, int64_t, int, CgState,
+                                               hipStream_t);
+
+}  // namespace semcond
