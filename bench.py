@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Benchmark of the condensed-Helmholtz BT solve on one MI355X.
+
+Workload (default): 16^3 uniform elements on the unit cube, GLL degree p = 8,
+lambda = 1e-3, homogeneous Dirichlet, one N(0,1) nodal right-hand side drawn
+from the seeded generator; FP64 throughout.  N = 129^3 = 2,146,689 nodes.
+
+One step = one full solve: condensed transformed right-hand side, BT conjugate
+gradients to ||r~|| <= 1e-10 ||F^~||, back-transform of the skeleton and
+recovery of the interior (all on the GPU; inputs resident in HBM).
+
+value = N * iterations / solve time  [GDOF/s]: total unknowns times CG
+iterations per second, i.e. the reciprocal of the time per DOF and iteration.
+The line also reports the apply kernel's own rate and its HBM roofline
+fraction (kernel durations from HIP events recorded by the library on its
+launch stream), and the FP64 CPU oracle's apply rate on this workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GDOF/s condensed Helmholtz apply; PCG time/DOF/iter, mixed vs FP64 @1e-10"
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wmesh, seconds=12.0):
+    """Time the FP64 CPU oracle's condensed apply (explicit Schur complements,
+    one GEMM per element class) on the same mesh, for about `seconds`."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import workloads as W
+    from oracle import mesh as M
+    from oracle.operators import CondensedOperator
+
+    op = CondensedOperator(M.make_mesh(**wmesh))
+    u = W.random_skeleton_input(op.sizes["N"], k=1, seed=0)[0]
+    op.apply(u)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        op.apply(u)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds or reps >= 2000:
+            break
+    threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    return {"value": op.sizes["N"] * reps / dt / 1e9, "unit": "GDOF/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "%d oracle condensed applies (explicit Schur complement, one DGEMM per element "
+                      "class; no CG vector work) on the same mesh, %.1f s, %s" % (reps, dt, cpu_model())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--apply-reps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; multi-GPU runs are not part of this build "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_1601_08179_amd import semcond
+
+    wmesh, f = W.config2(k=1)
+    ctx = semcond.Context(wmesh)
+    ft = torch.tensor(f, device="cuda")
+    u = torch.zeros_like(ft)
+    N, Ns = ctx.N, ctx.N_s
+
+    for _ in range(args.warmup):
+        ctx.solve(ft, out=u, tol=args.tol)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K full solves --------------------------------------------
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(args.steps):
+        _, info = ctx.solve(ft, out=u, tol=args.tol)
+        iters += info[0]["iters"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    apply_ms, launches = ctx.profile_read()
+    ctx.profile_enable(False)
+    solve_s = (t1 - t0) / args.steps
+    it_per_solve = iters / args.steps
+    value = N * iters / (t1 - t0) / 1e9
+    kern_s = apply_ms / 1e3 / max(launches, 1)
+
+    # ---- apply alone (transformed basis, back-to-back) ----------------------------
+    xs = torch.randn(Ns, dtype=torch.float64, device="cuda")
+    ys = torch.empty_like(xs)
+    for _ in range(10):
+        ctx.apply(xs, out=ys)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.apply_reps):
+        ctx.apply(xs, out=ys)
+    e1.record()
+    torch.cuda.synchronize()
+    apply_call_s = e0.elapsed_time(e1) / 1e3 / args.apply_reps
+
+    bytes_per_launch = 2 * 8 * Ns  # read u~ and write v~ once, FP64, k = 1
+    achieved = bytes_per_launch / kern_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": solve_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "BT solve to 1e-10: 16^3 uniform elements, p=8, lambda=1e-3, unit cube, "
+                               "Dirichlet, one N(0,1) nodal RHS (seeded)",
+                   "p": 8, "n_e": ctx.n_e, "N": N, "N_s": Ns, "k": 1, "tol": args.tol,
+                   "parallelism": "single GPU"},
+        "iterations": it_per_solve,
+        "ns_per_dof_iter": solve_s / (N * it_per_solve) * 1e9,
+        "apply_kernel_us": kern_s * 1e6,
+        "apply_kernel_gdof_s": N / kern_s / 1e9,
+        "apply_call_us": apply_call_s * 1e6,
+        "apply_call_gdof_s": N / apply_call_s / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_apply_tpt<double,7>", "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wmesh, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

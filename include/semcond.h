@@ -226,6 +226,16 @@ void semcond_solve_opts_default(semcond_solve_opts* opts);
 int semcond_solve(semcond_ctx* ctx, const void* f_nodal, void* u_nodal, int k,
                   const semcond_solve_opts* opts, semcond_solve_info* info, void* stream);
 
+/*
+ * Kernel tracing.  While enabled, every launch of the condensed-apply kernel
+ * (inside semcond_apply and semcond_solve) is bracketed by two HIP events
+ * recorded on the launch stream.  semcond_profile_enable resets the counters;
+ * semcond_profile_read synchronises the recorded events and returns the summed
+ * kernel time in milliseconds and the number of launches since the reset.
+ */
+int semcond_profile_enable(semcond_ctx* ctx, int enable);
+int semcond_profile_read(semcond_ctx* ctx, double* apply_ms, int64_t* apply_launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,7 +69,10 @@ class CondensedOperator:
 
     # -- apply ---------------------------------------------------------------
     def apply(self, u):
-        """v = R Hhat_L R^T u on the free skeleton (Sec. 4; one GEMM per class).
+        """v = R Hhat_L R^T u on the free skeleton (Sec. 4).
+
+        Face-to-face form with one dense matrix product per element class, the
+        "MMC" variant of Sec. 7 (Algorithm 2 with primary part included).
 
         u: (N,) or (N, k); constrained and interior entries of u are ignored.
         """
@@ -83,10 +86,11 @@ class CondensedOperator:
             if len(els) == 0:
                 continue
             idx = self.gB[els]                              # (ne_c, nB)
-            UL = Um[idx]                                    # (ne_c, nB, k)
-            VL = np.einsum("ab,ebk->eak", Hh, UL)
-            for r in range(V.shape[1]):
-                V[:, r] += np.bincount(idx.ravel(), weights=VL[:, :, r].ravel(),
+            k = Um.shape[1]
+            UL = Um[idx].transpose(1, 0, 2).reshape(len(self.B), -1)   # (nB, ne_c*k)
+            VL = (Hh @ UL).reshape(len(self.B), len(els), k)          # one GEMM per class
+            for r in range(k):
+                V[:, r] += np.bincount(idx.T.ravel(), weights=VL[:, :, r].ravel(),
                                        minlength=len(V))
         V[~self.free_skel] = 0.0
         return V[:, 0] if squeeze else V

@@ -57,6 +57,12 @@ struct semcond_ctx {
     Buffer ws_state;    // CG scalars (device)
     int* h_active = nullptr;  // pinned host copy of CG activity flags
     int h_active_cap = 0;
+    // tracing of the apply kernel
+    bool prof = false;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    size_t ev_used = 0;          // events recorded since the last read
+    double prof_ms = 0.0;
+    int64_t prof_launches = 0;
 };
 
 namespace {
@@ -166,7 +172,34 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, double* energy, h
     a.k = k;
     a.energy = energy;
     a.e_begin = 0;
+    if (c->prof) {
+        if (c->ev_used + 2 > c->ev.size()) {
+            for (int i = 0; i < 256; ++i) {
+                hipEvent_t e;
+                HIPCHK(c, hipEventCreate(&e));
+                c->ev.push_back(e);
+            }
+        }
+        HIPCHK(c, hipEventRecord(c->ev[c->ev_used], st));
+        HIPCHK(c, launch_apply_tpt<T>(a, c->n_e, st));
+        HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], st));
+        c->ev_used += 2;
+        return SEMCOND_OK;
+    }
     HIPCHK(c, launch_apply_tpt<T>(a, c->n_e, st));
+    return SEMCOND_OK;
+}
+
+// Accumulate the recorded event pairs into the profile totals.
+int profile_flush(semcond_ctx* c) {
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        HIPCHK(c, hipEventSynchronize(c->ev[i + 1]));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        c->prof_ms += ms;
+        c->prof_launches += 1;
+    }
+    c->ev_used = 0;
     return SEMCOND_OK;
 }
 
@@ -319,7 +352,27 @@ int semcond_destroy(semcond_ctx* c) {
     hipFree(c->ws_scratch.ptr);
     hipFree(c->ws_state.ptr);
     if (c->h_active) hipHostFree(c->h_active);
+    for (hipEvent_t e : c->ev) hipEventDestroy(e);
     delete c;
+    return SEMCOND_OK;
+}
+
+int semcond_profile_enable(semcond_ctx* c, int enable) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    int rc = profile_flush(c);
+    if (rc) return rc;
+    c->prof = enable != 0;
+    c->prof_ms = 0.0;
+    c->prof_launches = 0;
+    return SEMCOND_OK;
+}
+
+int semcond_profile_read(semcond_ctx* c, double* apply_ms, int64_t* apply_launches) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    int rc = profile_flush(c);
+    if (rc) return rc;
+    if (apply_ms) *apply_ms = c->prof_ms;
+    if (apply_launches) *apply_launches = c->prof_launches;
     return SEMCOND_OK;
 }
 

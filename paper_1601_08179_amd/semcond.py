@@ -63,6 +63,9 @@ _SIGS = {
     "semcond_nodal_to_skeleton": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_int, ctypes.c_void_p]),
     "semcond_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
+    "semcond_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "semcond_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int64)]),
     "semcond_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                      ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), ctypes.c_void_p]),
 }
@@ -202,6 +205,17 @@ class Context:
         N2 = self.n[1] * self.p + 1
         g = ijk[:, 0].astype(np.int64) + N1 * (ijk[:, 1].astype(np.int64) + N2 * ijk[:, 2].astype(np.int64))
         return g, free
+
+    # -- tracing -------------------------------------------------------------------
+    def profile_enable(self, enable=True):
+        _check(_lib.semcond_profile_enable(self._h, 1 if enable else 0), self._h)
+
+    def profile_read(self):
+        """(summed apply-kernel milliseconds, launches) since the last enable."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(_lib.semcond_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)), self._h)
+        return ms.value, n.value
 
     # -- operations --------------------------------------------------------------
     def _k_skel(self, t, name):
