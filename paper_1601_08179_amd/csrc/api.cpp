@@ -160,10 +160,11 @@ const double* pinv<double>(semcond_ctx* c) { return c->d_pinv64; }
 template <>
 const float* pinv<float>(semcond_ctx* c) { return c->d_pinv32; }
 
-// v = H~^ u (transformed).  v is zeroed first.  energy: optional [n_e][k].
+// v = H~^ u (transformed).  v is zeroed first unless v_is_zero.  energy: optional [n_e][k].
 template <typename T>
-int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, double* energy, hipStream_t st) {
-    HIPCHK(c, launch_fill<T>(v, c->N_s * k, (T)0, st));
+int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, double* energy, hipStream_t st,
+                      bool v_is_zero = false) {
+    if (!v_is_zero) HIPCHK(c, launch_fill<T>(v, c->N_s * k, (T)0, st));
     ApplyArgs<T> a;
     a.g = c->geo;
     a.tab = tabs<T>(c);
@@ -294,7 +295,8 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
         HIPCHK(c, launch_cg_init<T>(b, q, pinv<T>(c), r, p, Ns, k, w.partials, st));
     } else {
         HIPCHK(c, launch_fill<T>(x, Ns * k, (T)0, st));
-        HIPCHK(c, launch_cg_init<T>(b, nullptr, pinv<T>(c), r, p, Ns, k, w.partials, st));
+        HIPCHK(c, launch_fill<T>(q, Ns * k, (T)0, st));
+        HIPCHK(c, launch_cg_init<T>(b, (T*)nullptr, pinv<T>(c), r, p, Ns, k, w.partials, st));
     }
     HIPCHK(c, launch_cg_reduce(w.partials, kVecBlocks, 3, k, w.s, RED_INIT, st));
     if (check_every < 1) check_every = 1;
@@ -306,7 +308,8 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
             for (int i = 0; i < k; ++i) any |= c->h_active[i] != 0;
             if (!any) break;
         }
-        int rc = apply_transformed<T>(c, p, q, k, w.energy, st);
+        // q is zero here: zeroed at start and by every update
+        int rc = apply_transformed<T>(c, p, q, k, w.energy, st, true);
         if (rc) return rc;
         HIPCHK(c, launch_cg_reduce(w.energy, c->n_e, 1, k, w.s, RED_PQ, st));
         HIPCHK(c, launch_cg_update<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, st));

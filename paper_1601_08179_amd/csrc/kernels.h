@@ -79,18 +79,18 @@ constexpr int kVecBlocks = 512;  // fixed grid of the vector kernels (partials p
 
 int vec_block_threads(int k);
 
-// r = b - q0 (q0 nullable: then r = b), x = x0 or 0, p = pinv r,
+// r = b - q0 (q0 nullable: then r = b; else q0 is zeroed after use), p = pinv r,
 // partials[0]: r.z, [1]: r.r, [2]: b.b  ([3][kVecBlocks][k] doubles).
 template <typename T>
-hipError_t launch_cg_init(const T* b, const T* q0, const T* pinv, T* r, T* p, int64_t Ns, int k,
+hipError_t launch_cg_init(const T* b, T* q0, const T* pinv, T* r, T* p, int64_t Ns, int k,
                           double* partials, hipStream_t st);
 // Reduce [nparts][k] partials of `nq` quantities; mode selects the CG step logic.
 enum ReduceMode { RED_INIT = 0, RED_PQ = 1, RED_RZ = 2 };
 hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int k, CgState s, int mode,
                             hipStream_t st);
-// x += alpha p; r -= alpha q; partials[0] r.z (z = pinv r), [1] r.r.
+// x += alpha p; r -= alpha q; q = 0; partials[0] r.z (z = pinv r), [1] r.r.
 template <typename T>
-hipError_t launch_cg_update(T* x, T* r, const T* p, const T* q, const T* pinv, int64_t Ns, int k,
+hipError_t launch_cg_update(T* x, T* r, const T* p, T* q, const T* pinv, int64_t Ns, int k,
                             CgState s, double* partials, hipStream_t st);
 // p = pinv r + beta p.
 template <typename T>

@@ -515,16 +515,36 @@ __device__ inline void block_partials(double (&acc)[NQ], int k, double* __restri
     }
 }
 
+// Thread t of a block of B = k * (256/k) threads works on right-hand side
+// t mod k and on the nodes blockIdx.x * (B/k) + t/k + m * (B/k) * gridDim.x.
+struct VecIter {
+    int64_t s0, stride;
+    int rhs;
+};
+__device__ inline VecIter vec_iter(int k) {
+    VecIter it;
+    const int npb = blockDim.x / k;
+    it.rhs = threadIdx.x % k;
+    it.s0 = (int64_t)blockIdx.x * npb + threadIdx.x / k;
+    it.stride = (int64_t)npb * gridDim.x;
+    return it;
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_init(const T* __restrict__ b, const T* __restrict__ q0,
+__global__ __launch_bounds__(256) void k_cg_init(const T* __restrict__ b, T* __restrict__ q0,
                                                  const T* __restrict__ pinv, T* __restrict__ r, T* __restrict__ p,
                                                  int64_t Ns, int k, double* __restrict__ partials) {
-    const int64_t n = Ns * k;
+    const VecIter it = vec_iter(k);
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t s = it.s0; s < Ns; s += it.stride) {
+        const int64_t idx = s * k + it.rhs;
         const T bv = b[idx];
-        const T rv = q0 ? (T)(bv - q0[idx]) : bv;
-        const T z = pinv[idx / k] * rv;
+        T rv = bv;
+        if (q0) {
+            rv = bv - q0[idx];
+            q0[idx] = (T)0;  // leaves q zeroed for the first operator application
+        }
+        const T z = pinv[s] * rv;
         r[idx] = rv;
         p[idx] = z;
         acc[0] += (double)rv * (double)z;
@@ -535,16 +555,16 @@ __global__ __launch_bounds__(256) void k_cg_init(const T* __restrict__ b, const 
 }
 
 template <typename T>
-hipError_t launch_cg_init(const T* b, const T* q0, const T* pinv, T* r, T* p, int64_t Ns, int k, double* partials,
+hipError_t launch_cg_init(const T* b, T* q0, const T* pinv, T* r, T* p, int64_t Ns, int k, double* partials,
                           hipStream_t st) {
     hipLaunchKernelGGL(k_cg_init<T>, dim3(kVecBlocks), dim3(vec_block_threads(k)), 0, st, b, q0, pinv, r, p, Ns, k,
                        partials);
     return hipGetLastError();
 }
-template hipError_t launch_cg_init<double>(const double*, const double*, const double*, double*, double*, int64_t,
-                                           int, double*, hipStream_t);
-template hipError_t launch_cg_init<float>(const float*, const float*, const float*, float*, float*, int64_t, int,
-                                          double*, hipStream_t);
+template hipError_t launch_cg_init<double>(const double*, double*, const double*, double*, double*, int64_t, int,
+                                           double*, hipStream_t);
+template hipError_t launch_cg_init<float>(const float*, float*, const float*, float*, float*, int64_t, int, double*,
+                                          hipStream_t);
 
 // One block: totals of nq quantities per RHS, then the CG scalar step.
 __global__ __launch_bounds__(256) void k_cg_reduce(const double* __restrict__ partials, int64_t nparts, int nq,
@@ -632,21 +652,23 @@ hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int 
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                                                   const T* __restrict__ q, const T* __restrict__ pinv, int64_t Ns,
+                                                   T* __restrict__ q, const T* __restrict__ pinv, int64_t Ns,
                                                    int k, CgState s, double* __restrict__ partials) {
-    const int64_t n = Ns * k;
-    const int rhs = threadIdx.x % k;
-    const T alpha = (T)s.alpha[rhs];
-    const bool act = s.active[rhs] != 0;
+    const VecIter it = vec_iter(k);
+    const T alpha = (T)s.alpha[it.rhs];
+    const bool act = s.active[it.rhs] != 0;
     double acc[2] = {0.0, 0.0};
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t n = it.s0; n < Ns; n += it.stride) {
+        const int64_t idx = n * k + it.rhs;
         T rv = r[idx];
+        const T qv = q[idx];
+        q[idx] = (T)0;  // q is accumulated from zero by the next operator application
         if (act) {
             x[idx] += alpha * p[idx];
-            rv -= alpha * q[idx];
+            rv -= alpha * qv;
             r[idx] = rv;
         }
-        const T z = pinv[idx / k] * rv;
+        const T z = pinv[n] * rv;
         acc[0] += (double)rv * (double)z;
         acc[1] += (double)rv * (double)rv;
     }
@@ -654,26 +676,27 @@ __global__ __launch_bounds__(256) void k_cg_update(T* __restrict__ x, T* __restr
 }
 
 template <typename T>
-hipError_t launch_cg_update(T* x, T* r, const T* p, const T* q, const T* pinv, int64_t Ns, int k, CgState s,
+hipError_t launch_cg_update(T* x, T* r, const T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s,
                             double* partials, hipStream_t st) {
     hipLaunchKernelGGL(k_cg_update<T>, dim3(kVecBlocks), dim3(vec_block_threads(k)), 0, st, x, r, p, q, pinv, Ns, k,
                        s, partials);
     return hipGetLastError();
 }
-template hipError_t launch_cg_update<double>(double*, double*, const double*, const double*, const double*, int64_t,
-                                             int, CgState, double*, hipStream_t);
-template hipError_t launch_cg_update<float>(float*, float*, const float*, const float*, const float*, int64_t, int,
-                                            CgState, double*, hipStream_t);
+template hipError_t launch_cg_update<double>(double*, double*, const double*, double*, const double*, int64_t, int,
+                                             CgState, double*, hipStream_t);
+template hipError_t launch_cg_update<float>(float*, float*, const float*, float*, const float*, int64_t, int, CgState,
+                                            double*, hipStream_t);
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_direction(T* __restrict__ p, const T* __restrict__ r,
                                                       const T* __restrict__ pinv, int64_t Ns, int k, CgState s) {
-    const int64_t n = Ns * k;
-    const int rhs = threadIdx.x % k;
-    const T beta = (T)s.beta[rhs];
-    if (!s.active[rhs]) return;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x)
-        p[idx] = pinv[idx / k] * r[idx] + beta * p[idx];
+    const VecIter it = vec_iter(k);
+    const T beta = (T)s.beta[it.rhs];
+    if (!s.active[it.rhs]) return;
+    for (int64_t n = it.s0; n < Ns; n += it.stride) {
+        const int64_t idx = n * k + it.rhs;
+        p[idx] = pinv[n] * r[idx] + beta * p[idx];
+    }
 }
 
 template <typename T>
