@@ -160,6 +160,11 @@ const double* pinv<double>(semcond_ctx* c) { return c->d_pinv64; }
 template <>
 const float* pinv<float>(semcond_ctx* c) { return c->d_pinv32; }
 
+template <typename T>
+hipError_t launch_apply(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t st) {
+    return launch_apply_tpt<T>(a, n_elem, st);
+}
+
 // v = H~^ u (transformed).  v is zeroed first unless v_is_zero.  energy: optional [n_e][k].
 template <typename T>
 int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, double* energy, hipStream_t st,
@@ -182,12 +187,12 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, double* energy, h
             }
         }
         HIPCHK(c, hipEventRecord(c->ev[c->ev_used], st));
-        HIPCHK(c, launch_apply_tpt<T>(a, c->n_e, st));
+        HIPCHK(c, launch_apply<T>(a, c->n_e, st));
         HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], st));
         c->ev_used += 2;
         return SEMCOND_OK;
     }
-    HIPCHK(c, launch_apply_tpt<T>(a, c->n_e, st));
+    HIPCHK(c, launch_apply<T>(a, c->n_e, st));
     return SEMCOND_OK;
 }
 
@@ -246,16 +251,17 @@ struct CgWork {
     double* energy;    // [n_e][k]
 };
 
-// Device state layout inside ws_state.
-int cg_state(semcond_ctx* c, int k, CgWork* w) {
+// Device state layout inside ws_state: two independent CG states (slot 0 for
+// the CG iteration, slot 1 for the outer refinement loop of MIXED_IR).
+int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
     const size_t nd = 7 * (size_t)k + 1;               // rho pq alpha beta rr bb (6k) + spare k + tol2
     const size_t ni = 3 * (size_t)k;                    // active iters status
     const size_t np = 3 * (size_t)kVecBlocks * k;
     const size_t ne = (size_t)c->n_e * k;
-    const size_t bytes = (nd + np + ne) * sizeof(double) + ni * sizeof(int) + 256;
-    int rc = grow(c, c->ws_state, bytes);
+    const size_t one = ((nd + np + ne) * sizeof(double) + ni * sizeof(int) + 255) / 256 * 256;
+    int rc = grow(c, c->ws_state, 2 * one);
     if (rc) return rc;
-    double* d = (double*)c->ws_state.ptr;
+    double* d = (double*)((char*)c->ws_state.ptr + slot * one);
     w->s.rho = d;
     w->s.pq = d + k;
     w->s.alpha = d + 2 * k;
@@ -277,6 +283,26 @@ int cg_state(semcond_ctx* c, int k, CgWork* w) {
             return fail(c, SEMCOND_ENOMEM, "pinned host allocation failed");
         c->h_active_cap = 3 * k;
     }
+    return SEMCOND_OK;
+}
+
+struct CgHost {
+    std::vector<double> rr, bb;
+    std::vector<int> iters, status, active;
+};
+
+int read_state(semcond_ctx* c, const CgWork& w, int k, CgHost* h, hipStream_t st) {
+    h->rr.resize(k);
+    h->bb.resize(k);
+    h->iters.resize(k);
+    h->status.resize(k);
+    h->active.resize(k);
+    HIPCHK(c, hipMemcpyAsync(h->rr.data(), w.s.rr, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(h->bb.data(), w.s.bb, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(h->iters.data(), w.s.iters, k * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(h->status.data(), w.s.status, k * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(h->active.data(), w.s.active, k * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
     return SEMCOND_OK;
 }
 
@@ -635,25 +661,124 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
     else
         semcond_solve_opts_default(&o);
     if (!(o.tol > 0.0) || o.max_iter < 0) return fail(c, SEMCOND_EINVAL, "tol must be > 0 and max_iter >= 0");
-    if (o.precision != SEMCOND_PREC_F64) return fail(c, SEMCOND_EINVAL, "precision mode not available");
+    if (o.precision < SEMCOND_PREC_F64 || o.precision > SEMCOND_PREC_MIXED_IR)
+        return fail(c, SEMCOND_EINVAL, "unknown precision mode");
+    if (o.precision == SEMCOND_PREC_MIXED_IR && (!(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.max_outer < 1))
+        return fail(c, SEMCOND_EINVAL, "MIXED_IR needs 0 < inner_tol < 1 and max_outer >= 1");
     hipStream_t st = S(stream);
     const int64_t Ns = c->N_s;
     const size_t nv = (size_t)Ns * k;
-    rc = grow(c, c->ws_vec, 5 * nv * sizeof(double));
+    // FP64 vectors b x r p q, then FP32 vectors b x r p q
+    rc = grow(c, c->ws_vec, 5 * nv * sizeof(double) + (o.precision == SEMCOND_PREC_F64 ? 0 : 5 * nv * sizeof(float)));
     if (rc) return rc;
     double* b = (double*)c->ws_vec.ptr;
     double* x = b + nv;
     double* r = x + nv;
     double* p = r + nv;
     double* q = p + nv;
+    float* b32 = (float*)(q + nv);
+    float* x32 = b32 + nv;
+    float* r32 = x32 + nv;
+    float* p32 = r32 + nv;
+    float* q32 = p32 + nv;
     CgWork w;
-    rc = cg_state(c, k, &w);
+    rc = cg_state(c, k, 0, &w);
     if (rc) return rc;
     rc = condense_rhs64(c, (const double*)f, b, k, st);
     if (rc) return rc;
     if (o.x0) HIPCHK(c, hipMemcpyAsync(x, o.x0, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
-    rc = run_cg<double>(c, b, x, r, p, q, k, o.tol, o.max_iter, o.check_every, o.x0 != nullptr, w, st);
-    if (rc) return rc;
+
+    std::vector<int> iters(k, 0), status(k, 0), outer(k, 0);
+    std::vector<double> relres(k, 0.0);
+    CgHost h;
+    if (o.precision == SEMCOND_PREC_F64) {
+        rc = run_cg<double>(c, b, x, r, p, q, k, o.tol, o.max_iter, o.check_every, o.x0 != nullptr, w, st);
+        if (rc) return rc;
+        rc = read_state(c, w, k, &h, st);
+        if (rc) return rc;
+        for (int i = 0; i < k; ++i) {
+            iters[i] = h.iters[i];
+            status[i] = h.status[i] == 0 && h.active[i] ? SEMCOND_ENOTCONV : h.status[i];
+            relres[i] = h.bb[i] > 0 ? std::sqrt(h.rr[i] / h.bb[i]) : 0.0;
+        }
+    } else if (o.precision == SEMCOND_PREC_F32) {
+        // FP32 operator and vectors, FP64 dot products; no refinement
+        HIPCHK(c, (launch_convert<double, float>(b, b32, nv, st)));
+        if (o.x0) HIPCHK(c, (launch_convert<double, float>(x, x32, nv, st)));
+        rc = run_cg<float>(c, b32, x32, r32, p32, q32, k, o.tol, o.max_iter, o.check_every, o.x0 != nullptr, w, st);
+        if (rc) return rc;
+        HIPCHK(c, (launch_convert<float, double>(x32, x, nv, st)));
+        rc = read_state(c, w, k, &h, st);
+        if (rc) return rc;
+        for (int i = 0; i < k; ++i) {
+            iters[i] = h.iters[i];
+            status[i] = h.status[i] == 0 && h.active[i] ? SEMCOND_ENOTCONV : h.status[i];
+        }
+        // report the FP64 residual of the FP32 solution
+        CgWork wo;
+        rc = cg_state(c, k, 1, &wo);
+        if (rc) return rc;
+        const double tol2 = o.tol * o.tol;
+        HIPCHK(c, hipMemcpyAsync(wo.s.tol2, &tol2, sizeof(double), hipMemcpyHostToDevice, st));
+        rc = apply_transformed<double>(c, x, q, k, nullptr, st);
+        if (rc) return rc;
+        HIPCHK(c, launch_cg_init<double>(b, q, c->d_pinv64, r, p, Ns, k, wo.partials, st));
+        HIPCHK(c, launch_cg_reduce(wo.partials, kVecBlocks, 3, k, wo.s, RED_INIT, st));
+        CgHost ho;
+        rc = read_state(c, wo, k, &ho, st);
+        if (rc) return rc;
+        for (int i = 0; i < k; ++i) relres[i] = ho.bb[i] > 0 ? std::sqrt(ho.rr[i] / ho.bb[i]) : 0.0;
+    } else {
+        // Iterative refinement: outer FP64 residual r = b - A64 x, inner FP32
+        // CG on A32 d = r (FP64 dot products), x += d, until ||r|| <= tol ||b||.
+        CgWork wo;
+        rc = cg_state(c, k, 1, &wo);
+        if (rc) return rc;
+        const double tol2 = o.tol * o.tol;
+        HIPCHK(c, hipMemcpyAsync(wo.s.tol2, &tol2, sizeof(double), hipMemcpyHostToDevice, st));
+        if (!o.x0) HIPCHK(c, launch_fill<double>(x, nv, 0.0, st));
+        HIPCHK(c, launch_fill<double>(q, nv, 0.0, st));
+        int step = 0;
+        for (;; ++step) {
+            // r = b - A64 x (q holds A64 x; zeroed again by cg_init), convergence per RHS
+            if (step > 0 || o.x0) {
+                rc = apply_transformed<double>(c, x, q, k, nullptr, st, true);
+                if (rc) return rc;
+            }
+            HIPCHK(c, launch_cg_init<double>(b, q, c->d_pinv64, r, p, Ns, k, wo.partials, st));
+            HIPCHK(c, launch_cg_reduce(wo.partials, kVecBlocks, 3, k, wo.s, RED_INIT, st));
+            CgHost ho;
+            rc = read_state(c, wo, k, &ho, st);
+            if (rc) return rc;
+            bool any = false;
+            for (int i = 0; i < k; ++i) {
+                relres[i] = ho.bb[i] > 0 ? std::sqrt(ho.rr[i] / ho.bb[i]) : 0.0;
+                if (ho.status[i] < 0) status[i] = ho.status[i];
+                if (ho.active[i] && status[i] >= 0) {
+                    any = true;
+                    outer[i] = step + 1;
+                }
+            }
+            if (!any) break;
+            if (step >= o.max_outer) {
+                for (int i = 0; i < k; ++i)
+                    if (ho.active[i] && status[i] == 0) status[i] = SEMCOND_ENOTCONV;
+                break;
+            }
+            HIPCHK(c, launch_convert_masked(r, r32, nv, k, wo.s.active, st));
+            rc = run_cg<float>(c, r32, x32, b32, p32, q32, k, o.inner_tol, o.max_iter, o.check_every, false, w, st);
+            if (rc) return rc;
+            CgHost hi;
+            rc = read_state(c, w, k, &hi, st);
+            if (rc) return rc;
+            for (int i = 0; i < k; ++i) {
+                iters[i] += hi.iters[i];
+                if (hi.status[i] < 0 && status[i] == 0) status[i] = hi.status[i];
+            }
+            HIPCHK(c, launch_add_mixed(x, x32, nv, st));
+        }
+    }
+
     // back to the physical basis and the nodal array (Algorithm 4, second loop)
     HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.S, x, p, k, st));
     HIPCHK(c, launch_skel_to_nodal(c->L, p, (double*)u, c->N, k, st));
@@ -666,26 +791,17 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
                                           grid, st));
     }
     if (o.skel_out) HIPCHK(c, hipMemcpyAsync(o.skel_out, x, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
-    std::vector<double> rr(k), bb(k);
-    std::vector<int> iters(k), status(k), active(k);
-    HIPCHK(c, hipMemcpyAsync(rr.data(), w.s.rr, k * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipMemcpyAsync(bb.data(), w.s.bb, k * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipMemcpyAsync(iters.data(), w.s.iters, k * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipMemcpyAsync(status.data(), w.s.status, k * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipMemcpyAsync(active.data(), w.s.active, k * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     int worst = SEMCOND_OK;
     for (int i = 0; i < k; ++i) {
-        int s = status[i];
-        if (s == 0 && active[i]) s = SEMCOND_ENOTCONV;
         if (info) {
             info[i].iters = iters[i];
-            info[i].outer = 0;
-            info[i].rel_res = bb[i] > 0 ? std::sqrt(rr[i] / bb[i]) : 0.0;
-            info[i].status = s;
+            info[i].outer = outer[i];
+            info[i].rel_res = relres[i];
+            info[i].status = status[i];
         }
-        if (s < 0) worst = s;
-        else if (s == SEMCOND_ENOTCONV && worst == SEMCOND_OK) worst = s;
+        if (status[i] < 0) worst = status[i];
+        else if (status[i] == SEMCOND_ENOTCONV && worst == SEMCOND_OK) worst = status[i];
     }
     if (worst != SEMCOND_OK) fail(c, worst, "solve did not converge for every right-hand side");
     return worst;

@@ -17,15 +17,14 @@
 //
 // GPU mapping: one workgroup per element.  The element's 6 faces, 12 edges and
 // 8 vertices are gathered (R^T, index arithmetic on the skeleton layout) into
-// LDS.  For n_I <= 15 the eigenspace vector v = D^-1 u (n_I^3 values) is
-// formed in LDS with one thread per point, and each output slot's thread then
-// evaluates its primary-part row and, for face slots, its line reduction of v
-// along the face normal -- two barriers per element and right-hand side.  For
-// larger n_I the eigenspace is streamed in k-planes (double-buffered) by one
-// thread per (j,i) column, the b/t reductions stay in registers and the
-// w/e/s/n line reductions run per plane.  Results are summed into the skeleton
-// with hardware floating-point atomics (R).  Optionally each element's energy
-// u_e . (H~^ u)_e is written, whose sum is u . v (the CG step length).
+// LDS.  Thread (j,i) owns the column of eigenspace points (k, j, i), k = 0..n_I-1.
+// For n_I <= 15 the whole eigenspace vector v = D^-1 u fits in LDS and every
+// line reduction is done by the thread owning the output slot; for larger n_I
+// the eigenspace is streamed in k-planes (double-buffered), the b/t reductions
+// stay in registers and the w/e/s/n line reductions run per plane.  Results
+// are summed into the skeleton with hardware floating-point atomics (R).
+// Optionally each element's energy u_e . (H~^ u)_e is written, whose sum is
+// u . v (used for the CG step length).
 
 #include <hip/hip_runtime.h>
 
@@ -34,15 +33,8 @@
 
 namespace semcond {
 
-constexpr int apply_slots(int NI) { return 6 * NI * NI + 12 * NI + 8; }
-
-// Threads per element: for n_I <= 15 one thread per eigenspace point or output
-// slot (at most 512, looping beyond); for larger n_I one per (j,i) column.
 constexpr int apply_threads(int NI) {
-    return NI <= 15 ? (((NI * NI * NI > apply_slots(NI) ? NI * NI * NI : apply_slots(NI)) + 63) / 64 * 64 > 512
-                           ? 512
-                           : ((NI * NI * NI > apply_slots(NI) ? NI * NI * NI : apply_slots(NI)) + 63) / 64 * 64)
-                    : (NI * NI + 63) / 64 * 64;
+    return NI * NI <= 64 ? 64 : ((NI * NI + 63) / 64) * 64;
 }
 
 template <typename T, int NI>
@@ -55,7 +47,7 @@ __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A)
     constexpr int NW = CUBE ? NI * NI2 : 2 * NI2;
 
     __shared__ T F[NSLOT];       // gathered u~: faces [6][NI2], edges [12][NI], vertices [8]
-    __shared__ T OF[CUBE ? 1 : NFACE];  // condensed part of the face outputs (plane mode)
+    __shared__ T OF[NFACE];      // condensed part of the face outputs
     __shared__ T Wv[NW];         // eigenspace v = D^-1 u (cube or two planes)
     __shared__ T tl[3 * NI];     // Lambda, a, b
     __shared__ int64_t ebase[26];
@@ -112,13 +104,42 @@ __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A)
 
         // ---- condensed part: u_E = sum_f H~_EF u_f, v = D^-1 u_E, OF_f = -H~_FE v
         if constexpr (CUBE) {
-            // eigenspace v = D^-1 sum_f H~_Ef u_f, one point per thread
-            for (int idx = tid; idx < NI * NI2; idx += NT) {
-                const int i = idx % NI, j = (idx / NI) % NI, kk = idx / NI2;
-                const T uc = d1 * (ca[i] * UF(0, kk, j) + cb[i] * UF(1, kk, j)) +
-                             d2 * (ca[j] * UF(2, kk, i) + cb[j] * UF(3, kk, i)) +
-                             d3 * (ca[kk] * UF(4, j, i) + cb[kk] * UF(5, j, i));
-                Wv[idx] = uc / (d0 + d1 * lam[i] + d2 * lam[j] + d3 * lam[kk]);
+            if (tid < NI2) {
+                const int j = tid / NI, i = tid - (tid / NI) * NI;
+                const T ai = ca[i], bi = cb[i], aj = ca[j], bj = cb[j];
+                const T Dij = d0 + d1 * lam[i] + d2 * lam[j];
+                const T ub = UF(4, j, i), ut = UF(5, j, i);
+                T accb = 0, acct = 0;
+#pragma unroll
+                for (int kk = 0; kk < NI; ++kk) {
+                    const T ak = ca[kk], bk = cb[kk];
+                    T uc = d1 * (ai * UF(0, kk, j) + bi * UF(1, kk, j)) +
+                           d2 * (aj * UF(2, kk, i) + bj * UF(3, kk, i)) + d3 * (ak * ub + bk * ut);
+                    T vc = uc * recip<T>(Dij + d3 * lam[kk]);
+                    Wv[(kk * NI + j) * NI + i] = vc;
+                    accb += ak * vc;
+                    acct += bk * vc;
+                }
+                OF[4 * NI2 + tid] = -d3 * accb;
+                OF[5 * NI2 + tid] = -d3 * acct;
+            }
+            __syncthreads();
+            if (tid < NI2) {
+                const int s1 = tid / NI, s2 = tid - (tid / NI) * NI;
+                T sw = 0, se = 0, ss = 0, sn = 0;
+#pragma unroll
+                for (int m = 0; m < NI; ++m) {
+                    const T vi = Wv[(s1 * NI + s2) * NI + m];  // line along i at (k=s1, j=s2)
+                    sw += ca[m] * vi;
+                    se += cb[m] * vi;
+                    const T vj = Wv[(s1 * NI + m) * NI + s2];  // line along j at (k=s1, i=s2)
+                    ss += ca[m] * vj;
+                    sn += cb[m] * vj;
+                }
+                OF[0 * NI2 + tid] = -d1 * sw;
+                OF[1 * NI2 + tid] = -d1 * se;
+                OF[2 * NI2 + tid] = -d2 * ss;
+                OF[3 * NI2 + tid] = -d2 * sn;
             }
         } else {
             const int j = tid / NI, i = tid - (tid / NI) * NI;
@@ -139,7 +160,7 @@ __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A)
                     const T ak = ca[kk], bk = cb[kk];
                     T uc = d1 * (ai * UF(0, kk, j) + bi * UF(1, kk, j)) +
                            d2 * (aj * UF(2, kk, i) + bj * UF(3, kk, i)) + d3 * (ak * ub + bk * ut);
-                    T vc = uc / (Dij + d3 * lam[kk]);
+                    T vc = uc * recip<T>(Dij + d3 * lam[kk]);
                     P[tid] = vc;
                     accb += ak * vc;
                     acct += bk * vc;
@@ -222,26 +243,7 @@ __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A)
                               d2 * m0 * (ca[s1] * UE(2, s2) + cb[s1] * UE(3, s2));
                         break;
                 }
-                if constexpr (CUBE) {
-                    // condensed part: -d_n sum over the face normal of c_m v (Table 2, H~_FE)
-                    const T* c = (f & 1) ? cb : ca;
-                    T acc = 0;
-                    if (f < 2) {
-#pragma unroll
-                        for (int m = 0; m < NI; ++m) acc += c[m] * Wv[(s1 * NI + s2) * NI + m];
-                        out -= d1 * acc;
-                    } else if (f < 4) {
-#pragma unroll
-                        for (int m = 0; m < NI; ++m) acc += c[m] * Wv[(s1 * NI + m) * NI + s2];
-                        out -= d2 * acc;
-                    } else {
-#pragma unroll
-                        for (int m = 0; m < NI; ++m) acc += c[m] * Wv[(m * NI + s1) * NI + s2];
-                        out -= d3 * acc;
-                    }
-                } else {
-                    out += OF[s];
-                }
+                out += OF[s];
             } else if (s < NFACE + 12 * NI) {
                 const int q = (s - NFACE) / NI;
                 const int m = s - NFACE - q * NI;

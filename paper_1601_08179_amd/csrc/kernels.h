@@ -56,6 +56,10 @@ template <typename T>
 hipError_t launch_fill(T* x, int64_t n, T val, hipStream_t st);
 template <typename Tin, typename Tout>
 hipError_t launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t st);
+// out = active[r] ? float(in) : 0 per right-hand side r of an [N_s][k] array.
+hipError_t launch_convert_masked(const double* in, float* out, int64_t n, int k, const int* active, hipStream_t st);
+// x += double(d).
+hipError_t launch_add_mixed(double* x, const float* d, int64_t n, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Conjugate gradients (BT solver, Sec. 8) on [N_s][k] multivectors.
@@ -75,7 +79,7 @@ struct CgState {
     int* status;
 };
 
-constexpr int kVecBlocks = 512;  // fixed grid of the vector kernels (partials per RHS)
+constexpr int kVecBlocks = 2048;  // fixed grid of the vector kernels (partials per RHS)
 
 int vec_block_threads(int k);
 

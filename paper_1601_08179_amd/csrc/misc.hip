@@ -487,6 +487,33 @@ hipError_t launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 template hipError_t launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+
+// out[s*k + r] = active[r] ? (Tout)in[s*k + r] : 0   (residual hand-off of iterative refinement)
+template <typename Tin, typename Tout>
+__global__ void k_convert_masked(const Tin* __restrict__ in, Tout* __restrict__ out, int64_t n, int k,
+                                 const int* __restrict__ active) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = active[i % k] ? (Tout)in[i] : (Tout)0;
+}
+
+hipError_t launch_convert_masked(const double* in, float* out, int64_t n, int k, const int* active, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_convert_masked<double, float>), dim3(grid_for(n, 256)), dim3(256), 0, st, in, out, n, k,
+                       active);
+    return hipGetLastError();
+}
+
+// x += (double) d
+__global__ void k_add_mixed(double* __restrict__ x, const float* __restrict__ d, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += (double)d[i];
+}
+
+hipError_t launch_add_mixed(double* x, const float* d, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_mixed, dim3(grid_for(n, 256)), dim3(256), 0, st, x, d, n);
+    return hipGetLastError();
+}
 template hipError_t launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
 template hipError_t launch_convert<double, double>(const double*, double*, int64_t, hipStream_t);
 
@@ -498,20 +525,28 @@ template hipError_t launch_convert<double, double>(const double*, double*, int64
 
 int vec_block_threads(int k) { return k * (256 / k); }
 
+// Per-RHS block sums: the block holds npb = B/k values of each right-hand side
+// (value j of RHS r at position j*k + r); a fixed-shape tree adds them.
 template <int NQ>
 __device__ inline void block_partials(double (&acc)[NQ], int k, double* __restrict__ partials) {
     __shared__ double sh[NQ][256];
-    const int t = threadIdx.x, B = blockDim.x;
+    const int t = threadIdx.x, npb = blockDim.x / k;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) sh[q][t] = acc[q];
     __syncthreads();
+    int P = 1;
+    while (P < npb) P <<= 1;
+    const int j = t / k;
+    for (int w = P >> 1; w > 0; w >>= 1) {
+        if (j < w && j + w < npb) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) sh[q][t] += sh[q][t + w * k];
+        }
+        __syncthreads();
+    }
     if (t < k) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            double s = 0.0;
-            for (int m = t; m < B; m += k) s += sh[q][m];
-            partials[((int64_t)q * gridDim.x + blockIdx.x) * k + t] = s;
-        }
+        for (int q = 0; q < NQ; ++q) partials[((int64_t)q * gridDim.x + blockIdx.x) * k + t] = sh[q][t];
     }
 }
 

@@ -1,0 +1,115 @@
+"""GPU solver modes against the oracle: FP32 inner CG with FP64 iterative
+refinement (refined solution within 1e-10 of the oracle's direct solve), the
+unrefined FP32 solve (reported), k right-hand sides at once equal to k single
+solves, initial guess / resume, and error reporting."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import MESHES, both, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda", dtype=torch.float64)
+
+
+def _direct(op, f):
+    return np.stack([op.recover_interior(f[r], op.solve_condensed(f[r])) for r in range(f.shape[0])])
+
+
+@pytest.mark.parametrize("name", ["config1", "stretched3_p5", "lam_e_p3", "neumann_p6", "stretched3_p8", "p17_planes"])
+def test_mixed_ir_matches_direct(lib, name):
+    print("case", name, flush=True)
+    ctx, op, g, free = both(MESHES[name]())
+    f = W.random_skeleton_input(op.sizes["N"], k=3, seed=11)
+    u, info = ctx.solve(_t(f), tol=1e-12, precision=lib.PREC_MIXED_IR, inner_tol=1e-4)
+    ref = _direct(op, f)
+    u = u.cpu().numpy()
+    for r in range(3):
+        assert info[r]["status"] == 0 and info[r]["rel_res"] <= 1e-12, info[r]
+        assert info[r]["outer"] >= 2
+        assert np.abs(u[r] - ref[r]).max() <= 1e-10 * np.abs(ref[r]).max(), (name, r, info[r])
+
+
+@pytest.mark.parametrize("name", ["config1", "stretched3_p5"])
+def test_fp32_unrefined_reported(lib, name):
+    ctx, op, g, free = both(MESHES[name]())
+    f = W.random_skeleton_input(op.sizes["N"], k=2, seed=12)
+    u32, info = ctx.solve(_t(f), tol=1e-6, precision=lib.PREC_F32, raise_on_notconv=False)
+    u64, _ = ctx.solve(_t(f), tol=1e-12)
+    d = u32.cpu().numpy() - u64.cpu().numpy()
+    err = np.abs(d).max() / np.abs(u64.cpu().numpy()).max()
+    print("unrefined FP32 vs FP64 max rel err", name, err, info)
+    assert err < 1e-3
+
+
+@pytest.mark.parametrize("precision", ["PREC_F64", "PREC_MIXED_IR"])
+def test_batched_equals_single(lib, precision):
+    ctx, op, g, free = both(MESHES["stretched3_p5"]())
+    f = W.random_skeleton_input(op.sizes["N"], k=5, seed=13)
+    prec = getattr(lib, precision)
+    ub, infob = ctx.solve(_t(f), tol=1e-12, precision=prec)
+    ub = ub.cpu().numpy()
+    for r in range(5):
+        us, infos = ctx.solve(_t(f[r]), tol=1e-12, precision=prec)
+        assert rel_err(ub[r], us.cpu().numpy()) <= 1e-11
+        if precision == "PREC_F64":
+            assert infob[r]["iters"] == infos[0]["iters"]
+
+
+def test_zero_and_mixed_rhs(lib):
+    """A zero right-hand side converges in zero iterations beside nonzero ones."""
+    ctx, op, g, free = both(MESHES["config1"]())
+    f = W.random_skeleton_input(op.sizes["N"], k=3, seed=14)
+    f[1] = 0.0
+    u, info = ctx.solve(_t(f), tol=1e-12)
+    assert info[1]["iters"] == 0 and np.all(u.cpu().numpy()[1] == 0.0)
+    assert info[0]["iters"] > 0 and info[2]["iters"] > 0
+
+
+def test_resume_from_initial_guess(lib):
+    """Stop early (ENOTCONV, best iterate returned), resume with x0 = the
+    transformed skeleton iterate, reach the tolerance."""
+    import torch
+    ctx, op, g, free = both(MESHES["stretched3_p5"]())
+    f = W.random_skeleton_input(op.sizes["N"], k=1, seed=15)
+    skel = torch.zeros((ctx.N_s, 1), dtype=torch.float64, device="cuda")
+    _, info = ctx.solve(_t(f), tol=1e-12, max_iter=5, skel_out=skel, raise_on_notconv=False)
+    assert info[0]["status"] == lib.ENOTCONV and info[0]["iters"] == 5
+    u, info2 = ctx.solve(_t(f), tol=1e-12, x0=skel)
+    assert info2[0]["status"] == 0
+    ref = _direct(op, f)
+    assert np.abs(u.cpu().numpy()[0] - ref[0]).max() <= 1e-10 * np.abs(ref).max()
+    with pytest.raises(lib.SemcondError) as ei:
+        ctx.solve(_t(f), tol=1e-12, max_iter=3)
+    assert ei.value.code == lib.ENOTCONV
+
+
+def test_invalid_arguments(lib):
+    import torch
+    ctx, op, g, free = both(MESHES["config1"]())
+    f = _t(W.random_skeleton_input(op.sizes["N"], k=1, seed=16))
+    with pytest.raises(lib.SemcondError) as ei:
+        ctx.solve(f, tol=-1.0)
+    assert ei.value.code == lib.EINVAL
+    with pytest.raises(lib.SemcondError):
+        ctx.solve(f, precision=7)
+    with pytest.raises(lib.SemcondError):
+        ctx.solve(f, precision=lib.PREC_MIXED_IR, inner_tol=2.0)
+    with pytest.raises(ValueError):
+        ctx.apply(torch.zeros(ctx.N_s + 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        ctx.apply(torch.zeros(ctx.N_s, dtype=torch.int32, device="cuda"))
+
+
+def test_nonfinite_rhs_reported(lib):
+    ctx, op, g, free = both(MESHES["config1"]())
+    f = W.random_skeleton_input(op.sizes["N"], k=2, seed=17)
+    f[1, 434] = np.nan   # node (2, 3, 5): interior of element (0, 0, 1)
+    with pytest.raises(lib.SemcondError) as ei:
+        ctx.solve(_t(f), tol=1e-10)
+    assert ei.value.code == lib.ENONFINITE
