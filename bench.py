@@ -116,6 +116,16 @@ def main():
     value = N * iters / (t1 - t0) / 1e9
     kern_s = apply_ms / 1e3 / max(launches, 1)
 
+    # ---- same solve with FP32 inner CG + FP64 iterative refinement ---------------
+    mixed_steps = max(3, args.steps // 4)
+    ctx.solve(ft, out=u, tol=args.tol, precision=semcond.PREC_MIXED_IR, inner_tol=1e-4)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(mixed_steps):
+        _, minfo = ctx.solve(ft, out=u, tol=args.tol, precision=semcond.PREC_MIXED_IR, inner_tol=1e-4)
+    torch.cuda.synchronize()
+    mixed_s = (time.perf_counter() - t2) / mixed_steps
+
     # ---- apply alone (transformed basis, back-to-back) ----------------------------
     xs = torch.randn(Ns, dtype=torch.float64, device="cuda")
     ys = torch.empty_like(xs)
@@ -151,6 +161,9 @@ def main():
                    "parallelism": "single GPU"},
         "iterations": it_per_solve,
         "ns_per_dof_iter": solve_s / (N * it_per_solve) * 1e9,
+        "mixed_ir": {"ms_per_solve": mixed_s * 1e3, "speedup_vs_fp64": solve_s / mixed_s,
+                     "inner_iterations": minfo[0]["iters"], "outer_steps": minfo[0]["outer"],
+                     "rel_res": minfo[0]["rel_res"]},
         "apply_kernel_us": kern_s * 1e6,
         "apply_kernel_gdof_s": N / kern_s / 1e9,
         "apply_call_us": apply_call_s * 1e6,

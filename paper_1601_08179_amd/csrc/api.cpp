@@ -143,6 +143,9 @@ int check_dtype(semcond_ctx* c, int dtype) {
 
 int check_k(semcond_ctx* c, int k) {
     if (k < 1 || k > 256) return fail(c, SEMCOND_EINVAL, "k must be in [1, 256]");
+    // the apply kernels address [N_s][k] arrays with 32-bit offsets
+    if (c && c->N_s * (int64_t)k >= (int64_t(1) << 31))
+        return fail(c, SEMCOND_EINVAL, "N_s * k must stay below 2^31");
     return SEMCOND_OK;
 }
 

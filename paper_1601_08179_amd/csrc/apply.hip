@@ -42,14 +42,15 @@ __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A)
     constexpr int NI2 = NI * NI;
     constexpr int NT = apply_threads(NI);
     constexpr int NFACE = 6 * NI2;
-    constexpr int NSLOT = NFACE + 12 * NI + 8;
+    constexpr int NEDGE = 12 * NI;
+    constexpr int NSLOT = NFACE + NEDGE + 8;
     constexpr bool CUBE = NI <= 15;
     constexpr int NW = CUBE ? NI * NI2 : 2 * NI2;
 
-    __shared__ T F[NSLOT];       // gathered u~: faces [6][NI2], edges [12][NI], vertices [8]
-    __shared__ T OF[NFACE];      // condensed part of the face outputs
-    __shared__ T Wv[NW];         // eigenspace v = D^-1 u (cube or two planes)
-    __shared__ T tl[3 * NI];     // Lambda, a, b
+    __shared__ T F[NSLOT];              // gathered u~: faces [6][NI2], edges [12][NI], vertices [8]
+    __shared__ T OF[CUBE ? 1 : NFACE];  // condensed part of the face outputs (plane mode)
+    __shared__ T Wv[NW];                // eigenspace v = D^-1 u (cube or two planes)
+    __shared__ T tl[3 * NI];            // Lambda, a, b
     __shared__ int64_t ebase[26];
     __shared__ int econ[26];
     __shared__ double red[NT / 64];
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A)
     double dd[4];
     elem_metric(A.g, e, e1, e2, e3, dd);
     const T d0 = (T)dd[0], d1 = (T)dd[1], d2 = (T)dd[2], d3 = (T)dd[3];
-    const T m0 = A.tab.m0, K00 = A.tab.K00, K0p = A.tab.K0p;
+    const T m0 = A.tab.m0, K00 = A.tab.K00, K0p = A.tab.K0p, m02 = m0 * m0;
     const int k = A.k;
 
     if (tid < 26) {
@@ -81,65 +82,58 @@ __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A)
 
 #define UF(f, s1, s2) F[(f) * NI2 + (s1) * NI + (s2)]
 #define UE(q, m) F[NFACE + (q) * NI + (m)]
-#define UV(q) F[NFACE + 12 * NI + (q)]
+#define UV(q) F[NFACE + NEDGE + (q)]
 
     for (int r = 0; r < k; ++r) {
-        // ---- gather R^T: skeleton -> element boundary (constrained entities read as 0)
-        for (int s = tid; s < NSLOT; s += NT) {
-            int ent, loc;
-            if (s < NFACE) {
-                ent = s / NI2;
-                loc = s - ent * NI2;
-            } else if (s < NFACE + 12 * NI) {
-                int q = (s - NFACE) / NI;
-                ent = 6 + q;
-                loc = s - NFACE - q * NI;
-            } else {
-                ent = 18 + (s - NFACE - 12 * NI);
-                loc = 0;
+        // ---- gather R^T: skeleton -> element boundary (constrained entities read as 0).
+        // All loads of a thread are issued before any is consumed: the slot
+        // addresses are formed first, constrained slots read index r (a valid
+        // node) and are zeroed afterwards.
+        {
+            constexpr int NG = (NSLOT + NT - 1) / NT;
+            int64_t addr[NG];
+            bool keep[NG];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const int s = tid + g * NT;
+                int ent = 0, loc = 0;
+                if (s < NFACE) {
+                    ent = s / NI2;
+                    loc = s - ent * NI2;
+                } else if (s < NFACE + NEDGE) {
+                    const int q = (s - NFACE) / NI;
+                    ent = 6 + q;
+                    loc = s - NFACE - q * NI;
+                } else if (s < NSLOT) {
+                    ent = 18 + (s - NFACE - NEDGE);
+                }
+                keep[g] = s < NSLOT && !econ[ent];
+                addr[g] = keep[g] ? (ebase[ent] + loc) * k + r : (int64_t)r;
             }
-            F[s] = econ[ent] ? (T)0 : A.u[(ebase[ent] + loc) * k + r];
+            T val[NG];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) val[g] = (tid + g * NT < NSLOT) ? A.u[addr[g]] : (T)0;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const int s = tid + g * NT;
+                if (s < NSLOT) F[s] = keep[g] ? val[g] : (T)0;
+            }
         }
         __syncthreads();
 
-        // ---- condensed part: u_E = sum_f H~_EF u_f, v = D^-1 u_E, OF_f = -H~_FE v
+        // ---- condensed part: u_E = sum_f H~_EF u_f, v = D^-1 u_E
         if constexpr (CUBE) {
             if (tid < NI2) {
                 const int j = tid / NI, i = tid - (tid / NI) * NI;
                 const T ai = ca[i], bi = cb[i], aj = ca[j], bj = cb[j];
                 const T Dij = d0 + d1 * lam[i] + d2 * lam[j];
                 const T ub = UF(4, j, i), ut = UF(5, j, i);
-                T accb = 0, acct = 0;
 #pragma unroll
                 for (int kk = 0; kk < NI; ++kk) {
-                    const T ak = ca[kk], bk = cb[kk];
-                    T uc = d1 * (ai * UF(0, kk, j) + bi * UF(1, kk, j)) +
-                           d2 * (aj * UF(2, kk, i) + bj * UF(3, kk, i)) + d3 * (ak * ub + bk * ut);
-                    T vc = uc * recip<T>(Dij + d3 * lam[kk]);
-                    Wv[(kk * NI + j) * NI + i] = vc;
-                    accb += ak * vc;
-                    acct += bk * vc;
+                    const T uc = d1 * (ai * UF(0, kk, j) + bi * UF(1, kk, j)) +
+                                 d2 * (aj * UF(2, kk, i) + bj * UF(3, kk, i)) + d3 * (ca[kk] * ub + cb[kk] * ut);
+                    Wv[(kk * NI + j) * NI + i] = uc * recip<T>(Dij + d3 * lam[kk]);
                 }
-                OF[4 * NI2 + tid] = -d3 * accb;
-                OF[5 * NI2 + tid] = -d3 * acct;
-            }
-            __syncthreads();
-            if (tid < NI2) {
-                const int s1 = tid / NI, s2 = tid - (tid / NI) * NI;
-                T sw = 0, se = 0, ss = 0, sn = 0;
-#pragma unroll
-                for (int m = 0; m < NI; ++m) {
-                    const T vi = Wv[(s1 * NI + s2) * NI + m];  // line along i at (k=s1, j=s2)
-                    sw += ca[m] * vi;
-                    se += cb[m] * vi;
-                    const T vj = Wv[(s1 * NI + m) * NI + s2];  // line along j at (k=s1, i=s2)
-                    ss += ca[m] * vj;
-                    sn += cb[m] * vj;
-                }
-                OF[0 * NI2 + tid] = -d1 * sw;
-                OF[1 * NI2 + tid] = -d1 * se;
-                OF[2 * NI2 + tid] = -d2 * ss;
-                OF[3 * NI2 + tid] = -d2 * sn;
             }
         } else {
             const int j = tid / NI, i = tid - (tid / NI) * NI;
@@ -194,122 +188,107 @@ __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A)
         }
         __syncthreads();
 
-        // ---- primary part + condensed part, scatter-add R, element energy
         double en = 0.0;
-        const T m02 = m0 * m0;
-        for (int s = tid; s < NSLOT; s += NT) {
-            T out;
-            int ent, loc;
-            if (s < NFACE) {
-                const int f = s / NI2;
-                loc = s - f * NI2;
-                ent = f;
+        T* const vr = A.v + r;
+        // ---- faces, one algebraic form for all six (Sec. 6 primary part, Table 2
+        // condensed part), one face per round so that every face-dependent
+        // quantity is wave-uniform.  Face f = w,e,s,n,b,t has slot (s1,s2) =
+        // (k,j), (k,j), (k,i), (k,i), (j,i), (j,i); normal / fast / slow axes
+        // give d_n, d_fast, d_slow.  Bordering edges (UE index), fast-lo,
+        // fast-hi, slow-lo, slow-hi: w {8,10,4,6} e {9,11,5,7} s {8,9,0,2}
+        // n {10,11,1,3} b {4,5,0,1} t {6,7,2,3}.
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            constexpr int efl_t[6] = {8, 9, 8, 10, 4, 6}, efh_t[6] = {10, 11, 9, 11, 5, 7};
+            constexpr int esl_t[6] = {4, 5, 0, 1, 0, 2}, esh_t[6] = {6, 7, 2, 3, 1, 3};
+            const int efl = efl_t[f], efh = efh_t[f], esl = esl_t[f], esh = esh_t[f];
+            const T dn = f < 2 ? d1 : (f < 4 ? d2 : d3);
+            const T dfast = f < 2 ? d2 : d1;
+            const T dslow = f < 4 ? d3 : d2;
+            const T* cc = (f & 1) ? cb : ca;
+            const bool con = econ[f] != 0;
+            const uint32_t fbase = (uint32_t)ebase[f];
+            for (int loc = tid; loc < NI2; loc += NT) {
                 const int s1 = loc / NI, s2 = loc - (loc / NI) * NI;
-                switch (f) {
-                    case 0:  // w: (k, j) = (s1, s2); edges Z(0,0), Z(0,1) along k; Y(0,0), Y(0,1) along j
-                        out = (d0 * m0 + d1 * K00 + d2 * m0 * lam[s2] + d3 * m0 * lam[s1]) * UF(0, s1, s2) +
-                              d1 * K0p * UF(1, s1, s2) +
-                              d2 * m0 * (ca[s2] * UE(8, s1) + cb[s2] * UE(10, s1)) +
-                              d3 * m0 * (ca[s1] * UE(4, s2) + cb[s1] * UE(6, s2));
-                        break;
-                    case 1:  // e
-                        out = (d0 * m0 + d1 * K00 + d2 * m0 * lam[s2] + d3 * m0 * lam[s1]) * UF(1, s1, s2) +
-                              d1 * K0p * UF(0, s1, s2) +
-                              d2 * m0 * (ca[s2] * UE(9, s1) + cb[s2] * UE(11, s1)) +
-                              d3 * m0 * (ca[s1] * UE(5, s2) + cb[s1] * UE(7, s2));
-                        break;
-                    case 2:  // s: (k, i) = (s1, s2); edges Z(0,0), Z(1,0) along k; X(0,0), X(0,1) along i
-                        out = (d0 * m0 + d2 * K00 + d1 * m0 * lam[s2] + d3 * m0 * lam[s1]) * UF(2, s1, s2) +
-                              d2 * K0p * UF(3, s1, s2) +
-                              d1 * m0 * (ca[s2] * UE(8, s1) + cb[s2] * UE(9, s1)) +
-                              d3 * m0 * (ca[s1] * UE(0, s2) + cb[s1] * UE(2, s2));
-                        break;
-                    case 3:  // n
-                        out = (d0 * m0 + d2 * K00 + d1 * m0 * lam[s2] + d3 * m0 * lam[s1]) * UF(3, s1, s2) +
-                              d2 * K0p * UF(2, s1, s2) +
-                              d1 * m0 * (ca[s2] * UE(10, s1) + cb[s2] * UE(11, s1)) +
-                              d3 * m0 * (ca[s1] * UE(1, s2) + cb[s1] * UE(3, s2));
-                        break;
-                    case 4:  // b: (j, i) = (s1, s2); edges Y(0,0), Y(1,0) along j; X(0,0), X(1,0) along i
-                        out = (d0 * m0 + d3 * K00 + d1 * m0 * lam[s2] + d2 * m0 * lam[s1]) * UF(4, s1, s2) +
-                              d3 * K0p * UF(5, s1, s2) +
-                              d1 * m0 * (ca[s2] * UE(4, s1) + cb[s2] * UE(5, s1)) +
-                              d2 * m0 * (ca[s1] * UE(0, s2) + cb[s1] * UE(1, s2));
-                        break;
-                    default:  // t
-                        out = (d0 * m0 + d3 * K00 + d1 * m0 * lam[s2] + d2 * m0 * lam[s1]) * UF(5, s1, s2) +
-                              d3 * K0p * UF(4, s1, s2) +
-                              d1 * m0 * (ca[s2] * UE(6, s1) + cb[s2] * UE(7, s1)) +
-                              d2 * m0 * (ca[s1] * UE(2, s2) + cb[s1] * UE(3, s2));
-                        break;
+                T cond;
+                if constexpr (CUBE) {
+                    // eigenspace line along the face normal: w/e along i, s/n along j, b/t along k
+                    const int base = f < 2 ? loc * NI : (f < 4 ? s1 * NI2 + s2 : loc);
+                    constexpr int st_t[3] = {1, NI, NI2};
+                    T acc = 0;
+#pragma unroll
+                    for (int m = 0; m < NI; ++m) acc += cc[m] * Wv[base + m * st_t[f >> 1]];
+                    cond = -dn * acc;
+                } else {
+                    cond = OF[f * NI2 + loc];
                 }
-                out += OF[s];
-            } else if (s < NFACE + 12 * NI) {
-                const int q = (s - NFACE) / NI;
-                const int m = s - NFACE - q * NI;
-                loc = m;
-                ent = 6 + q;
-                if (q < 4) {  // X(jb,kb) along i: faces b/t (kb) over j, s/n (jb) over k
-                    const int jb = q & 1, kb = q >> 1;
-                    const T* cj = jb ? cb : ca;
-                    const T* ck = kb ? cb : ca;
-                    T sf1 = 0, sf2 = 0;
-                    for (int m2 = 0; m2 < NI; ++m2) {
-                        sf1 += cj[m2] * UF(4 + kb, m2, m);
-                        sf2 += ck[m2] * UF(2 + jb, m2, m);
-                    }
-                    out = (d0 * m02 + d1 * m02 * lam[m] + (d2 + d3) * m0 * K00) * UE(q, m) +
-                          d2 * m0 * K0p * UE((1 - jb) + 2 * kb, m) + d3 * m0 * K0p * UE(jb + 2 * (1 - kb), m) +
-                          d1 * m02 * (ca[m] * UV(2 * jb + 4 * kb) + cb[m] * UV(1 + 2 * jb + 4 * kb)) +
-                          d2 * m0 * sf1 + d3 * m0 * sf2;
-                } else if (q < 8) {  // Y(ib,kb) along j: faces b/t (kb) over i, w/e (ib) over k
-                    const int ib = (q - 4) & 1, kb = (q - 4) >> 1;
-                    const T* ci = ib ? cb : ca;
-                    const T* ck = kb ? cb : ca;
-                    T sf1 = 0, sf2 = 0;
-                    for (int m2 = 0; m2 < NI; ++m2) {
-                        sf1 += ci[m2] * UF(4 + kb, m, m2);
-                        sf2 += ck[m2] * UF(ib, m2, m);
-                    }
-                    out = (d0 * m02 + d2 * m02 * lam[m] + (d1 + d3) * m0 * K00) * UE(q, m) +
-                          d1 * m0 * K0p * UE(4 + (1 - ib) + 2 * kb, m) + d3 * m0 * K0p * UE(4 + ib + 2 * (1 - kb), m) +
-                          d2 * m02 * (ca[m] * UV(ib + 4 * kb) + cb[m] * UV(ib + 2 + 4 * kb)) +
-                          d1 * m0 * sf1 + d3 * m0 * sf2;
-                } else {  // Z(ib,jb) along k: faces s/n (jb) over i, w/e (ib) over j
-                    const int ib = (q - 8) & 1, jb = (q - 8) >> 1;
-                    const T* ci = ib ? cb : ca;
-                    const T* cj = jb ? cb : ca;
-                    T sf1 = 0, sf2 = 0;
-                    for (int m2 = 0; m2 < NI; ++m2) {
-                        sf1 += ci[m2] * UF(2 + jb, m, m2);
-                        sf2 += cj[m2] * UF(ib, m, m2);
-                    }
-                    out = (d0 * m02 + d3 * m02 * lam[m] + (d1 + d2) * m0 * K00) * UE(q, m) +
-                          d1 * m0 * K0p * UE(8 + (1 - ib) + 2 * jb, m) + d2 * m0 * K0p * UE(8 + ib + 2 * (1 - jb), m) +
-                          d3 * m02 * (ca[m] * UV(ib + 2 * jb) + cb[m] * UV(ib + 2 * jb + 4)) +
-                          d1 * m0 * sf1 + d2 * m0 * sf2;
+                const T uf = F[f * NI2 + loc];
+                const T out = (d0 * m0 + dn * K00 + dfast * m0 * lam[s2] + dslow * m0 * lam[s1]) * uf +
+                              dn * K0p * F[(f ^ 1) * NI2 + loc] +
+                              dfast * m0 * (ca[s2] * UE(efl, s1) + cb[s2] * UE(efh, s1)) +
+                              dslow * m0 * (ca[s1] * UE(esl, s2) + cb[s1] * UE(esh, s2)) + cond;
+                if (!con) {
+                    atomic_add(vr + (fbase + (uint32_t)loc) * (uint32_t)k, out);
+                    en += (double)uf * (double)out;
                 }
-            } else {
-                const int q = s - NFACE - 12 * NI;
-                const int ib = q & 1, jb = (q >> 1) & 1, kb = q >> 2;
-                ent = 18 + q;
-                loc = 0;
-                const T* ci = ib ? cb : ca;
-                const T* cj = jb ? cb : ca;
-                const T* ck = kb ? cb : ca;
-                T sx = 0, sy = 0, sz = 0;
-                for (int m2 = 0; m2 < NI; ++m2) {
-                    sx += ci[m2] * UE(jb + 2 * kb, m2);
-                    sy += cj[m2] * UE(4 + ib + 2 * kb, m2);
-                    sz += ck[m2] * UE(8 + ib + 2 * jb, m2);
-                }
-                out = (d0 * m02 * m0 + (d1 + d2 + d3) * m02 * K00) * UV(q) +
-                      m02 * K0p * (d1 * UV(q ^ 1) + d2 * UV(q ^ 2) + d3 * UV(q ^ 4)) +
-                      m02 * (d1 * sx + d2 * sy + d3 * sz);
             }
-            if (!econ[ent]) {
-                atomic_add(&A.v[(ebase[ent] + loc) * k + r], out);
-                en += (double)F[s] * (double)out;
+        }
+        // ---- edges, one direction per round: edge q = 4 par + b0 + 2 b1 along axis
+        // `par`, other axes o1, o2 at boundary bits b0, b1.  Neighbour edges differ
+        // in one bit; the face couplings are line sums of the two bordering faces.
+#pragma unroll
+        for (int par = 0; par < 3; ++par) {
+            const T dpar = par == 0 ? d1 : (par == 1 ? d2 : d3);
+            const T do1 = par == 0 ? d2 : d1;
+            const T do2 = par == 2 ? d2 : d3;
+            const T dg0 = d0 * m02 + (do1 + do2) * m0 * K00;
+            for (int idx = tid; idx < 4 * NI; idx += NT) {
+                const int qq = idx / NI, m = idx - (idx / NI) * NI;
+                const int b0 = qq & 1, b1 = qq >> 1, q = 4 * par + qq;
+                const T* c0 = b0 ? cb : ca;
+                const T* c1 = b1 ? cb : ca;
+                // X(jb,kb): sum_j c^jb_j b/t(kb)[j][m], sum_k c^kb_k s/n(jb)[k][m]
+                // Y(ib,kb): sum_i c^ib_i b/t(kb)[m][i], sum_k c^kb_k w/e(ib)[k][m]
+                // Z(ib,jb): sum_i c^ib_i s/n(jb)[m][i], sum_j c^jb_j w/e(ib)[m][j]
+                const int f1 = (par == 2 ? 2 : 4) + b1, f2 = (par == 0 ? 2 : 0) + b0;
+                const int base1 = f1 * NI2 + (par == 0 ? m : m * NI), st1 = par == 0 ? NI : 1;
+                const int base2 = f2 * NI2 + (par == 2 ? m * NI : m), st2 = par == 2 ? 1 : NI;
+                T l1 = 0, l2 = 0;
+#pragma unroll
+                for (int m2 = 0; m2 < NI; ++m2) {
+                    l1 += c0[m2] * F[base1 + m2 * st1];
+                    l2 += c1[m2] * F[base2 + m2 * st2];
+                }
+                const int vlo = par == 0 ? 2 * b0 + 4 * b1 : (par == 1 ? b0 + 4 * b1 : b0 + 2 * b1);
+                const int vhi = vlo + (par == 0 ? 1 : (par == 1 ? 2 : 4));
+                const T ue = UE(q, m);
+                const T out = (dg0 + dpar * m02 * lam[m]) * ue + m0 * K0p * (do1 * UE(q ^ 1, m) + do2 * UE(q ^ 2, m)) +
+                              dpar * m02 * (ca[m] * UV(vlo) + cb[m] * UV(vhi)) + m0 * (do1 * l1 + do2 * l2);
+                if (!econ[6 + q]) {
+                    atomic_add(vr + ((uint32_t)ebase[6 + q] + (uint32_t)m) * (uint32_t)k, out);
+                    en += (double)ue * (double)out;
+                }
+            }
+        }
+        // ---- vertices
+        if (tid < 8) {
+            const int q = tid, ib = q & 1, jb = (q >> 1) & 1, kb = q >> 2;
+            const T* ci_ = ib ? cb : ca;
+            const T* cj_ = jb ? cb : ca;
+            const T* ck_ = kb ? cb : ca;
+            T sx = 0, sy = 0, sz = 0;
+#pragma unroll
+            for (int m2 = 0; m2 < NI; ++m2) {
+                sx += ci_[m2] * UE(jb + 2 * kb, m2);
+                sy += cj_[m2] * UE(4 + ib + 2 * kb, m2);
+                sz += ck_[m2] * UE(8 + ib + 2 * jb, m2);
+            }
+            const T out = (d0 * m02 * m0 + (d1 + d2 + d3) * m02 * K00) * UV(q) +
+                          m02 * K0p * (d1 * UV(q ^ 1) + d2 * UV(q ^ 2) + d3 * UV(q ^ 4)) +
+                          m02 * (d1 * sx + d2 * sy + d3 * sz);
+            if (!econ[18 + q]) {
+                atomic_add(vr + (uint32_t)ebase[18 + q] * (uint32_t)k, out);
+                en += (double)UV(q) * (double)out;
             }
         }
         if (A.energy) {
@@ -317,9 +296,9 @@ __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A)
             if ((tid & 63) == 0) red[tid >> 6] = en;
             __syncthreads();
             if (tid == 0) {
-                double s = 0.0;
-                for (int w = 0; w < NT / 64; ++w) s += red[w];
-                A.energy[e * k + r] = s;
+                double sum = 0.0;
+                for (int w = 0; w < NT / 64; ++w) sum += red[w];
+                A.energy[e * k + r] = sum;
             }
         }
         __syncthreads();
