@@ -87,7 +87,8 @@ typedef struct semcond_ctx semcond_ctx;
  *   dcoef_e         optional per-element metric override d_e (n_e x 4, row
  *                   per element, entries 1..3 > 0, entry 0 >= 0), or NULL;
  *                   when given it replaces widths/lambda in the operator (the
- *                   RHS mass matrix still uses the widths)
+ *                   RHS mass matrix still uses the widths); when lambda_e is
+ *                   given too, d_{e,0} = J_e lambda_e and column 0 is ignored
  *   dirichlet_mask  bit 0: x1-low face, 1: x1-high, 2: x2-low, 3: x2-high,
  *                   4: x3-low, 5: x3-high.  Set bits carry homogeneous
  *                   Dirichlet conditions, clear bits natural ones.  With
@@ -114,6 +115,9 @@ typedef struct {
     void* skel_out;         /* optional out: TRANSFORMED skeleton solution [N_s][k] FP64  */
     double inner_tol;       /* MIXED_IR: relative tolerance of each FP32 inner solve      */
     int max_outer;          /* MIXED_IR: refinement steps, default 30                     */
+    int rhs_dual;           /* 0: f are nodal values, F = M_G f (default); 1: f is the   */
+                            /* assembled discrete right-hand side itself (R F_L), as in  */
+                            /* an adjoint solve H_G a = dL/du                             */
 } semcond_solve_opts;
 
 /* Per right-hand-side result of semcond_solve (host array of k entries). */
@@ -225,6 +229,39 @@ void semcond_solve_opts_default(semcond_solve_opts* opts);
  */
 int semcond_solve(semcond_ctx* ctx, const void* f_nodal, void* u_nodal, int k,
                   const semcond_solve_opts* opts, semcond_solve_info* info, void* stream);
+
+/*
+ * Replace the Helmholtz parameter / metric coefficients of an existing context
+ * (Sec. 3: d_e = (h1 h2 h3/8)(lambda, 4/h1^2, 4/h2^2, 4/h3^2); Sec. 8 notes that
+ * lambda changes between time steps) and rebuild the preconditioner.  Same
+ * meaning and validation as the semcond_mesh fields (host pointers, copied;
+ * lambda_e and dcoef_e may be NULL).  Widths and the RHS mass are unchanged.
+ * Synchronises the stream.
+ */
+int semcond_update_coefficients(semcond_ctx* ctx, double lambda, const double* lambda_e,
+                                const double* dcoef_e, void* stream);
+
+/* Assembled GLL-lumped mass M_G = R (J_e W(x)W(x)W) R^T as a nodal array
+ * (Sec. 3; J_e = h1 h2 h3 / 8).  mass: device [N] FP64. */
+int semcond_nodal_mass(semcond_ctx* ctx, void* mass, void* stream);
+
+/* out = M_G (x) in, or in / M_G when inverse != 0, for nodal [k][N] FP64
+ * arrays (the assembled GLL-lumped mass of Sec. 3; dL/df = M_G a in the
+ * adjoint method).  in and out may coincide. */
+int semcond_mass_apply(semcond_ctx* ctx, const void* in, void* out, int k, int inverse, void* stream);
+
+/*
+ * Element gradients for the adjoint method: with u the solution of the full
+ * discrete system H_G u = M_G f and a the adjoint (H_G a = dL/du), the
+ * derivative of L with respect to the metric coefficient d_{e,m} (Sec. 3, eq.
+ * helmholtz_operator, H_e = sum_m d_{e,m} A_m) is -a_e^T A_m u_e.
+ *   u_nodal, a_nodal  device [k][N] FP64, full nodal vectors (interior included)
+ *   grad              device [n_e][5] FP64, summed over the k right-hand sides:
+ *                     columns 0..3 dL/dd_{e,0..3}, column 4 dL/dlambda_e =
+ *                     J_e dL/dd_{e,0} (d_{e,0} = J_e lambda_e)
+ */
+int semcond_element_grads(semcond_ctx* ctx, const void* u_nodal, const void* a_nodal, void* grad,
+                          int k, void* stream);
 
 /*
  * Kernel tracing.  While enabled, every launch of the condensed-apply kernel

@@ -1,0 +1,48 @@
+"""Differentiable solve: torch.autograd.Function around the library's BT solve.
+
+forward:  u = H_G^-1 M_G f for nodal right-hand sides f [k, N], with the element
+          operators H_e = sum_m d_{e,m} A_m (Sec. 3), d_{e,0} = J_e lambda_e and
+          the metric terms d_{e,1..3} taken as independent per-element inputs.
+backward: one adjoint solve with the same operator (H_G is symmetric), a =
+          H_G^-1 dL/du (the library's solve with an assembled right-hand side,
+          interior recovered), then dL/df = M_G a, dL/dlambda_e and dL/dd_{e,1..3}
+          from the library's per-element kernel (-a_e^T A_m u_e).
+All arithmetic runs in the HIP library; this module only moves tensors.
+"""
+
+import torch
+
+from . import semcond
+
+
+class _Solve(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, f, lam_e, dmetric, ctx, tol, precision):
+        dcoef = torch.zeros((ctx.n_e, 4), dtype=torch.float64)
+        dcoef[:, 1:] = dmetric.detach().to("cpu", torch.float64)
+        ctx.update_coefficients(lam_e=lam_e.detach().to("cpu", torch.float64).numpy(), dcoef=dcoef.numpy())
+        u, info = ctx.solve(f.detach().contiguous(), tol=tol, precision=precision)
+        fctx.ctx = ctx
+        fctx.tol = tol
+        fctx.precision = precision
+        fctx.info = info
+        fctx.save_for_backward(u)
+        return u
+
+    @staticmethod
+    def backward(fctx, grad_u):
+        (u,) = fctx.saved_tensors
+        ctx = fctx.ctx
+        a, _ = ctx.solve(grad_u.contiguous(), tol=fctx.tol, precision=fctx.precision, rhs_dual=True)
+        g = ctx.element_grads(u, a)
+        grad_f = ctx.mass_apply(a)
+        return grad_f, g[:, 4], g[:, 1:4], None, None, None
+
+
+def solve(ctx, f, lam_e, dmetric, tol=1e-12, precision=semcond.PREC_F64):
+    """Differentiable u(f, lambda_e, d_{e,1..3}) on the mesh of `ctx` (a semcond.Context).
+
+    f: [k, N] or [N] float64 CUDA tensor; lam_e: [n_e]; dmetric: [n_e, 3]
+    (the metric coefficients d_{e,1}, d_{e,2}, d_{e,3}).  Returns nodal u like f.
+    """
+    return _Solve.apply(f, lam_e, dmetric, ctx, tol, precision)

@@ -25,6 +25,7 @@ template <typename T>
 struct DevTables {
     T* buf = nullptr;
     DevTab<T> tab{};
+    const T* K = nullptr;  // (p+1)^2 stiffness
 };
 
 struct Buffer {
@@ -55,6 +56,7 @@ struct semcond_ctx {
     Buffer ws_vec;      // vectors for apply / solve
     Buffer ws_scratch;  // element cubes for large p
     Buffer ws_state;    // CG scalars (device)
+    Buffer ws_nodal;    // nodal right-hand sides of dual solves
     int* h_active = nullptr;  // pinned host copy of CG activity flags
     int h_active_cap = 0;
     // tracing of the apply kernel
@@ -100,7 +102,7 @@ template <typename T>
 int upload_tables(semcond_ctx* c, DevTables<T>& d) {
     const Tables1D& t = c->t;
     const int NI = t.NI, n = t.p + 1;
-    const size_t count = 3 * NI + 4 * (size_t)NI * NI + n;
+    const size_t count = 3 * NI + 4 * (size_t)NI * NI + n + (size_t)n * n;
     std::vector<T> h(count);
     size_t o = 0;
     auto put = [&](const std::vector<double>& v) {
@@ -115,6 +117,7 @@ int upload_tables(semcond_ctx* c, DevTables<T>& d) {
     put(t.Sinv);
     put(t.SinvT);
     put(t.w);
+    put(t.K);
     HIPCHK(c, hipMalloc(&d.buf, count * sizeof(T)));
     HIPCHK(c, hipMemcpy(d.buf, h.data(), count * sizeof(T), hipMemcpyHostToDevice));
     T* b = d.buf;
@@ -126,6 +129,7 @@ int upload_tables(semcond_ctx* c, DevTables<T>& d) {
     d.tab.Sinv = d.tab.St + NI * NI;
     d.tab.SinvT = d.tab.Sinv + NI * NI;
     d.tab.w = d.tab.SinvT + NI * NI;
+    d.K = d.tab.w + n;
     d.tab.m0 = (T)t.m0;
     d.tab.K00 = (T)t.K00;
     d.tab.K0p = (T)t.K0p;
@@ -348,6 +352,48 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     return SEMCOND_OK;
 }
 
+// Upload lambda / lambda_e / dcoef_e (validated by the caller) and rebuild the
+// preconditioner diagonal and its inverses.
+int set_coefficients(semcond_ctx* c, double lambda, const double* lambda_e, const double* dcoef_e, hipStream_t st) {
+    const int64_t ne = c->n_e;
+    if (lambda_e) {
+        if (!c->d_lam_e) HIPCHK(c, hipMalloc(&c->d_lam_e, ne * sizeof(double)));
+        HIPCHK(c, hipMemcpy(c->d_lam_e, lambda_e, ne * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (dcoef_e) {
+        if (!c->d_dcoef) HIPCHK(c, hipMalloc(&c->d_dcoef, 4 * ne * sizeof(double)));
+        HIPCHK(c, hipMemcpy(c->d_dcoef, dcoef_e, 4 * ne * sizeof(double), hipMemcpyHostToDevice));
+    }
+    c->geo.lam = lambda;
+    c->geo.lam_e = lambda_e ? c->d_lam_e : nullptr;
+    c->geo.dcoef = dcoef_e ? c->d_dcoef : nullptr;
+    HIPCHK(c, launch_fill<double>(c->d_diag, c->N_s, 0.0, st));
+    HIPCHK(c, launch_precond_diag(c->geo, c->t64.tab, c->d_diag, st));
+    HIPCHK(c, launch_precond_invert<double>(c->L, c->d_diag, c->d_pinv64, st));
+    HIPCHK(c, launch_precond_invert<float>(c->L, c->d_diag, c->d_pinv32, st));
+    return SEMCOND_OK;
+}
+
+// Validation shared by create and update: returns an error message or NULL.
+const char* check_coefficients(int64_t ne, unsigned mask, double lambda, const double* lambda_e, const double* dcoef_e) {
+    if (!lambda_e && !dcoef_e && !(std::isfinite(lambda) && lambda >= 0.0)) return "lambda must be finite and >= 0";
+    bool any_d0 = !lambda_e && !dcoef_e && lambda > 0.0;
+    if (lambda_e)
+        for (int64_t e = 0; e < ne; ++e) {
+            if (!(std::isfinite(lambda_e[e]) && lambda_e[e] >= 0.0)) return "lambda_e must be finite and >= 0";
+            any_d0 |= lambda_e[e] > 0.0;
+        }
+    if (dcoef_e)
+        for (int64_t e = 0; e < ne; ++e) {
+            const double* d = dcoef_e + 4 * e;
+            if (!(std::isfinite(d[0]) && d[0] >= 0.0) || !finite_pos(d[1]) || !finite_pos(d[2]) || !finite_pos(d[3]))
+                return "dcoef_e entries invalid";
+            if (!lambda_e) any_d0 |= d[0] > 0.0;
+        }
+    if (!any_d0 && mask == 0) return "lambda = 0 everywhere needs at least one Dirichlet face";
+    return nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -383,6 +429,7 @@ int semcond_destroy(semcond_ctx* c) {
     hipFree(c->ws_vec.ptr);
     hipFree(c->ws_scratch.ptr);
     hipFree(c->ws_state.ptr);
+    hipFree(c->ws_nodal.ptr);
     if (c->h_active) hipHostFree(c->h_active);
     for (hipEvent_t e : c->ev) hipEventDestroy(e);
     delete c;
@@ -423,26 +470,8 @@ int semcond_create(const semcond_mesh* m, void* stream, semcond_ctx** out) {
     }
     if (ne > (int64_t(1) << 26)) return fail(nullptr, SEMCOND_EINVAL, "too many elements (max 2^26)");
     if (m->dirichlet_mask > 63u) return fail(nullptr, SEMCOND_EINVAL, "dirichlet_mask has bits above 5");
-    if (!m->lambda_e && !m->dcoef_e && !(std::isfinite(m->lambda) && m->lambda >= 0.0))
-        return fail(nullptr, SEMCOND_EINVAL, "lambda must be finite and >= 0");
-    bool any_d0 = !m->lambda_e && !m->dcoef_e && m->lambda > 0.0;
-    if (m->lambda_e)
-        for (int64_t e = 0; e < ne; ++e) {
-            if (!(std::isfinite(m->lambda_e[e]) && m->lambda_e[e] >= 0.0))
-                return fail(nullptr, SEMCOND_EINVAL, "lambda_e must be finite and >= 0");
-            any_d0 |= m->lambda_e[e] > 0.0;
-        }
-    if (m->dcoef_e) {
-        any_d0 = false;
-        for (int64_t e = 0; e < ne; ++e) {
-            const double* d = m->dcoef_e + 4 * e;
-            if (!(std::isfinite(d[0]) && d[0] >= 0.0) || !finite_pos(d[1]) || !finite_pos(d[2]) || !finite_pos(d[3]))
-                return fail(nullptr, SEMCOND_EINVAL, "dcoef_e entries invalid");
-            any_d0 |= d[0] > 0.0;
-        }
-    }
-    if (!any_d0 && m->dirichlet_mask == 0)
-        return fail(nullptr, SEMCOND_EINVAL, "lambda = 0 everywhere needs at least one Dirichlet face");
+    if (const char* msg = check_coefficients(ne, m->dirichlet_mask, m->lambda, m->lambda_e, m->dcoef_e))
+        return fail(nullptr, SEMCOND_EINVAL, msg);
 
     semcond_ctx* c = new (std::nothrow) semcond_ctx();
     if (!c) return fail(nullptr, SEMCOND_ENOMEM, "host allocation failed");
@@ -487,28 +516,15 @@ int semcond_create(const semcond_mesh* m, void* stream, semcond_ctx** out) {
     } while (0)
     CHK(hipMalloc(&c->d_widths, nw * sizeof(double)));
     CHK(hipMemcpy(c->d_widths, hw.data(), nw * sizeof(double), hipMemcpyHostToDevice));
-    if (m->lambda_e) {
-        CHK(hipMalloc(&c->d_lam_e, ne * sizeof(double)));
-        CHK(hipMemcpy(c->d_lam_e, m->lambda_e, ne * sizeof(double), hipMemcpyHostToDevice));
-    }
-    if (m->dcoef_e) {
-        CHK(hipMalloc(&c->d_dcoef, 4 * ne * sizeof(double)));
-        CHK(hipMemcpy(c->d_dcoef, m->dcoef_e, 4 * ne * sizeof(double), hipMemcpyHostToDevice));
-    }
     c->geo.L = c->L;
     c->geo.hx = c->d_widths;
     c->geo.hy = c->d_widths + m->n[0];
     c->geo.hz = c->d_widths + m->n[0] + m->n[1];
-    c->geo.lam = m->lambda;
-    c->geo.lam_e = c->d_lam_e;
-    c->geo.dcoef = c->d_dcoef;
     CHK(hipMalloc(&c->d_diag, c->N_s * sizeof(double)));
     CHK(hipMalloc(&c->d_pinv64, c->N_s * sizeof(double)));
     CHK(hipMalloc(&c->d_pinv32, c->N_s * sizeof(float)));
-    CHK(launch_fill<double>(c->d_diag, c->N_s, 0.0, st));
-    CHK(launch_precond_diag(c->geo, c->t64.tab, c->d_diag, st));
-    CHK(launch_precond_invert<double>(c->L, c->d_diag, c->d_pinv64, st));
-    CHK(launch_precond_invert<float>(c->L, c->d_diag, c->d_pinv32, st));
+    rc = set_coefficients(c, m->lambda, m->lambda_e, m->dcoef_e, st);
+    if (rc) return bail(rc);
     CHK(hipStreamSynchronize(st));
 #undef CHK
     *out = c;
@@ -639,6 +655,42 @@ int semcond_nodal_to_skeleton(semcond_ctx* c, const void* nodal, void* skel, int
     return SEMCOND_OK;
 }
 
+int semcond_update_coefficients(semcond_ctx* c, double lambda, const double* lambda_e, const double* dcoef_e,
+                                void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (const char* msg = check_coefficients(c->n_e, c->L.mask, lambda, lambda_e, dcoef_e))
+        return fail(c, SEMCOND_EINVAL, msg);
+    hipStream_t st = S(stream);
+    int rc = set_coefficients(c, lambda, lambda_e, dcoef_e, st);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(st));
+    return SEMCOND_OK;
+}
+
+int semcond_nodal_mass(semcond_ctx* c, void* mass, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!mass) return fail(c, SEMCOND_EINVAL, "mass is NULL");
+    HIPCHK(c, launch_nodal_mass(c->geo, c->t64.tab.w, (double*)mass, c->N, S(stream)));
+    return SEMCOND_OK;
+}
+
+int semcond_mass_apply(semcond_ctx* c, const void* in, void* out, int k, int inverse, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!in || !out) return fail(c, SEMCOND_EINVAL, "NULL pointer");
+    if (k < 1 || k > 256) return fail(c, SEMCOND_EINVAL, "k must be in [1, 256]");
+    HIPCHK(c, launch_mass_apply(c->geo, c->t64.tab.w, (const double*)in, (double*)out, c->N, k, inverse, S(stream)));
+    return SEMCOND_OK;
+}
+
+int semcond_element_grads(semcond_ctx* c, const void* u, const void* a, void* grad, int k, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!u || !a || !grad) return fail(c, SEMCOND_EINVAL, "NULL pointer");
+    if (k < 1 || k > 256) return fail(c, SEMCOND_EINVAL, "k must be in [1, 256]");
+    HIPCHK(c, launch_element_grads(c->geo, c->t64.tab.w, c->t64.K, (const double*)u, (const double*)a, c->N, k,
+                                   (double*)grad, S(stream)));
+    return SEMCOND_OK;
+}
+
 void semcond_solve_opts_default(semcond_solve_opts* o) {
     if (!o) return;
     o->tol = 1e-10;
@@ -650,6 +702,7 @@ void semcond_solve_opts_default(semcond_solve_opts* o) {
     o->skel_out = nullptr;
     o->inner_tol = 1e-5;
     o->max_outer = 30;
+    o->rhs_dual = 0;
 }
 
 int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_solve_opts* opts,
@@ -671,6 +724,13 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
     hipStream_t st = S(stream);
     const int64_t Ns = c->N_s;
     const size_t nv = (size_t)Ns * k;
+    if (o.rhs_dual) {
+        // an assembled right-hand side g equals M_G f' for the nodal values f' = g / M_G
+        rc = grow(c, c->ws_nodal, (size_t)c->N * k * sizeof(double));
+        if (rc) return rc;
+        HIPCHK(c, launch_mass_apply(c->geo, c->t64.tab.w, (const double*)f, (double*)c->ws_nodal.ptr, c->N, k, 1, st));
+        f = c->ws_nodal.ptr;
+    }
     // FP64 vectors b x r p q, then FP32 vectors b x r p q
     rc = grow(c, c->ws_vec, 5 * nv * sizeof(double) + (o.precision == SEMCOND_PREC_F64 ? 0 : 5 * nv * sizeof(float)));
     if (rc) return rc;

@@ -35,7 +35,7 @@ struct Geo {
     const double* hz;
     double lam;
     const double* lam_e;  // nullable, n_e
-    const double* dcoef;  // nullable, n_e x 4
+    const double* dcoef;  // nullable, n_e x 4 (column 0 unused when lam_e is given)
 };
 
 __device__ inline void elem_index(const Layout& L, int64_t e, int* e1, int* e2, int* e3) {
@@ -47,7 +47,8 @@ __device__ inline void elem_index(const Layout& L, int64_t e, int* e1, int* e2, 
 
 __device__ inline void elem_metric(const Geo& g, int64_t e, int e1, int e2, int e3, double d[4]) {
     if (g.dcoef) {
-        d[0] = g.dcoef[4 * e + 0];
+        // metric terms from the table; d_0 = J_e lambda_e when lambda_e is also given
+        d[0] = g.lam_e ? g.hx[e1] * g.hy[e2] * g.hz[e3] / 8.0 * g.lam_e[e] : g.dcoef[4 * e + 0];
         d[1] = g.dcoef[4 * e + 1];
         d[2] = g.dcoef[4 * e + 2];
         d[3] = g.dcoef[4 * e + 3];

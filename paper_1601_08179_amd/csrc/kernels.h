@@ -52,6 +52,15 @@ hipError_t launch_skel_to_nodal(const Layout& L, const double* skel, double* nod
 hipError_t launch_nodal_to_skel(const Layout& L, const double* nodal, double* skel, int64_t N, int k,
                                 hipStream_t st);
 
+// Assembled GLL-lumped nodal mass M_G [N] (w: p+1 GLL weights on the device).
+hipError_t launch_nodal_mass(const Geo& g, const double* w, double* mass, int64_t N, hipStream_t st);
+// out = in * M_G (or in / M_G when inverse), nodal [k][N].
+hipError_t launch_mass_apply(const Geo& g, const double* w, const double* in, double* out, int64_t N, int k,
+                             int inverse, hipStream_t st);
+// grad[e][m] = -sum_r a_e^T A_m u_e (m = 0..3), grad[e][4] = J_e grad[e][0]  ([n_e][5]).
+hipError_t launch_element_grads(const Geo& g, const double* w, const double* K, const double* u, const double* a,
+                                int64_t N, int k, double* grad, hipStream_t st);
+
 template <typename T>
 hipError_t launch_fill(T* x, int64_t n, T val, hipStream_t st);
 template <typename Tin, typename Tout>

@@ -745,3 +745,132 @@ template hipError_t launch_cg_direction<float>(float*, const float*, const float
                                                hipStream_t);
 
 }  // namespace semcond
+
+namespace semcond {
+
+// ---------------------------------------------------------------------------
+// Assembled GLL-lumped mass M_G = R (J_e W(x)W(x)W) R^T, a diagonal (Sec. 3).
+// With J_e = prod_a h_a/2 it factorises per axis: M_G(I) = prod_a m_a(I_a),
+// m_a(I) = sum over the elements e_a containing I of (h_a(e_a)/2) w_{I - e_a p}.
+// ---------------------------------------------------------------------------
+
+__device__ inline double axis_mass(const double* h, int n, int p, const double* w, int I) {
+    const int e = I / p, loc = I - e * p;
+    double m = 0.0;
+    if (e < n) m += 0.5 * h[e] * w[loc];
+    if (loc == 0 && e > 0) m += 0.5 * h[e - 1] * w[p];
+    return m;
+}
+
+__global__ void k_nodal_mass(Geo g, const double* __restrict__ w, double* __restrict__ mass) {
+    const Layout& L = g.L;
+    const int p = L.p;
+    const int64_t N1 = (int64_t)L.n1 * p + 1, N2 = (int64_t)L.n2 * p + 1, N3 = (int64_t)L.n3 * p + 1;
+    const int64_t N = N1 * N2 * N3;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int I1 = (int)(idx % N1);
+        const int64_t r = idx / N1;
+        const int I2 = (int)(r % N2), I3 = (int)(r / N2);
+        mass[idx] = axis_mass(g.hx, L.n1, p, w, I1) * axis_mass(g.hy, L.n2, p, w, I2) * axis_mass(g.hz, L.n3, p, w, I3);
+    }
+}
+
+hipError_t launch_nodal_mass(const Geo& g, const double* w, double* mass, int64_t N, hipStream_t st) {
+    hipLaunchKernelGGL(k_nodal_mass, dim3(grid_for(N, 256)), dim3(256), 0, st, g, w, mass);
+    return hipGetLastError();
+}
+
+// out[r][I] = in[r][I] * M_G(I)  (or / M_G(I) when inverse), nodal [k][N].
+__global__ void k_mass_apply(Geo g, const double* __restrict__ w, const double* __restrict__ in,
+                             double* __restrict__ out, int k, int inverse) {
+    const Layout& L = g.L;
+    const int p = L.p;
+    const int64_t N1 = (int64_t)L.n1 * p + 1, N2 = (int64_t)L.n2 * p + 1, N3 = (int64_t)L.n3 * p + 1;
+    const int64_t N = N1 * N2 * N3;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int I1 = (int)(idx % N1);
+        const int64_t rr = idx / N1;
+        const int I2 = (int)(rr % N2), I3 = (int)(rr / N2);
+        const double m = axis_mass(g.hx, L.n1, p, w, I1) * axis_mass(g.hy, L.n2, p, w, I2) *
+                         axis_mass(g.hz, L.n3, p, w, I3);
+        for (int r = 0; r < k; ++r) {
+            const int64_t o = (int64_t)r * N + idx;
+            out[o] = inverse ? in[o] / m : in[o] * m;
+        }
+    }
+}
+
+hipError_t launch_mass_apply(const Geo& g, const double* w, const double* in, double* out, int64_t N, int k,
+                             int inverse, hipStream_t st) {
+    hipLaunchKernelGGL(k_mass_apply, dim3(grid_for(N, 256)), dim3(256), 0, st, g, w, in, out, k, inverse);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Element gradients of a loss L(u) through H_G u = M_G f (adjoint a = H_G^-1 dL/du):
+//   grad[e][m] = dL/dd_{e,m} = -a_e^T A_m u_e (m = 0..3), grad[e][4] = dL/dlambda_e = J_e grad[e][0],
+//    A_0 = M(x)M(x)M, A_1 = M(x)M(x)K, A_2 = M(x)K(x)M,
+//   A_3 = K(x)M(x)M (Sec. 3, eq. helmholtz_operator), summed over the k right-hand
+//   sides; u and a are nodal [k][N].  One workgroup per element; each thread
+//   handles whole 1D lines of the element.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_element_grads(Geo g, const double* __restrict__ w, const double* __restrict__ K,
+                                                       const double* __restrict__ u, const double* __restrict__ a,
+                                                       int64_t N, int k, double* __restrict__ grad) {
+    const Layout& L = g.L;
+    const int p = L.p, n = p + 1;
+    const int64_t N1 = (int64_t)L.n1 * p + 1, N2 = (int64_t)L.n2 * p + 1;
+    const int64_t e = blockIdx.x;
+    int e1, e2, e3;
+    elem_index(L, e, &e1, &e2, &e3);
+    const int64_t base = (int64_t)e1 * p + N1 * ((int64_t)e2 * p + N2 * (int64_t)e3 * p);
+    const int64_t stride[3] = {1, N1, N1 * N2};  // node stride along i, j, k
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < k; ++r) {
+        const double* ur = u + (int64_t)r * N + base;
+        const double* ar = a + (int64_t)r * N + base;
+        // mass term: sum w_i w_j w_k a u over the element's nodes
+        for (int idx = threadIdx.x; idx < n * n * n; idx += blockDim.x) {
+            const int i = idx % n, j = (idx / n) % n, kk = idx / (n * n);
+            const int64_t off = i + N1 * (j + N2 * (int64_t)kk);
+            acc[0] += w[i] * w[j] * w[kk] * ar[off] * ur[off];
+        }
+        // stiffness terms: lines along axis ax, weighted by w of the two other indices
+        for (int t = threadIdx.x; t < 3 * n * n; t += blockDim.x) {
+            const int ax = t / (n * n), l = t % (n * n), s1 = l / n, s2 = l % n;
+            int64_t lb;
+            double wt;
+            if (ax == 0) { lb = N1 * (s2 + N2 * (int64_t)s1); wt = w[s1] * w[s2]; }        // (k, j) fixed
+            else if (ax == 1) { lb = s2 + N1 * N2 * (int64_t)s1; wt = w[s1] * w[s2]; }     // (k, i) fixed
+            else { lb = s2 + N1 * (int64_t)s1; wt = w[s1] * w[s2]; }                        // (j, i) fixed
+            const int64_t st = stride[ax];
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) {
+                double ku = 0.0;
+                for (int i2 = 0; i2 < n; ++i2) ku += K[i * n + i2] * ur[lb + i2 * st];
+                s += ar[lb + i * st] * ku;
+            }
+            acc[1 + ax] += wt * s;
+        }
+    }
+    __shared__ double red[4][256];
+    for (int m = 0; m < 4; ++m) red[m][threadIdx.x] = acc[m];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int m = 0; m < 4; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) grad[e * 5 + threadIdx.x] = -red[threadIdx.x][0];
+    if (threadIdx.x == 4) grad[e * 5 + 4] = -red[0][0] * elem_jacobian(g, e1, e2, e3);  // d d0 / d lambda_e = J_e
+}
+
+hipError_t launch_element_grads(const Geo& g, const double* w, const double* K, const double* u, const double* a,
+                                int64_t N, int k, double* grad, hipStream_t st) {
+    const int64_t ne = (int64_t)g.L.n1 * g.L.n2 * g.L.n3;
+    hipLaunchKernelGGL(k_element_grads, dim3((unsigned)ne), dim3(256), 0, st, g, w, K, u, a, N, k, grad);
+    return hipGetLastError();
+}
+
+}  // namespace semcond

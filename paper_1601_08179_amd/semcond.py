@@ -33,7 +33,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("recover_interior", ctypes.c_int),
                 ("x0", ctypes.c_void_p), ("skel_out", ctypes.c_void_p),
-                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int)]
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("rhs_dual", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -63,6 +63,13 @@ _SIGS = {
     "semcond_nodal_to_skeleton": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_int, ctypes.c_void_p]),
     "semcond_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
+    "semcond_update_coefficients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, _c_double_p, _c_double_p,
+                                                   ctypes.c_void_p]),
+    "semcond_nodal_mass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "semcond_mass_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_void_p]),
+    "semcond_element_grads": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int, ctypes.c_void_p]),
     "semcond_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "semcond_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int64)]),
@@ -298,9 +305,46 @@ class Context:
                                               _stream(stream)), self._h)
         return out
 
+    def update_coefficients(self, lam=None, lam_e=None, dcoef=None, stream=None):
+        """Replace lambda / lambda_e / metric table and rebuild the preconditioner."""
+        self._lam_e = None if lam_e is None else np.ascontiguousarray(lam_e, dtype=np.float64).reshape(-1)
+        self._dcoef = None if dcoef is None else np.ascontiguousarray(dcoef, dtype=np.float64).reshape(-1)
+        le = self._lam_e.ctypes.data_as(_c_double_p) if self._lam_e is not None else None
+        dc = self._dcoef.ctypes.data_as(_c_double_p) if self._dcoef is not None else None
+        _check(_lib.semcond_update_coefficients(self._h, 0.0 if lam is None else float(lam), le, dc,
+                                                _stream(stream)), self._h)
+
+    def nodal_mass(self, stream=None):
+        import torch
+        out = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(_lib.semcond_nodal_mass(self._h, _dev(out, "out"), _stream(stream)), self._h)
+        return out
+
+    def mass_apply(self, x, inverse=False, out=None, stream=None):
+        import torch
+        k = self._k_nodal(x, "x")
+        if x.dtype != torch.float64:
+            raise TypeError("x must be float64")
+        if out is None:
+            out = torch.empty_like(x)
+        _check(_lib.semcond_mass_apply(self._h, _dev(x, "x"), _dev(out, "out"), k, 1 if inverse else 0,
+                                       _stream(stream)), self._h)
+        return out
+
+    def element_grads(self, u, a, stream=None):
+        """[n_e, 5]: dL/dd_{e,0..3} and dL/dlambda_e for adjoint a of nodal solutions u."""
+        import torch
+        k = self._k_nodal(u, "u")
+        if a.shape != u.shape:
+            raise ValueError("a must match u")
+        out = torch.empty((self.n_e, 5), dtype=torch.float64, device=u.device)
+        _check(_lib.semcond_element_grads(self._h, _dev(u, "u"), _dev(a, "a"), _dev(out, "out"), k,
+                                          _stream(stream)), self._h)
+        return out
+
     def solve(self, f, out=None, tol=1e-10, max_iter=20000, precision=PREC_F64, check_every=8,
               recover_interior=True, x0=None, skel_out=None, inner_tol=1e-5, max_outer=30,
-              stream=None, raise_on_notconv=True):
+              rhs_dual=False, stream=None, raise_on_notconv=True):
         """Solve for nodal right-hand sides f (k, N) or (N,), FP64.  Returns (u, info)."""
         import torch
         k = self._k_nodal(f, "f")
@@ -319,6 +363,7 @@ class Context:
         o.skel_out = None if skel_out is None else _dev(skel_out, "skel_out").value
         o.inner_tol = inner_tol
         o.max_outer = max_outer
+        o.rhs_dual = 1 if rhs_dual else 0
         info = (SolveInfo * k)()
         allow = (OK, ENOTCONV) if not raise_on_notconv else (OK,)
         _check(_lib.semcond_solve(self._h, _dev(f, "f"), _dev(out, "out"), k, ctypes.byref(o), info,
