@@ -11,9 +11,12 @@ recovery of the interior (all on the GPU; inputs resident in HBM).
 
 value = N * iterations / solve time  [GDOF/s]: total unknowns times CG
 iterations per second, i.e. the reciprocal of the time per DOF and iteration.
-The line also reports the apply kernel's own rate and its HBM roofline
-fraction (kernel durations from HIP events recorded by the library on its
-launch stream), and the FP64 CPU oracle's apply rate on this workload.
+The CG runs as one persistent cooperative launch per solve; its HBM roofline
+uses 13 x 8 x N_s algorithmic bytes per iteration and the kernel time from HIP
+events the library records on the launch stream.  The line also reports the
+same solve with one launch per CG step, the mixed-precision solve, the
+standalone apply kernel's rate and roofline, and the FP64 CPU oracle's apply
+rate on this workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -99,7 +102,7 @@ def main():
         ctx.solve(ft, out=u, tol=args.tol)
     torch.cuda.synchronize()
 
-    # ---- timed region: K full solves --------------------------------------------
+    # ---- timed region: K full solves (persistent cooperative CG launch) ----------
     ctx.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -109,39 +112,50 @@ def main():
         iters += info[0]["iters"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    apply_ms, launches = ctx.profile_read()
+    cg_ms, cg_launches, cg_iters = ctx.profile_read(semcond.KERNEL_PCG)
     ctx.profile_enable(False)
     solve_s = (t1 - t0) / args.steps
     it_per_solve = iters / args.steps
     value = N * iters / (t1 - t0) / 1e9
-    kern_s = apply_ms / 1e3 / max(launches, 1)
 
-    # ---- same solve with FP32 inner CG + FP64 iterative refinement ---------------
-    mixed_steps = max(3, args.steps // 4)
+    # ---- the same solves with one launch per CG step --------------------------------
+    side_steps = max(3, args.steps // 4)
+    ctx.solve(ft, out=u, tol=args.tol, persistent=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(side_steps):
+        ctx.solve(ft, out=u, tol=args.tol, persistent=False)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t2) / side_steps
+
+    # ---- FP32 inner CG + FP64 iterative refinement ----------------------------------
     ctx.solve(ft, out=u, tol=args.tol, precision=semcond.PREC_MIXED_IR, inner_tol=1e-4)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    for _ in range(mixed_steps):
+    for _ in range(side_steps):
         _, minfo = ctx.solve(ft, out=u, tol=args.tol, precision=semcond.PREC_MIXED_IR, inner_tol=1e-4)
     torch.cuda.synchronize()
-    mixed_s = (time.perf_counter() - t2) / mixed_steps
+    mixed_s = (time.perf_counter() - t2) / side_steps
 
-    # ---- apply alone (transformed basis, back-to-back) ----------------------------
+    # ---- apply alone (transformed basis, back-to-back), kernel time from events ------
     xs = torch.randn(Ns, dtype=torch.float64, device="cuda")
     ys = torch.empty_like(xs)
     for _ in range(10):
         ctx.apply(xs, out=ys)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    ctx.profile_enable(True)
     for _ in range(args.apply_reps):
         ctx.apply(xs, out=ys)
-    e1.record()
-    torch.cuda.synchronize()
-    apply_call_s = e0.elapsed_time(e1) / 1e3 / args.apply_reps
+    ap_ms, ap_launches, _ = ctx.profile_read(semcond.KERNEL_APPLY)
+    ctx.profile_enable(False)
+    kern_s = ap_ms / 1e3 / max(ap_launches, 1)
 
-    bytes_per_launch = 2 * 8 * Ns  # read u~ and write v~ once, FP64, k = 1
-    achieved = bytes_per_launch / kern_s / 1e9
+    # algorithmic FP64 bytes (k = 1): apply reads p, writes q (2 N_s); update reads
+    # x, p, r, q, P^-1 and writes x, r (7 N_s); direction reads r, P^-1, p, writes p (4 N_s)
+    cg_bytes = 13 * 8 * Ns * cg_iters
+    cg_achieved = cg_bytes / (cg_ms / 1e3) / 1e9
+    apply_bytes = 2 * 8 * Ns
+    apply_achieved = apply_bytes / kern_s / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -161,16 +175,19 @@ def main():
                    "parallelism": "single GPU"},
         "iterations": it_per_solve,
         "ns_per_dof_iter": solve_s / (N * it_per_solve) * 1e9,
+        "stepwise": {"ms_per_solve": step_s * 1e3, "persistent_speedup": step_s / solve_s},
         "mixed_ir": {"ms_per_solve": mixed_s * 1e3, "speedup_vs_fp64": solve_s / mixed_s,
                      "inner_iterations": minfo[0]["iters"], "outer_steps": minfo[0]["outer"],
                      "rel_res": minfo[0]["rel_res"]},
-        "apply_kernel_us": kern_s * 1e6,
-        "apply_kernel_gdof_s": N / kern_s / 1e9,
-        "apply_call_us": apply_call_s * 1e6,
-        "apply_call_gdof_s": N / apply_call_s / 1e9,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_apply_tpt<double,7>", "bytes_per_launch": bytes_per_launch},
+        "roofline": {"bound": "hbm", "achieved": cg_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": cg_achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_pcg_persistent<double,7,4>",
+                     "bytes_per_launch": cg_bytes / max(cg_launches, 1),
+                     "kernel_ms_per_launch": cg_ms / max(cg_launches, 1)},
+        "apply_roofline": {"bound": "hbm", "achieved": apply_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": apply_achieved / HBM_PEAK_GBS, "kernel": "k_apply_tpt<double,7>",
+                           "kernel_us": kern_s * 1e6, "gdof_s": N / kern_s / 1e9,
+                           "bytes_per_launch": apply_bytes},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wmesh, args.cpu_seconds)

@@ -118,6 +118,11 @@ typedef struct {
     int rhs_dual;           /* 0: f are nodal values, F = M_G f (default); 1: f is the   */
                             /* assembled discrete right-hand side itself (R F_L), as in  */
                             /* an adjoint solve H_G a = dL/du                             */
+    int persistent;         /* 1: every CG (inner CG for MIXED_IR) runs as one persistent */
+                            /* cooperative launch with the autotuned grid; 0: one launch  */
+                            /* per step with host convergence polls.  Default 1; falls   */
+                            /* back to 0 where no persistent kernel exists (n_I > 15, or  */
+                            /* k not a power of two up to 32)                            */
 } semcond_solve_opts;
 
 /* Per right-hand-side result of semcond_solve (host array of k entries). */
@@ -264,14 +269,30 @@ int semcond_element_grads(semcond_ctx* ctx, const void* u_nodal, const void* a_n
                           int k, void* stream);
 
 /*
+ * Autotuner of the persistent CG launch (k right-hand sides of scalar type
+ * dtype): times the candidate grids (workgroup count G, element groups per
+ * workgroup S) for a few CG iterations on this context's problem and keeps the
+ * fastest for later solves.  When cache_path is non-NULL the choice is read
+ * from / appended to that text file (one line "p n1 n2 n3 k dtype S G").
+ * S_out, G_out (nullable) receive the choice.  Returns EINVAL when no
+ * persistent kernel exists for (p, k).  Synchronises the device.
+ */
+int semcond_autotune(semcond_ctx* ctx, int k, int dtype, const char* cache_path, int* S_out, int* G_out);
+
+/*
  * Kernel tracing.  While enabled, every launch of the condensed-apply kernel
- * (inside semcond_apply and semcond_solve) is bracketed by two HIP events
+ * (SEMCOND_KERNEL_APPLY: inside semcond_apply and the stepwise CG) and of the
+ * persistent CG kernel (SEMCOND_KERNEL_PCG) is bracketed by two HIP events
  * recorded on the launch stream.  semcond_profile_enable resets the counters;
  * semcond_profile_read synchronises the recorded events and returns the summed
- * kernel time in milliseconds and the number of launches since the reset.
+ * kernel time in milliseconds and the number of launches of `kernel` since the
+ * reset, and for SEMCOND_KERNEL_PCG the CG iterations those launches ran
+ * (summed over right-hand sides' maximum per launch) in *iters (nullable).
  */
+#define SEMCOND_KERNEL_APPLY 0
+#define SEMCOND_KERNEL_PCG   1
 int semcond_profile_enable(semcond_ctx* ctx, int enable);
-int semcond_profile_read(semcond_ctx* ctx, double* apply_ms, int64_t* apply_launches);
+int semcond_profile_read(semcond_ctx* ctx, int kernel, double* ms, int64_t* launches, int64_t* iters);
 
 #ifdef __cplusplus
 }

@@ -12,7 +12,12 @@
 #include "../../include/semcond.h"
 #include "kernels.h"
 #include "layout.h"
+#include "pcg_persistent.h"
 #include "tables.h"
+
+#include <chrono>
+#include <cstdio>
+#include <map>
 
 using namespace semcond;
 
@@ -57,14 +62,19 @@ struct semcond_ctx {
     Buffer ws_scratch;  // element cubes for large p
     Buffer ws_state;    // CG scalars (device)
     Buffer ws_nodal;    // nodal right-hand sides of dual solves
+    Buffer ws_persist;  // partials and barrier words of the persistent CG
     int* h_active = nullptr;  // pinned host copy of CG activity flags
     int h_active_cap = 0;
-    // tracing of the apply kernel
+    // persistent CG launch configuration per (k, dtype): (S, G)
+    std::map<std::pair<int, int>, std::pair<int, int>> tuned;
+    // tracing: event pairs around kernel launches, with the kernel id
     bool prof = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    std::vector<int> ev_kind;    // kernel id per pair
     size_t ev_used = 0;          // events recorded since the last read
-    double prof_ms = 0.0;
-    int64_t prof_launches = 0;
+    double prof_ms[2] = {0.0, 0.0};
+    int64_t prof_launches[2] = {0, 0};
+    int64_t prof_iters = 0;
 };
 
 namespace {
@@ -167,6 +177,27 @@ const double* pinv<double>(semcond_ctx* c) { return c->d_pinv64; }
 template <>
 const float* pinv<float>(semcond_ctx* c) { return c->d_pinv32; }
 
+// Start / end event of a traced launch of kernel `kind` on stream st.
+int profile_begin(semcond_ctx* c, int kind, hipStream_t st) {
+    if (c->ev_used + 2 > c->ev.size()) {
+        for (int i = 0; i < 256; ++i) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
+        c->ev_kind.resize(c->ev.size() / 2);
+    }
+    c->ev_kind[c->ev_used / 2] = kind;
+    HIPCHK(c, hipEventRecord(c->ev[c->ev_used], st));
+    return SEMCOND_OK;
+}
+
+int profile_end(semcond_ctx* c, hipStream_t st) {
+    HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], st));
+    c->ev_used += 2;
+    return SEMCOND_OK;
+}
+
 template <typename T>
 hipError_t launch_apply(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t st) {
     return launch_apply_tpt<T>(a, n_elem, st);
@@ -186,18 +217,10 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, double* energy, h
     a.energy = energy;
     a.e_begin = 0;
     if (c->prof) {
-        if (c->ev_used + 2 > c->ev.size()) {
-            for (int i = 0; i < 256; ++i) {
-                hipEvent_t e;
-                HIPCHK(c, hipEventCreate(&e));
-                c->ev.push_back(e);
-            }
-        }
-        HIPCHK(c, hipEventRecord(c->ev[c->ev_used], st));
+        int rc = profile_begin(c, SEMCOND_KERNEL_APPLY, st);
+        if (rc) return rc;
         HIPCHK(c, launch_apply<T>(a, c->n_e, st));
-        HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], st));
-        c->ev_used += 2;
-        return SEMCOND_OK;
+        return profile_end(c, st);
     }
     HIPCHK(c, launch_apply<T>(a, c->n_e, st));
     return SEMCOND_OK;
@@ -209,8 +232,9 @@ int profile_flush(semcond_ctx* c) {
         HIPCHK(c, hipEventSynchronize(c->ev[i + 1]));
         float ms = 0.f;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
-        c->prof_ms += ms;
-        c->prof_launches += 1;
+        const int kind = c->ev_kind[i / 2];
+        c->prof_ms[kind] += ms;
+        c->prof_launches[kind] += 1;
     }
     c->ev_used = 0;
     return SEMCOND_OK;
@@ -394,6 +418,174 @@ const char* check_coefficients(int64_t ne, unsigned mask, double lambda, const d
     return nullptr;
 }
 
+
+template <typename T>
+constexpr int dtype_of() { return sizeof(T) == 8 ? SEMCOND_F64 : SEMCOND_F32; }
+
+// Default persistent configuration: the largest element-group count that k
+// divides, and as many workgroups as are co-resident, but no more than needed
+// to give every element group one element.
+bool persist_default(semcond_ctx* c, int k, int dtype, int* S, int* G) {
+    const int NI = c->L.NI;
+    int cand[2] = {NI * NI <= 64 ? 4 : (NI * NI <= 128 ? 2 : 1), 1};
+    for (int S0 : cand) {
+        if (!persist_supported(NI, S0, k)) continue;
+        const int mg = dtype == SEMCOND_F64 ? persist_max_grid<double>(NI, S0) : persist_max_grid<float>(NI, S0);
+        if (mg <= 0) continue;
+        int64_t need = (c->n_e + S0 - 1) / S0;
+        *S = S0;
+        *G = (int)std::min<int64_t>(mg, need);
+        return true;
+    }
+    return false;
+}
+
+template <typename T>
+int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, int max_iter, CgWork& w, int S, int G,
+                   hipStream_t st) {
+    const size_t need = 3 * (size_t)G * k * sizeof(double) + 512;
+    int rc = grow(c, c->ws_persist, need);
+    if (rc) return rc;
+    double* part = (double*)c->ws_persist.ptr;
+    unsigned* bar = (unsigned*)((char*)c->ws_persist.ptr + 3 * (size_t)G * k * sizeof(double));
+    // barrier words and error flag start at zero (bit pattern of 0.0f)
+    HIPCHK(c, launch_fill<float>((float*)bar, 128, 0.0f, st));
+    PcgArgs<T> P;
+    P.A.g = c->geo;
+    P.A.tab = tabs<T>(c);
+    P.A.u = p;
+    P.A.v = q;
+    P.A.k = k;
+    P.A.energy = nullptr;
+    P.A.e_begin = 0;
+    P.x = x;
+    P.r = r;
+    P.p = p;
+    P.q = q;
+    P.pinv = pinv<T>(c);
+    P.Ns = c->N_s;
+    P.n_e = c->n_e;
+    P.k = k;
+    P.part = part;
+    P.rho = w.s.rho;
+    P.rr = w.s.rr;
+    P.bb = w.s.bb;
+    P.active = w.s.active;
+    P.iters = w.s.iters;
+    P.status = w.s.status;
+    P.tol2 = tol * tol;
+    P.max_iter = max_iter;
+    P.bar = bar;
+    P.err = (int*)(bar + 64);
+    P.spin_limit = 1u << 24;
+    std::vector<int> it0;
+    if (c->prof) {
+        it0.resize(k);
+        HIPCHK(c, hipMemcpyAsync(it0.data(), w.s.iters, k * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        rc = profile_begin(c, SEMCOND_KERNEL_PCG, st);
+        if (rc) return rc;
+    }
+    HIPCHK(c, launch_pcg_persistent<T>(P, c->L.NI, S, G, st));
+    if (c->prof) {
+        rc = profile_end(c, st);
+        if (rc) return rc;
+    }
+    int herr = 0;
+    HIPCHK(c, hipMemcpyAsync(&herr, P.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (herr) return fail(c, SEMCOND_EDEVICE, "persistent CG: grid barrier wait exceeded its bound");
+    if (c->prof) {
+        std::vector<int> it1(k);
+        HIPCHK(c, hipMemcpy(it1.data(), w.s.iters, k * sizeof(int), hipMemcpyDeviceToHost));
+        int mx = 0;
+        for (int i = 0; i < k; ++i) mx = std::max(mx, it1[i] - it0[i]);
+        c->prof_iters += mx;
+    }
+    return SEMCOND_OK;
+}
+
+// CG on the transformed condensed system: persistent launch when requested and
+// available, else one launch per step.
+template <typename T>
+int run_cg_any(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol, int max_iter, int check_every,
+               bool x0_given, bool persistent, CgWork& w, hipStream_t st) {
+    int S = 0, G = 0;
+    bool use = false;
+    if (persistent && persist_supported(c->L.NI, 1, k)) {
+        auto it = c->tuned.find({k, dtype_of<T>()});
+        if (it != c->tuned.end()) {
+            S = it->second.first;
+            G = it->second.second;
+            use = true;
+        } else {
+            use = persist_default(c, k, dtype_of<T>(), &S, &G);
+        }
+    }
+    if (!use) return run_cg<T>(c, b, x, r, p, q, k, tol, max_iter, check_every, x0_given, w, st);
+    const int64_t Ns = c->N_s;
+    const double tol2 = tol * tol;
+    HIPCHK(c, hipMemcpyAsync(w.s.tol2, &tol2, sizeof(double), hipMemcpyHostToDevice, st));
+    if (x0_given) {
+        int rc = apply_transformed<T>(c, x, q, k, nullptr, st);
+        if (rc) return rc;
+        HIPCHK(c, launch_cg_init<T>(b, q, pinv<T>(c), r, p, Ns, k, w.partials, st));
+    } else {
+        HIPCHK(c, launch_fill<T>(x, Ns * k, (T)0, st));
+        HIPCHK(c, launch_fill<T>(q, Ns * k, (T)0, st));
+        HIPCHK(c, launch_cg_init<T>(b, (T*)nullptr, pinv<T>(c), r, p, Ns, k, w.partials, st));
+    }
+    HIPCHK(c, launch_cg_reduce(w.partials, kVecBlocks, 3, k, w.s, RED_INIT, st));
+    return run_persistent<T>(c, x, r, p, q, k, tol, max_iter, w, S, G, st);
+}
+
+// Time the candidate persistent configurations for `iters` CG iterations on
+// the condensed RHS b (tolerance 0, so every RHS stays active).
+template <typename T>
+int autotune_persistent(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, CgWork& w, hipStream_t st,
+                        int* bestS, int* bestG) {
+    const int NI = c->L.NI;
+    const int smax = NI * NI <= 64 ? 4 : (NI * NI <= 128 ? 2 : 1);
+    std::vector<std::pair<int, int>> cands;
+    for (int S : {smax, 1}) {
+        if (!persist_supported(NI, S, k)) continue;
+        const int mg = persist_max_grid<T>(NI, S);
+        const int64_t need = (c->n_e + S - 1) / S;
+        for (int div : {1, 2, 4, 8}) {
+            int G = (int)std::min<int64_t>(mg / div, need);
+            if (G < 1) continue;
+            bool dup = false;
+            for (auto& cc : cands) dup |= cc.first == S && cc.second == G;
+            if (!dup) cands.push_back({S, G});
+        }
+        if (S == 1 && smax == 1) break;
+    }
+    if (cands.empty()) return fail(c, SEMCOND_EINVAL, "no persistent kernel for this degree and k");
+    const int iters = 12;
+    double best = 1e300;
+    for (auto& cc : cands) {
+        double t_best = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIPCHK(c, launch_fill<T>(x, c->N_s * k, (T)0, st));
+            HIPCHK(c, launch_fill<T>(q, c->N_s * k, (T)0, st));
+            HIPCHK(c, launch_cg_init<T>(b, (T*)nullptr, pinv<T>(c), r, p, c->N_s, k, w.partials, st));
+            HIPCHK(c, launch_cg_reduce(w.partials, kVecBlocks, 3, k, w.s, RED_INIT, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            auto t0 = std::chrono::steady_clock::now();
+            int rc = run_persistent<T>(c, x, r, p, q, k, 0.0, iters, w, cc.first, cc.second, st);
+            if (rc) return rc;
+            const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            t_best = std::min(t_best, dt);
+        }
+        if (t_best < best) {
+            best = t_best;
+            *bestS = cc.first;
+            *bestG = cc.second;
+        }
+    }
+    return SEMCOND_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -430,6 +622,7 @@ int semcond_destroy(semcond_ctx* c) {
     hipFree(c->ws_scratch.ptr);
     hipFree(c->ws_state.ptr);
     hipFree(c->ws_nodal.ptr);
+    hipFree(c->ws_persist.ptr);
     if (c->h_active) hipHostFree(c->h_active);
     for (hipEvent_t e : c->ev) hipEventDestroy(e);
     delete c;
@@ -441,17 +634,20 @@ int semcond_profile_enable(semcond_ctx* c, int enable) {
     int rc = profile_flush(c);
     if (rc) return rc;
     c->prof = enable != 0;
-    c->prof_ms = 0.0;
-    c->prof_launches = 0;
+    c->prof_ms[0] = c->prof_ms[1] = 0.0;
+    c->prof_launches[0] = c->prof_launches[1] = 0;
+    c->prof_iters = 0;
     return SEMCOND_OK;
 }
 
-int semcond_profile_read(semcond_ctx* c, double* apply_ms, int64_t* apply_launches) {
+int semcond_profile_read(semcond_ctx* c, int kernel, double* ms, int64_t* launches, int64_t* iters) {
     if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (kernel != SEMCOND_KERNEL_APPLY && kernel != SEMCOND_KERNEL_PCG) return fail(c, SEMCOND_EINVAL, "bad kernel id");
     int rc = profile_flush(c);
     if (rc) return rc;
-    if (apply_ms) *apply_ms = c->prof_ms;
-    if (apply_launches) *apply_launches = c->prof_launches;
+    if (ms) *ms = c->prof_ms[kernel];
+    if (launches) *launches = c->prof_launches[kernel];
+    if (iters) *iters = kernel == SEMCOND_KERNEL_PCG ? c->prof_iters : 0;
     return SEMCOND_OK;
 }
 
@@ -674,6 +870,67 @@ int semcond_nodal_mass(semcond_ctx* c, void* mass, void* stream) {
     return SEMCOND_OK;
 }
 
+int semcond_autotune(semcond_ctx* c, int k, int dtype, const char* cache_path, int* S_out, int* G_out) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    int rc = check_k(c, k);
+    if (!rc) rc = check_dtype(c, dtype);
+    if (rc) return rc;
+    if (!persist_supported(c->L.NI, 1, k)) return fail(c, SEMCOND_EINVAL, "no persistent kernel for this degree and k");
+    char key[160];
+    std::snprintf(key, sizeof key, "%d %d %d %d %d %d", c->p, c->n[0], c->n[1], c->n[2], k, dtype);
+    int S = 0, G = 0;
+    bool found = false;
+    if (cache_path) {
+        if (FILE* fh = std::fopen(cache_path, "r")) {
+            char line[256];
+            while (std::fgets(line, sizeof line, fh)) {
+                int a[6], s0, g0;
+                if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &s0, &g0) == 8) {
+                    char k2[160];
+                    std::snprintf(k2, sizeof k2, "%d %d %d %d %d %d", a[0], a[1], a[2], a[3], a[4], a[5]);
+                    if (std::strcmp(k2, key) == 0 && persist_supported(c->L.NI, s0, k) && g0 > 0) {
+                        S = s0;
+                        G = g0;
+                        found = true;
+                    }
+                }
+            }
+            std::fclose(fh);
+        }
+    }
+    hipStream_t st = nullptr;
+    if (!found) {
+        // tune on a synthetic right-hand side in the workspace: b = 1 on every slot
+        const size_t nv = (size_t)c->N_s * k;
+        const size_t es = dtype == SEMCOND_F64 ? sizeof(double) : sizeof(float);
+        rc = grow(c, c->ws_vec, 5 * nv * es);
+        if (rc) return rc;
+        CgWork w;
+        rc = cg_state(c, k, 0, &w);
+        if (rc) return rc;
+        if (dtype == SEMCOND_F64) {
+            double* b = (double*)c->ws_vec.ptr;
+            HIPCHK(c, launch_fill<double>(b, nv, 1.0, st));
+            rc = autotune_persistent<double>(c, b, b + nv, b + 2 * nv, b + 3 * nv, b + 4 * nv, k, w, st, &S, &G);
+        } else {
+            float* b = (float*)c->ws_vec.ptr;
+            HIPCHK(c, launch_fill<float>(b, nv, 1.0f, st));
+            rc = autotune_persistent<float>(c, b, b + nv, b + 2 * nv, b + 3 * nv, b + 4 * nv, k, w, st, &S, &G);
+        }
+        if (rc) return rc;
+        if (cache_path) {
+            if (FILE* fh = std::fopen(cache_path, "a")) {
+                std::fprintf(fh, "%s %d %d\n", key, S, G);
+                std::fclose(fh);
+            }
+        }
+    }
+    c->tuned[{k, dtype}] = {S, G};
+    if (S_out) *S_out = S;
+    if (G_out) *G_out = G;
+    return SEMCOND_OK;
+}
+
 int semcond_mass_apply(semcond_ctx* c, const void* in, void* out, int k, int inverse, void* stream) {
     if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
     if (!in || !out) return fail(c, SEMCOND_EINVAL, "NULL pointer");
@@ -703,6 +960,7 @@ void semcond_solve_opts_default(semcond_solve_opts* o) {
     o->inner_tol = 1e-5;
     o->max_outer = 30;
     o->rhs_dual = 0;
+    o->persistent = 1;
 }
 
 int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_solve_opts* opts,
@@ -755,7 +1013,8 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
     std::vector<double> relres(k, 0.0);
     CgHost h;
     if (o.precision == SEMCOND_PREC_F64) {
-        rc = run_cg<double>(c, b, x, r, p, q, k, o.tol, o.max_iter, o.check_every, o.x0 != nullptr, w, st);
+        rc = run_cg_any<double>(c, b, x, r, p, q, k, o.tol, o.max_iter, o.check_every, o.x0 != nullptr,
+                                o.persistent != 0, w, st);
         if (rc) return rc;
         rc = read_state(c, w, k, &h, st);
         if (rc) return rc;
@@ -768,7 +1027,8 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
         // FP32 operator and vectors, FP64 dot products; no refinement
         HIPCHK(c, (launch_convert<double, float>(b, b32, nv, st)));
         if (o.x0) HIPCHK(c, (launch_convert<double, float>(x, x32, nv, st)));
-        rc = run_cg<float>(c, b32, x32, r32, p32, q32, k, o.tol, o.max_iter, o.check_every, o.x0 != nullptr, w, st);
+        rc = run_cg_any<float>(c, b32, x32, r32, p32, q32, k, o.tol, o.max_iter, o.check_every, o.x0 != nullptr,
+                               o.persistent != 0, w, st);
         if (rc) return rc;
         HIPCHK(c, (launch_convert<float, double>(x32, x, nv, st)));
         rc = read_state(c, w, k, &h, st);
@@ -829,7 +1089,8 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
                 break;
             }
             HIPCHK(c, launch_convert_masked(r, r32, nv, k, wo.s.active, st));
-            rc = run_cg<float>(c, r32, x32, b32, p32, q32, k, o.inner_tol, o.max_iter, o.check_every, false, w, st);
+            rc = run_cg_any<float>(c, r32, x32, b32, p32, q32, k, o.inner_tol, o.max_iter, o.check_every, false,
+                                   o.persistent != 0, w, st);
             if (rc) return rc;
             CgHost hi;
             rc = read_state(c, w, k, &hi, st);

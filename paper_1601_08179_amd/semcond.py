@@ -19,6 +19,7 @@ F64, F32 = 0, 1
 PHYSICAL, TRANSFORMED = 0, 1
 COEF_TO_TRANSFORMED, COEF_TO_PHYSICAL, DUAL_TO_TRANSFORMED, DUAL_TO_PHYSICAL = 0, 1, 2, 3
 PREC_F64, PREC_F32, PREC_MIXED_IR = 0, 1, 2
+KERNEL_APPLY, KERNEL_PCG = 0, 1
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -33,7 +34,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("recover_interior", ctypes.c_int),
                 ("x0", ctypes.c_void_p), ("skel_out", ctypes.c_void_p),
-                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("rhs_dual", ctypes.c_int)]
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("rhs_dual", ctypes.c_int),
+                ("persistent", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -70,9 +72,11 @@ _SIGS = {
                                           ctypes.c_int, ctypes.c_void_p]),
     "semcond_element_grads": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int, ctypes.c_void_p]),
+    "semcond_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_char_p,
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "semcond_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
-    "semcond_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
-                                            ctypes.POINTER(ctypes.c_int64)]),
+    "semcond_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "semcond_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                      ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), ctypes.c_void_p]),
 }
@@ -217,12 +221,14 @@ class Context:
     def profile_enable(self, enable=True):
         _check(_lib.semcond_profile_enable(self._h, 1 if enable else 0), self._h)
 
-    def profile_read(self):
-        """(summed apply-kernel milliseconds, launches) since the last enable."""
+    def profile_read(self, kernel=KERNEL_APPLY):
+        """(summed kernel milliseconds, launches, CG iterations) since the last enable."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
-        _check(_lib.semcond_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)), self._h)
-        return ms.value, n.value
+        it = ctypes.c_int64()
+        _check(_lib.semcond_profile_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n),
+                                         ctypes.byref(it)), self._h)
+        return ms.value, n.value, it.value
 
     # -- operations --------------------------------------------------------------
     def _k_skel(self, t, name):
@@ -314,6 +320,16 @@ class Context:
         _check(_lib.semcond_update_coefficients(self._h, 0.0 if lam is None else float(lam), le, dc,
                                                 _stream(stream)), self._h)
 
+    def autotune(self, k=1, dtype=None, cache_path=None):
+        """Pick the persistent CG launch (element groups S, grid G) by timing; returns (S, G)."""
+        import torch
+        code = F32 if dtype == torch.float32 else F64
+        S = ctypes.c_int()
+        G = ctypes.c_int()
+        _check(_lib.semcond_autotune(self._h, int(k), code, None if cache_path is None else cache_path.encode(),
+                                     ctypes.byref(S), ctypes.byref(G)), self._h)
+        return S.value, G.value
+
     def nodal_mass(self, stream=None):
         import torch
         out = torch.empty(self.N, dtype=torch.float64, device="cuda")
@@ -344,7 +360,7 @@ class Context:
 
     def solve(self, f, out=None, tol=1e-10, max_iter=20000, precision=PREC_F64, check_every=8,
               recover_interior=True, x0=None, skel_out=None, inner_tol=1e-5, max_outer=30,
-              rhs_dual=False, stream=None, raise_on_notconv=True):
+              rhs_dual=False, persistent=True, stream=None, raise_on_notconv=True):
         """Solve for nodal right-hand sides f (k, N) or (N,), FP64.  Returns (u, info)."""
         import torch
         k = self._k_nodal(f, "f")
@@ -364,6 +380,7 @@ class Context:
         o.inner_tol = inner_tol
         o.max_outer = max_outer
         o.rhs_dual = 1 if rhs_dual else 0
+        o.persistent = 1 if persistent else 0
         info = (SolveInfo * k)()
         allow = (OK, ENOTCONV) if not raise_on_notconv else (OK,)
         _check(_lib.semcond_solve(self._h, _dev(f, "f"), _dev(out, "out"), k, ctypes.byref(o), info,
