@@ -11,12 +11,13 @@ recovery of the interior (all on the GPU; inputs resident in HBM).
 
 value = N * iterations / solve time  [GDOF/s]: total unknowns times CG
 iterations per second, i.e. the reciprocal of the time per DOF and iteration.
-The CG runs as one persistent cooperative launch per solve; its HBM roofline
-uses 13 x 8 x N_s algorithmic bytes per iteration and the kernel time from HIP
-events the library records on the launch stream.  The line also reports the
-same solve with one launch per CG step, the mixed-precision solve, the
-standalone apply kernel's rate and roofline, and the FP64 CPU oracle's apply
-rate on this workload.
+The CG launch (one launch per step, or one persistent cooperative launch) is
+the one the library's autotuner picks for this problem.  The roofline is that
+of the dominant kernel of the timed solves, from its algorithmic bytes and the
+kernel time from HIP events the library records on the launch stream.  The
+line also reports the solve with each launch kind forced, the mixed-precision
+solve, the standalone apply kernel's rate and roofline, and the FP64 CPU
+oracle's apply rate on this workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -98,12 +99,13 @@ def main():
     u = torch.zeros_like(ft)
     N, Ns = ctx.N, ctx.N_s
 
+    # CG launch choice for (k = 1, FP64): one launch per step or a persistent grid
+    tS, tG = ctx.autotune(k=1, dtype=torch.float64)
     for _ in range(args.warmup):
         ctx.solve(ft, out=u, tol=args.tol)
     torch.cuda.synchronize()
 
-    # ---- timed region: K full solves (persistent cooperative CG launch) ----------
-    ctx.profile_enable(True)
+    # ---- timed region: K full solves with the tuned CG launch ------------------------
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = 0
@@ -112,30 +114,35 @@ def main():
         iters += info[0]["iters"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    cg_ms, cg_launches, cg_iters = ctx.profile_read(semcond.KERNEL_PCG)
-    ctx.profile_enable(False)
     solve_s = (t1 - t0) / args.steps
     it_per_solve = iters / args.steps
     value = N * iters / (t1 - t0) / 1e9
 
-    # ---- the same solves with one launch per CG step --------------------------------
+    # ---- kernel times of the same solves: HIP events around every apply / persistent
+    # CG launch on the launch stream (a separate pass: the events cost a few us each)
     side_steps = max(3, args.steps // 4)
-    ctx.solve(ft, out=u, tol=args.tol, persistent=False)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    ctx.profile_enable(True)
     for _ in range(side_steps):
-        ctx.solve(ft, out=u, tol=args.tol, persistent=False)
-    torch.cuda.synchronize()
-    step_s = (time.perf_counter() - t2) / side_steps
+        ctx.solve(ft, out=u, tol=args.tol)
+    ap_ms, ap_launches, _ = ctx.profile_read(semcond.KERNEL_APPLY)
+    cg_ms, cg_launches, cg_iters = ctx.profile_read(semcond.KERNEL_PCG)
+    ctx.profile_enable(False)
 
-    # ---- FP32 inner CG + FP64 iterative refinement ----------------------------------
-    ctx.solve(ft, out=u, tol=args.tol, precision=semcond.PREC_MIXED_IR, inner_tol=1e-4)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(side_steps):
-        _, minfo = ctx.solve(ft, out=u, tol=args.tol, precision=semcond.PREC_MIXED_IR, inner_tol=1e-4)
-    torch.cuda.synchronize()
-    mixed_s = (time.perf_counter() - t2) / side_steps
+    # ---- the same solves with each launch kind forced --------------------------------
+
+    def timed(**kw):
+        ctx.solve(ft, out=u, tol=args.tol, **kw)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(side_steps):
+            _, inf = ctx.solve(ft, out=u, tol=args.tol, **kw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - ta) / side_steps, inf
+
+    step_s, _ = timed(persistent=False)
+    pers_s, _ = timed(persistent=True)
+    # FP32 inner CG + FP64 iterative refinement
+    mixed_s, minfo = timed(precision=semcond.PREC_MIXED_IR, inner_tol=1e-4)
 
     # ---- apply alone (transformed basis, back-to-back), kernel time from events ------
     xs = torch.randn(Ns, dtype=torch.float64, device="cuda")
@@ -146,14 +153,21 @@ def main():
     ctx.profile_enable(True)
     for _ in range(args.apply_reps):
         ctx.apply(xs, out=ys)
-    ap_ms, ap_launches, _ = ctx.profile_read(semcond.KERNEL_APPLY)
+    pa_ms, pa_launches, _ = ctx.profile_read(semcond.KERNEL_APPLY)
     ctx.profile_enable(False)
-    kern_s = ap_ms / 1e3 / max(ap_launches, 1)
+    kern_s = pa_ms / 1e3 / max(pa_launches, 1)
 
-    # algorithmic FP64 bytes (k = 1): apply reads p, writes q (2 N_s); update reads
-    # x, p, r, q, P^-1 and writes x, r (7 N_s); direction reads r, P^-1, p, writes p (4 N_s)
-    cg_bytes = 13 * 8 * Ns * cg_iters
-    cg_achieved = cg_bytes / (cg_ms / 1e3) / 1e9
+    # Roofline of the dominant kernel of the timed solves.  Algorithmic FP64 bytes
+    # (k = 1): the CG apply gathers p, r and P^-1 (it forms the direction) and adds
+    # into q: 4 N_s; the persistent CG per iteration moves 13 N_s (apply 4; step:
+    # reads r, q, P^-1, p, x and writes q, p, x, r).
+    if cg_ms >= ap_ms:
+        dom = {"kernel": "k_pcg_persistent<double,7,%d>" % tS, "ms": cg_ms, "launches": cg_launches,
+               "bytes": 13 * 8 * Ns * cg_iters}
+    else:
+        dom = {"kernel": "k_apply_tpt<double,7,true>", "ms": ap_ms, "launches": ap_launches,
+               "bytes": 4 * 8 * Ns * ap_launches}
+    dom_achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
     apply_bytes = 2 * 8 * Ns
     apply_achieved = apply_bytes / kern_s / 1e9
     out = {
@@ -175,17 +189,18 @@ def main():
                    "parallelism": "single GPU"},
         "iterations": it_per_solve,
         "ns_per_dof_iter": solve_s / (N * it_per_solve) * 1e9,
-        "stepwise": {"ms_per_solve": step_s * 1e3, "persistent_speedup": step_s / solve_s},
+        "cg_launch": {"tuned": "stepwise" if tS == 0 else "persistent S=%d G=%d" % (tS, tG),
+                      "stepwise_ms_per_solve": step_s * 1e3, "persistent_ms_per_solve": pers_s * 1e3},
         "mixed_ir": {"ms_per_solve": mixed_s * 1e3, "speedup_vs_fp64": solve_s / mixed_s,
                      "inner_iterations": minfo[0]["iters"], "outer_steps": minfo[0]["outer"],
                      "rel_res": minfo[0]["rel_res"]},
-        "roofline": {"bound": "hbm", "achieved": cg_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": cg_achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_pcg_persistent<double,7,4>",
-                     "bytes_per_launch": cg_bytes / max(cg_launches, 1),
-                     "kernel_ms_per_launch": cg_ms / max(cg_launches, 1)},
+        "roofline": {"bound": "hbm", "achieved": dom_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom_achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": dom["kernel"], "launches": dom["launches"],
+                     "bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
+                     "kernel_us_per_launch": dom["ms"] * 1e3 / max(dom["launches"], 1)},
         "apply_roofline": {"bound": "hbm", "achieved": apply_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": apply_achieved / HBM_PEAK_GBS, "kernel": "k_apply_tpt<double,7>",
+                           "frac": apply_achieved / HBM_PEAK_GBS, "kernel": "k_apply_tpt<double,7,false>",
                            "kernel_us": kern_s * 1e6, "gdof_s": N / kern_s / 1e9,
                            "bytes_per_launch": apply_bytes},
     }

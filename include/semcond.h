@@ -118,12 +118,20 @@ typedef struct {
     int rhs_dual;           /* 0: f are nodal values, F = M_G f (default); 1: f is the   */
                             /* assembled discrete right-hand side itself (R F_L), as in  */
                             /* an adjoint solve H_G a = dL/du                             */
-    int persistent;         /* 1: every CG (inner CG for MIXED_IR) runs as one persistent */
-                            /* cooperative launch with the autotuned grid; 0: one launch  */
-                            /* per step with host convergence polls.  Default 1; falls   */
-                            /* back to 0 where no persistent kernel exists (n_I > 15, or  */
-                            /* k not a power of two up to 32)                            */
+    int persistent;         /* how every CG (inner CG for MIXED_IR) is launched:          */
+                            /* SEMCOND_CG_STEPWISE: one launch per step, host polls       */
+                            /*   convergence every check_every iterations;               */
+                            /* SEMCOND_CG_PERSISTENT: one persistent cooperative launch   */
+                            /*   (autotuned grid, else the largest co-resident one);     */
+                            /* SEMCOND_CG_AUTO (default): what semcond_autotune chose for */
+                            /*   (k, type), else stepwise.  Persistent kernels exist for  */
+                            /*   n_I <= 15 and k dividing the workgroup (k <= 32); other  */
+                            /*   cases run stepwise                                       */
 } semcond_solve_opts;
+
+#define SEMCOND_CG_STEPWISE   0
+#define SEMCOND_CG_PERSISTENT 1
+#define SEMCOND_CG_AUTO       (-1)
 
 /* Per right-hand-side result of semcond_solve (host array of k entries). */
 typedef struct {
@@ -269,11 +277,12 @@ int semcond_element_grads(semcond_ctx* ctx, const void* u_nodal, const void* a_n
                           int k, void* stream);
 
 /*
- * Autotuner of the persistent CG launch (k right-hand sides of scalar type
- * dtype): times the candidate grids (workgroup count G, element groups per
- * workgroup S) for a few CG iterations on this context's problem and keeps the
- * fastest for later solves.  When cache_path is non-NULL the choice is read
- * from / appended to that text file (one line "p n1 n2 n3 k dtype S G").
+ * Autotuner of the CG launch (k right-hand sides of scalar type dtype): times
+ * one launch per step and the candidate persistent grids (workgroup count G,
+ * element groups per workgroup S) for a few CG iterations on this context's
+ * problem and keeps the fastest for later SEMCOND_CG_AUTO solves; (S, G) =
+ * (0, 0) denotes one launch per step.  When cache_path is non-NULL the choice
+ * is read from / appended to that text file (one line "p n1 n2 n3 k dtype S G").
  * S_out, G_out (nullable) receive the choice.  Returns EINVAL when no
  * persistent kernel exists for (p, k).  Synchronises the device.
  */

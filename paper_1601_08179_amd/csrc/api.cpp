@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -204,9 +206,11 @@ hipError_t launch_apply(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t st) {
 }
 
 // v = H~^ u (transformed).  v is zeroed first unless v_is_zero.  energy: optional [n_e][k].
+// With dir_r set, the operand is the CG direction fmadd(beta, u, pinv r) (u:
+// previous direction) and q = v must be zero on entry.
 template <typename T>
 int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, double* energy, hipStream_t st,
-                      bool v_is_zero = false) {
+                      bool v_is_zero = false, const T* dir_r = nullptr, const double* dir_beta = nullptr) {
     if (!v_is_zero) HIPCHK(c, launch_fill<T>(v, c->N_s * k, (T)0, st));
     ApplyArgs<T> a;
     a.g = c->geo;
@@ -216,6 +220,12 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, double* energy, h
     a.k = k;
     a.energy = energy;
     a.e_begin = 0;
+    if (dir_r) {
+        if (!dir_beta) return fail(c, SEMCOND_EINVAL, "fused direction needs beta");
+        a.dir_r = dir_r;
+        a.dir_pinv = pinv<T>(c);
+        a.dir_beta = dir_beta;
+    }
     if (c->prof) {
         int rc = profile_begin(c, SEMCOND_KERNEL_APPLY, st);
         if (rc) return rc;
@@ -365,13 +375,13 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
             for (int i = 0; i < k; ++i) any |= c->h_active[i] != 0;
             if (!any) break;
         }
-        // q is zero here: zeroed at start and by every update
-        int rc = apply_transformed<T>(c, p, q, k, w.energy, st, true);
+        // q is zero here: zeroed at start and by every step.  The apply forms
+        // the direction p = beta p + z at its gather; the step stores it.
+        int rc = apply_transformed<T>(c, p, q, k, w.energy, st, true, r, w.s.beta);
         if (rc) return rc;
         HIPCHK(c, launch_cg_reduce(w.energy, c->n_e, 1, k, w.s, RED_PQ, st));
-        HIPCHK(c, launch_cg_update<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, st));
+        HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, st));
         HIPCHK(c, launch_cg_reduce(w.partials, kVecBlocks, 2, k, w.s, RED_RZ, st));
-        HIPCHK(c, launch_cg_direction<T>(p, r, pinv<T>(c), Ns, k, w.s, st));
     }
     return SEMCOND_OK;
 }
@@ -443,13 +453,19 @@ bool persist_default(semcond_ctx* c, int k, int dtype, int* S, int* G) {
 template <typename T>
 int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, int max_iter, CgWork& w, int S, int G,
                    hipStream_t st) {
-    const size_t need = 3 * (size_t)G * k * sizeof(double) + 512;
+    // a cooperative grid must be co-resident: reject configurations (e.g. from a
+    // stale tuning cache) beyond what the device holds at once
+    const int mg = persist_max_grid<T>(c->L.NI, S);
+    if (!persist_supported(c->L.NI, S, k) || G < 1 || G > mg)
+        return fail(c, SEMCOND_EINVAL, "persistent CG: configuration (S, G) not co-resident on this device");
+    const size_t part_bytes = (3 * (size_t)G * k * sizeof(double) + 255) / 256 * 256;
+    const size_t need = part_bytes + kBarWords * sizeof(unsigned);
     int rc = grow(c, c->ws_persist, need);
     if (rc) return rc;
     double* part = (double*)c->ws_persist.ptr;
-    unsigned* bar = (unsigned*)((char*)c->ws_persist.ptr + 3 * (size_t)G * k * sizeof(double));
+    unsigned* bar = (unsigned*)((char*)c->ws_persist.ptr + part_bytes);
     // barrier words and error flag start at zero (bit pattern of 0.0f)
-    HIPCHK(c, launch_fill<float>((float*)bar, 128, 0.0f, st));
+    HIPCHK(c, launch_fill<float>((float*)bar, kBarWords, 0.0f, st));
     PcgArgs<T> P;
     P.A.g = c->geo;
     P.A.tab = tabs<T>(c);
@@ -458,6 +474,10 @@ int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, in
     P.A.k = k;
     P.A.energy = nullptr;
     P.A.e_begin = 0;
+    // the kernel forms the direction at its gather from r, pinv and its own beta
+    P.A.dir_r = r;
+    P.A.dir_pinv = pinv<T>(c);
+    P.A.dir_beta = nullptr;
     P.x = x;
     P.r = r;
     P.p = p;
@@ -468,6 +488,7 @@ int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, in
     P.k = k;
     P.part = part;
     P.rho = w.s.rho;
+    P.beta = w.s.beta;
     P.rr = w.s.rr;
     P.bb = w.s.bb;
     P.active = w.s.active;
@@ -476,7 +497,7 @@ int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, in
     P.tol2 = tol * tol;
     P.max_iter = max_iter;
     P.bar = bar;
-    P.err = (int*)(bar + 64);
+    P.err = (int*)(bar + (kBarGroups + 2) * kBarSlot);
     P.spin_limit = 1u << 24;
     std::vector<int> it0;
     if (c->prof) {
@@ -486,7 +507,29 @@ int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, in
         rc = profile_begin(c, SEMCOND_KERNEL_PCG, st);
         if (rc) return rc;
     }
+    if (!P.A.u || !P.A.v || !P.A.dir_r || !P.A.dir_pinv || !P.x || !P.r || !P.q || !P.pinv || !P.part || !P.beta)
+        return fail(c, SEMCOND_EINVAL, "persistent CG: missing operand");
+#ifdef SEMCOND_PCG_TRACE
+    const size_t ntr = (size_t)kPcgTraceIters * 4 * G;
+    HIPCHK(c, hipMalloc(&P.trace, ntr * sizeof(long long)));
+    HIPCHK(c, hipMemsetAsync(P.trace, 0, ntr * sizeof(long long), st));
+#endif
     HIPCHK(c, launch_pcg_persistent<T>(P, c->L.NI, S, G, st));
+#ifdef SEMCOND_PCG_TRACE
+    {
+        std::vector<long long> tr(ntr);
+        HIPCHK(c, hipMemcpyAsync(tr.data(), P.trace, ntr * sizeof(long long), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        HIPCHK(c, hipFree(P.trace));
+        if (const char* fn = std::getenv("SEMCOND_PCG_TRACE_FILE")) {
+            if (FILE* fp = std::fopen(fn, "a")) {
+                std::fprintf(fp, "launch NI %d S %d G %d k %d\n", c->L.NI, S, G, k);
+                for (size_t i = 0; i < ntr; ++i) std::fprintf(fp, "%lld%c", tr[i], (i + 1) % G ? ' ' : '\n');
+                std::fclose(fp);
+            }
+        }
+    }
+#endif
     if (c->prof) {
         rc = profile_end(c, st);
         if (rc) return rc;
@@ -505,20 +548,22 @@ int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, in
     return SEMCOND_OK;
 }
 
-// CG on the transformed condensed system: persistent launch when requested and
-// available, else one launch per step.
+// CG on the transformed condensed system.  mode SEMCOND_CG_AUTO takes the
+// autotuned choice for (k, type) when there is one (S = 0 meaning one launch
+// per step), else one launch per step; SEMCOND_CG_PERSISTENT takes the tuned
+// or default persistent grid where a persistent kernel exists.
 template <typename T>
 int run_cg_any(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol, int max_iter, int check_every,
-               bool x0_given, bool persistent, CgWork& w, hipStream_t st) {
+               bool x0_given, int mode, CgWork& w, hipStream_t st) {
     int S = 0, G = 0;
     bool use = false;
-    if (persistent && persist_supported(c->L.NI, 1, k)) {
+    if (mode != SEMCOND_CG_STEPWISE && persist_supported(c->L.NI, 1, k)) {
         auto it = c->tuned.find({k, dtype_of<T>()});
-        if (it != c->tuned.end()) {
+        if (it != c->tuned.end() && it->second.first > 0) {
             S = it->second.first;
             G = it->second.second;
             use = true;
-        } else {
+        } else if (mode == SEMCOND_CG_PERSISTENT) {
             use = persist_default(c, k, dtype_of<T>(), &S, &G);
         }
     }
@@ -539,14 +584,15 @@ int run_cg_any(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double
     return run_persistent<T>(c, x, r, p, q, k, tol, max_iter, w, S, G, st);
 }
 
-// Time the candidate persistent configurations for `iters` CG iterations on
-// the condensed RHS b (tolerance 0, so every RHS stays active).
+// Time the candidate persistent configurations, and one launch per step, for
+// `iters` CG iterations on the condensed RHS b (tolerance 0, so every RHS
+// stays active).  (S, G) = (0, 0) when one launch per step is fastest.
 template <typename T>
 int autotune_persistent(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, CgWork& w, hipStream_t st,
                         int* bestS, int* bestG) {
     const int NI = c->L.NI;
     const int smax = NI * NI <= 64 ? 4 : (NI * NI <= 128 ? 2 : 1);
-    std::vector<std::pair<int, int>> cands;
+    std::vector<std::pair<int, int>> cands = {{0, 0}};
     for (int S : {smax, 1}) {
         if (!persist_supported(NI, S, k)) continue;
         const int mg = persist_max_grid<T>(NI, S);
@@ -560,7 +606,6 @@ int autotune_persistent(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int 
         }
         if (S == 1 && smax == 1) break;
     }
-    if (cands.empty()) return fail(c, SEMCOND_EINVAL, "no persistent kernel for this degree and k");
     const int iters = 12;
     double best = 1e300;
     for (auto& cc : cands) {
@@ -572,7 +617,13 @@ int autotune_persistent(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int 
             HIPCHK(c, launch_cg_reduce(w.partials, kVecBlocks, 3, k, w.s, RED_INIT, st));
             HIPCHK(c, hipStreamSynchronize(st));
             auto t0 = std::chrono::steady_clock::now();
-            int rc = run_persistent<T>(c, x, r, p, q, k, 0.0, iters, w, cc.first, cc.second, st);
+            int rc;
+            if (cc.first == 0) {
+                rc = run_cg<T>(c, b, x, r, p, q, k, 0.0, iters, iters + 1, false, w, st);
+                if (!rc) HIPCHK(c, hipStreamSynchronize(st));
+            } else {
+                rc = run_persistent<T>(c, x, r, p, q, k, 0.0, iters, w, cc.first, cc.second, st);
+            }
             if (rc) return rc;
             const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             t_best = std::min(t_best, dt);
@@ -888,7 +939,8 @@ int semcond_autotune(semcond_ctx* c, int k, int dtype, const char* cache_path, i
                 if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &s0, &g0) == 8) {
                     char k2[160];
                     std::snprintf(k2, sizeof k2, "%d %d %d %d %d %d", a[0], a[1], a[2], a[3], a[4], a[5]);
-                    if (std::strcmp(k2, key) == 0 && persist_supported(c->L.NI, s0, k) && g0 > 0) {
+                    if (std::strcmp(k2, key) == 0 &&
+                        ((s0 == 0 && g0 == 0) || (persist_supported(c->L.NI, s0, k) && g0 > 0))) {
                         S = s0;
                         G = g0;
                         found = true;
@@ -960,7 +1012,7 @@ void semcond_solve_opts_default(semcond_solve_opts* o) {
     o->inner_tol = 1e-5;
     o->max_outer = 30;
     o->rhs_dual = 0;
-    o->persistent = 1;
+    o->persistent = SEMCOND_CG_AUTO;
 }
 
 int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_solve_opts* opts,
@@ -1014,7 +1066,7 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
     CgHost h;
     if (o.precision == SEMCOND_PREC_F64) {
         rc = run_cg_any<double>(c, b, x, r, p, q, k, o.tol, o.max_iter, o.check_every, o.x0 != nullptr,
-                                o.persistent != 0, w, st);
+                                o.persistent, w, st);
         if (rc) return rc;
         rc = read_state(c, w, k, &h, st);
         if (rc) return rc;
@@ -1028,7 +1080,7 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
         HIPCHK(c, (launch_convert<double, float>(b, b32, nv, st)));
         if (o.x0) HIPCHK(c, (launch_convert<double, float>(x, x32, nv, st)));
         rc = run_cg_any<float>(c, b32, x32, r32, p32, q32, k, o.tol, o.max_iter, o.check_every, o.x0 != nullptr,
-                               o.persistent != 0, w, st);
+                               o.persistent, w, st);
         if (rc) return rc;
         HIPCHK(c, (launch_convert<float, double>(x32, x, nv, st)));
         rc = read_state(c, w, k, &h, st);
@@ -1090,7 +1142,7 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
             }
             HIPCHK(c, launch_convert_masked(r, r32, nv, k, wo.s.active, st));
             rc = run_cg_any<float>(c, r32, x32, b32, p32, q32, k, o.inner_tol, o.max_iter, o.check_every, false,
-                                   o.persistent != 0, w, st);
+                                   o.persistent, w, st);
             if (rc) return rc;
             CgHost hi;
             rc = read_state(c, w, k, &hi, st);

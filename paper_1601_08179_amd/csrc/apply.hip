@@ -8,10 +8,10 @@
 
 namespace semcond {
 
-template <typename T, int NI>
+template <typename T, int NI, bool DIR>
 __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A) {
     __shared__ ApplySmem<T, NI> sm;
-    apply_element<T, NI>(A, (int64_t)blockIdx.x + A.e_begin, sm, nullptr, threadIdx.x, true);
+    apply_element<T, NI, DIR>(A, (int64_t)blockIdx.x + A.e_begin, sm, nullptr, threadIdx.x, true, A.dir_beta);
 }
 
 template <typename T>
@@ -19,9 +19,12 @@ hipError_t launch_apply_tpt(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t s
     const int NI = a.g.L.NI;
     if (n_elem <= 0) return hipSuccess;
     dim3 grid((unsigned)n_elem);
-#define CASE(N)                                                                         \
-    case N:                                                                             \
-        hipLaunchKernelGGL((k_apply_tpt<T, N>), grid, dim3(apply_threads(N)), 0, st, a); \
+#define CASE(N)                                                                                \
+    case N:                                                                                    \
+        if (a.dir_r)                                                                           \
+            hipLaunchKernelGGL((k_apply_tpt<T, N, true>), grid, dim3(apply_threads(N)), 0, st, a); \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_apply_tpt<T, N, false>), grid, dim3(apply_threads(N)), 0, st, a); \
         break;
     switch (NI) {
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)

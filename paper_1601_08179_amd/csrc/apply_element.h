@@ -59,15 +59,17 @@ struct ApplySmem {
 };
 
 // Apply the condensed operator of element e to all k right-hand sides of
-// A.u, scattering into A.v.  The element energies u_e . (H~^ u)_e go to
+// A.u, scattering into A.v.  With DIR the operand is the CG direction
+// p = fmadd(beta[r], A.u, A.dir_pinv * A.dir_r), formed at the gather (beta:
+// [k], global or shared memory).  The element energies u_e . (H~^ u)_e go to
 // A.energy[e*k + r] when A.energy is set and are added to en_acc[r] (shared
 // memory, by the group's thread 0) when en_acc is set.  Executed by a group of
 // apply_threads(NI) threads with local ids tid; every thread of the workgroup
 // must make the same sequence of calls (the function uses workgroup
 // barriers).  live = false runs the same code without any global write.
-template <typename T, int NI>
+template <typename T, int NI, bool DIR>
 __device__ void apply_element(const ApplyArgs<T>& A, int64_t e, ApplySmem<T, NI>& sm, double* en_acc,
-                              int tid, bool live) {
+                              int tid, bool live, const double* beta) {
     constexpr int NI2 = NI * NI;
     constexpr int NT = apply_threads(NI);
     constexpr int NFACE = 6 * NI2;
@@ -118,7 +120,7 @@ __device__ void apply_element(const ApplyArgs<T>& A, int64_t e, ApplySmem<T, NI>
         // node) and are zeroed afterwards.
         {
             constexpr int NG = (NSLOT + NT - 1) / NT;
-            int64_t addr[NG];
+            int64_t node[NG];
             bool keep[NG];
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
@@ -135,11 +137,23 @@ __device__ void apply_element(const ApplyArgs<T>& A, int64_t e, ApplySmem<T, NI>
                     ent = 18 + (s - NFACE - NEDGE);
                 }
                 keep[g] = s < NSLOT && !econ[ent];
-                addr[g] = keep[g] ? (ebase[ent] + loc) * k + r : (int64_t)r;
+                node[g] = keep[g] ? ebase[ent] + loc : 0;
             }
             T val[NG];
 #pragma unroll
-            for (int g = 0; g < NG; ++g) val[g] = (tid + g * NT < NSLOT) ? A.u[addr[g]] : (T)0;
+            for (int g = 0; g < NG; ++g) val[g] = (tid + g * NT < NSLOT) ? A.u[node[g] * k + r] : (T)0;
+            if constexpr (DIR) {
+                const T bt = (T)beta[r];
+                T rv[NG], pv[NG];
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const bool in = tid + g * NT < NSLOT;
+                    rv[g] = in ? A.dir_r[node[g] * k + r] : (T)0;
+                    pv[g] = in ? A.dir_pinv[node[g]] : (T)0;
+                }
+#pragma unroll
+                for (int g = 0; g < NG; ++g) val[g] = fmadd(bt, val[g], pv[g] * rv[g]);
+            }
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
                 const int s = tid + g * NT;

@@ -87,6 +87,11 @@ __device__ inline float recip<float>(float x) {
     return __builtin_fmaf(r, e, r);
 }
 
+// a*b + c with one rounding (the CG direction is formed with it wherever it is
+// needed, so every copy of it is bitwise the same).
+__device__ inline double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ inline float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 template <typename T>
 __device__ inline void atomic_add(T* p, T v) {
     unsafeAtomicAdd(p, v);

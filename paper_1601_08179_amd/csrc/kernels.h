@@ -17,6 +17,12 @@ struct ApplyArgs {
     int k;
     double* energy;   // nullable, [n_elem][k]: element energies u_e . (H~^ u)_e
     int64_t e_begin;  // first element of this launch
+    // Fused CG direction (all null for a plain apply): when dir_r is set the
+    // operand is p = beta_r u + pinv r, formed at the gather with fmadd, where
+    // u holds the previous direction and beta the per-RHS coefficients [k].
+    const T* dir_r = nullptr;
+    const T* dir_pinv = nullptr;
+    const double* dir_beta = nullptr;
 };
 
 template <typename T>
@@ -92,7 +98,8 @@ constexpr int kVecBlocks = 2048;  // fixed grid of the vector kernels (partials 
 
 int vec_block_threads(int k);
 
-// r = b - q0 (q0 nullable: then r = b; else q0 is zeroed after use), p = pinv r,
+// r = b - q0 (q0 nullable: then r = b; else q0 is zeroed after use), p = 0
+// (the previous direction of the first step, whose beta is 0),
 // partials[0]: r.z, [1]: r.r, [2]: b.b  ([3][kVecBlocks][k] doubles).
 template <typename T>
 hipError_t launch_cg_init(const T* b, T* q0, const T* pinv, T* r, T* p, int64_t Ns, int k,
@@ -101,13 +108,11 @@ hipError_t launch_cg_init(const T* b, T* q0, const T* pinv, T* r, T* p, int64_t 
 enum ReduceMode { RED_INIT = 0, RED_PQ = 1, RED_RZ = 2 };
 hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int k, CgState s, int mode,
                             hipStream_t st);
-// x += alpha p; r -= alpha q; q = 0; partials[0] r.z (z = pinv r), [1] r.r.
+// One CG step on active right-hand sides, with q = H~^ p already formed:
+// p = fmadd(beta, p, pinv r) (the direction the apply used), x += alpha p,
+// r -= alpha q; then q = 0 and partials[0] r.z (z = pinv r), [1] r.r.
 template <typename T>
-hipError_t launch_cg_update(T* x, T* r, const T* p, T* q, const T* pinv, int64_t Ns, int k,
-                            CgState s, double* partials, hipStream_t st);
-// p = pinv r + beta p.
-template <typename T>
-hipError_t launch_cg_direction(T* p, const T* r, const T* pinv, int64_t Ns, int k, CgState s,
-                               hipStream_t st);
+hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s,
+                          double* partials, hipStream_t st);
 
 }  // namespace semcond

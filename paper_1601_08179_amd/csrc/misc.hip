@@ -581,7 +581,7 @@ __global__ __launch_bounds__(256) void k_cg_init(const T* __restrict__ b, T* __r
         }
         const T z = pinv[s] * rv;
         r[idx] = rv;
-        p[idx] = z;
+        p[idx] = (T)0;
         acc[0] += (double)rv * (double)z;
         acc[1] += (double)rv * (double)rv;
         acc[2] += (double)bv * (double)bv;
@@ -601,109 +601,134 @@ template hipError_t launch_cg_init<double>(const double*, double*, const double*
 template hipError_t launch_cg_init<float>(const float*, float*, const float*, float*, float*, int64_t, int, double*,
                                           hipStream_t);
 
-// One block: totals of nq quantities per RHS, then the CG scalar step.
-__global__ __launch_bounds__(256) void k_cg_reduce(const double* __restrict__ partials, int64_t nparts, int nq,
-                                                   int k, CgState s, int mode) {
-    __shared__ double sh[256];
-    __shared__ double tot[3 * 256];
-    const int t = threadIdx.x;
-    for (int q = 0; q < nq; ++q) {
-        for (int r = 0; r < k; ++r) {
-            double acc = 0.0;
-            for (int64_t m = t; m < nparts; m += 256) acc += partials[((int64_t)q * nparts + m) * k + r];
-            sh[t] = acc;
-            __syncthreads();
-            for (int w = 128; w > 0; w >>= 1) {
-                if (t < w) sh[t] += sh[t + w];
-                __syncthreads();
-            }
-            if (t == 0) tot[q * 256 + r] = sh[0];
-            __syncthreads();
-        }
+// One block of B = k * floor(1024/k) threads: thread t sums RHS t mod k over
+// the parts t/k, t/k + B/k, ... (all loads of a thread issued together), a
+// fixed-shape tree adds the B/k sums; then the CG scalar step per RHS.
+constexpr int kReduceThreads = 1024;
+
+__global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __restrict__ partials, int64_t nparts,
+                                                              int nq, int k, CgState s, int mode) {
+    __shared__ double sh[3][kReduceThreads];
+    const int t = threadIdx.x, r = t % k, j = t / k, npb = blockDim.x / k;
+    constexpr int U = 8;
+    // per-RHS state read before anything is written, so that no load waits on a store
+    int act = 0, its = 0;
+    double rho = 0.0, bb = 0.0, tol2 = 0.0;
+    if (t < k) {
+        act = s.active[t];
+        its = s.iters[t];
+        rho = s.rho[t];
+        bb = s.bb[t];
+        tol2 = s.tol2[0];
     }
-    for (int r = t; r < k; r += 256) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t m0 = j; m0 < nparts; m0 += (int64_t)U * npb) {
+        double v[3][U];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t m = m0 + (int64_t)u * npb;
+                v[q][u] = (q < nq && m < nparts) ? partials[((int64_t)q * nparts + m) * k + r] : 0.0;
+            }
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[q] += v[q][u];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) sh[q][t] = acc[q];
+    __syncthreads();
+    int P = 1;
+    while (P < npb) P <<= 1;
+    for (int w = P >> 1; w > 0; w >>= 1) {
+        if (j < w && j + w < npb) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) sh[q][t] += sh[q][t + w * k];
+        }
+        __syncthreads();
+    }
+    if (t < k) {
+        const double t0 = sh[0][t], t1 = sh[1][t], t2 = sh[2][t];
         if (mode == RED_INIT) {
-            const double rz = tot[r], rr = tot[256 + r], bb = tot[512 + r];
+            const double rz = t0, rr = t1, b2 = t2;
             s.rho[r] = rz;
             s.rr[r] = rr;
-            s.bb[r] = bb;
+            s.bb[r] = b2;
             s.iters[r] = 0;
-            s.status[r] = 0;
             s.alpha[r] = 0.0;
             s.beta[r] = 0.0;
-            if (!isfinite(rr) || !isfinite(rz)) {
-                s.status[r] = -5;
-                s.active[r] = 0;
-            } else {
-                s.active[r] = (rr > s.tol2[0] * bb) ? 1 : 0;
-            }
+            const bool bad = !isfinite(rr) || !isfinite(rz);
+            s.status[r] = bad ? -5 : 0;
+            s.active[r] = bad ? 0 : ((rr > tol2 * b2) ? 1 : 0);
         } else if (mode == RED_PQ) {
-            const double pq = tot[r];
+            const double pq = t0;
             s.pq[r] = pq;
-            if (s.active[r]) {
+            double alpha = 0.0;
+            if (act) {
                 if (!isfinite(pq)) {
                     s.status[r] = -5;
                     s.active[r] = 0;
-                    s.alpha[r] = 0.0;
                 } else if (!(pq > 0.0)) {
                     s.status[r] = -4;
                     s.active[r] = 0;
-                    s.alpha[r] = 0.0;
                 } else {
-                    s.alpha[r] = s.rho[r] / pq;
+                    alpha = rho / pq;
                 }
-            } else {
-                s.alpha[r] = 0.0;
             }
+            s.alpha[r] = alpha;
         } else {  // RED_RZ
-            const double rz = tot[r], rr = tot[256 + r];
-            if (s.active[r]) {
-                s.iters[r] += 1;
+            const double rz = t0, rr = t1;
+            double beta = 0.0;
+            if (act) {
+                s.iters[r] = its + 1;
                 s.rr[r] = rr;
                 if (!isfinite(rr) || !isfinite(rz)) {
                     s.status[r] = -5;
                     s.active[r] = 0;
-                    s.beta[r] = 0.0;
-                } else if (rr <= s.tol2[0] * s.bb[r]) {
+                } else if (rr <= tol2 * bb) {
                     s.active[r] = 0;
-                    s.beta[r] = 0.0;
                 } else {
-                    s.beta[r] = rz / s.rho[r];
+                    beta = rz / rho;
                     s.rho[r] = rz;
                 }
-            } else {
-                s.beta[r] = 0.0;
             }
+            s.beta[r] = beta;
         }
     }
 }
 
 hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int k, CgState s, int mode,
                             hipStream_t st) {
-    if (k > 256 || nq > 3) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(256), 0, st, partials, nparts, nq, k, s, mode);
+    if (k < 1 || k > kReduceThreads || nq < 1 || nq > 3) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(k * (kReduceThreads / k)), 0, st, partials, nparts, nq, k, s,
+                       mode);
     return hipGetLastError();
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                                                   T* __restrict__ q, const T* __restrict__ pinv, int64_t Ns,
-                                                   int k, CgState s, double* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
+                                                 T* __restrict__ q, const T* __restrict__ pinv, int64_t Ns, int k,
+                                                 CgState s, double* __restrict__ partials) {
     const VecIter it = vec_iter(k);
     const T alpha = (T)s.alpha[it.rhs];
+    const T beta = (T)s.beta[it.rhs];
     const bool act = s.active[it.rhs] != 0;
     double acc[2] = {0.0, 0.0};
     for (int64_t n = it.s0; n < Ns; n += it.stride) {
         const int64_t idx = n * k + it.rhs;
         T rv = r[idx];
         const T qv = q[idx];
+        const T pn = pinv[n];
         q[idx] = (T)0;  // q is accumulated from zero by the next operator application
         if (act) {
-            x[idx] += alpha * p[idx];
+            const T pv = fmadd(beta, p[idx], pn * rv);  // the direction the apply used
+            p[idx] = pv;
+            x[idx] += alpha * pv;
             rv -= alpha * qv;
             r[idx] = rv;
         }
-        const T z = pinv[n] * rv;
+        const T z = pn * rv;
         acc[0] += (double)rv * (double)z;
         acc[1] += (double)rv * (double)rv;
     }
@@ -711,38 +736,16 @@ __global__ __launch_bounds__(256) void k_cg_update(T* __restrict__ x, T* __restr
 }
 
 template <typename T>
-hipError_t launch_cg_update(T* x, T* r, const T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s,
-                            double* partials, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(kVecBlocks), dim3(vec_block_threads(k)), 0, st, x, r, p, q, pinv, Ns, k,
-                       s, partials);
+hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s, double* partials,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_step<T>, dim3(kVecBlocks), dim3(vec_block_threads(k)), 0, st, x, r, p, q, pinv, Ns, k, s,
+                       partials);
     return hipGetLastError();
 }
-template hipError_t launch_cg_update<double>(double*, double*, const double*, double*, const double*, int64_t, int,
-                                             CgState, double*, hipStream_t);
-template hipError_t launch_cg_update<float>(float*, float*, const float*, float*, const float*, int64_t, int, CgState,
-                                            double*, hipStream_t);
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_cg_direction(T* __restrict__ p, const T* __restrict__ r,
-                                                      const T* __restrict__ pinv, int64_t Ns, int k, CgState s) {
-    const VecIter it = vec_iter(k);
-    const T beta = (T)s.beta[it.rhs];
-    if (!s.active[it.rhs]) return;
-    for (int64_t n = it.s0; n < Ns; n += it.stride) {
-        const int64_t idx = n * k + it.rhs;
-        p[idx] = pinv[n] * r[idx] + beta * p[idx];
-    }
-}
-
-template <typename T>
-hipError_t launch_cg_direction(T* p, const T* r, const T* pinv, int64_t Ns, int k, CgState s, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_direction<T>, dim3(kVecBlocks), dim3(vec_block_threads(k)), 0, st, p, r, pinv, Ns, k, s);
-    return hipGetLastError();
-}
-template hipError_t launch_cg_direction<double>(double*, const double*, const double*, int64_t, int, CgState,
-                                                hipStream_t);
-template hipError_t launch_cg_direction<float>(float*, const float*, const float*, int64_t, int, CgState,
-                                               hipStream_t);
+template hipError_t launch_cg_step<double>(double*, double*, double*, double*, const double*, int64_t, int, CgState,
+                                           double*, hipStream_t);
+template hipError_t launch_cg_step<float>(float*, float*, float*, float*, const float*, int64_t, int, CgState, double*,
+                                          hipStream_t);
 
 }  // namespace semcond
 

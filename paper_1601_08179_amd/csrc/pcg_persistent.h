@@ -9,13 +9,18 @@
 namespace semcond {
 
 constexpr int kPersistMaxK = 32;  // right-hand sides of one persistent launch
+// Grid barrier words: kBarGroups group counters, a top counter, the generation
+// and the error flag, each kBarSlot unsigned words (256 B) apart.
+constexpr int kBarSlot = 64;
+constexpr int kBarGroups = 64;
+constexpr int kBarWords = (kBarGroups + 3) * kBarSlot;
 
 template <typename T>
 struct PcgArgs {
     ApplyArgs<T> A;  // operator: A.u = p, A.v = q, A.k = k, A.energy = nullptr
     T* x;
     T* r;
-    T* p;
+    T* p;            // previous direction (0 with beta = 0 before the first step)
     T* q;            // zero on entry; zeroed again after every use
     const T* pinv;   // [N_s] inverse preconditioner diagonal
     int64_t Ns, n_e;
@@ -23,6 +28,7 @@ struct PcgArgs {
     double* part;    // [3][grid][k] workgroup partials
     // CG state (device, per RHS), read at start and written back at exit
     double* rho;
+    double* beta;
     double* rr;
     const double* bb;
     int* active;
@@ -30,10 +36,17 @@ struct PcgArgs {
     int* status;
     double tol2;
     int max_iter;
-    unsigned* bar;   // grid barrier words (bar[0] count, bar[32] generation), zero on first use
-    int* err;        // set when a barrier wait exceeded spin_limit
+    unsigned* bar;   // kBarWords grid barrier words, zero on first use
+    int* err;        // set when a barrier wait exceeded spin_limit (own 256-B slot)
     unsigned spin_limit;
+#ifdef SEMCOND_PCG_TRACE
+    long long* trace;  // [kPcgTraceIters][4][grid] wall-clock stamps (instrumented builds only)
+#endif
 };
+
+#ifdef SEMCOND_PCG_TRACE
+constexpr int kPcgTraceIters = 16;
+#endif
 
 // Whether (n_I, S, k) has a compiled persistent kernel: n_I <= 15, S = 1 or
 // the largest group count for n_I, k <= kPersistMaxK dividing the workgroup.

@@ -1,10 +1,12 @@
 // BT conjugate gradients (Sec. 8) for k right-hand sides in one persistent,
 // cooperative launch.
 //
-// Every iteration runs three phases separated by grid-wide barriers:
-//   A  q = H~^ p on all elements (apply_element.h), per-RHS energies p.q;
-//   B  alpha = rho / p.q, x += alpha p, r -= alpha q, q = 0, partial r.z, r.r;
-//   C  beta, convergence per RHS, p = z + beta p  (z = P~^-1 r, never stored).
+// Every iteration runs two phases separated by grid-wide barriers:
+//   A  p = beta p + z (z = P~^-1 r, formed at the gather, never stored),
+//      q = H~^ p on all elements (apply_element.h), per-RHS energies p.q;
+//   B  alpha = rho / p.q; on the workgroup's nodes p is formed again (bitwise
+//      the same) and stored, x += alpha p, r -= alpha q, q = 0; partial r.z,
+//      r.r; then beta and convergence per RHS.
 // The scalars are reduced by every workgroup from the per-workgroup partials
 // in one fixed order, so all workgroups take identical decisions (exit, per-RHS
 // freeze) without further communication, and results do not depend on
@@ -21,85 +23,135 @@
 
 namespace semcond {
 
-// Grid barrier on bar[0] (arrival count) and bar[32] (generation, separate
-// cache line).  Returns false when the wait bound was exceeded or another
+// Grid barrier, two levels: workgroups arrive on the counter of their group
+// of gs consecutive workgroups; the last arrival of a group arrives on the top
+// counter, and the last group bumps the generation that everyone waits on.
+// Same-address atomics are executed one after another at the memory side, so
+// the tree keeps every counter at no more than max(32, G/64) arrivals.
+// Words live kBarSlot words (256 B) apart: bar[g * kBarSlot] group counters,
+// bar[kBarGroups * kBarSlot] top counter, bar[(kBarGroups + 1) * kBarSlot]
+// generation.  One thread per workgroup synchronises: the workgroup barrier
+// orders the other waves' stores before its agent-scope release (the arrival
+// increment; arrivals are acquire-release, so the chain of increments carries
+// every workgroup's stores to the generation bump), and its agent-scope acquire
+// after the wait is followed by a workgroup barrier.  The spin uses relaxed
+// loads so that waiting workgroups do not invalidate the caches of those still
+// working.  Returns false when the wait bound was exceeded or another
 // workgroup raised the error flag.
 __device__ inline bool grid_barrier(unsigned* bar, int* err, unsigned spin_limit, int* s_ok) {
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned* count = bar;
-        unsigned* gen = bar + 32;
-        const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived = atomicAdd(count, 1u);
+        const unsigned G = gridDim.x;
+        const unsigned gs = max(32u, (G + kBarGroups - 1) / kBarGroups);
+        const unsigned ng = (G + gs - 1) / gs;
+        const unsigned grp = blockIdx.x / gs;
+        const unsigned gsize = min(gs, G - grp * gs);
+        unsigned* cnt = bar + grp * kBarSlot;
+        unsigned* top = bar + kBarGroups * kBarSlot;
+        unsigned* gen = bar + (kBarGroups + 1) * kBarSlot;
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
-        if (arrived == gridDim.x - 1) {
-            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            atomicAdd(gen, 1u);
-        } else {
+        bool released = false;
+        if (__hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gsize - 1) {
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == ng - 1) {
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        }
+        if (!released) {
             unsigned spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > spin_limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > spin_limit) {
+                    ok = 0;
+                    break;
+                }
+                if ((spins & 63u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     ok = 0;
                     break;
                 }
             }
         }
-        if (!ok) atomicExch(err, 1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (!ok) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         *s_ok = ok;
     }
     __syncthreads();
-    __threadfence();
     return *s_ok != 0;
 }
 
-// out[r] = sum over workgroups b of part[(q*G + b)*k + r], in a fixed order.
-template <int WG>
-__device__ inline void reduce_partials(const double* part, int q, int k, double* s_red, double* out) {
+// Store that is made coherent at device scope as it is written (through the
+// XCD's L2), so the release at the next grid barrier has no dirty lines of the
+// CG vectors to write back; every vector is re-read only after that barrier's
+// acquire, which invalidates the L2 anyway.
+template <typename T>
+__device__ inline void store_dev(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// out[q][r] = sum over workgroups b of part[(q*G + b)*k + r] for q < NQ, in a
+// fixed order; every load of a thread is issued before the first add.
+template <int WG, int NQ>
+__device__ inline void reduce_partials(const double* part, int k, double (*s_red)[WG], double (*out)[kPersistMaxK]) {
     const int t = threadIdx.x, G = gridDim.x, r = t % k, j = t / k, npb = WG / k;
-    double acc = 0.0;
-#pragma unroll 4
-    for (int b = j; b < G; b += npb) acc += part[((int64_t)q * G + b) * k + r];
-    s_red[t] = acc;
+    constexpr int U = 4;
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int b0 = j; b0 < G; b0 += U * npb) {
+        double v[NQ][U];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int b = b0 + u * npb;
+                v[q][u] = b < G ? part[((int64_t)q * G + b) * k + r] : 0.0;
+            }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[q] += v[q][u];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) s_red[q][t] = acc[q];
     __syncthreads();
     int P = 1;
     while (P < npb) P <<= 1;
     for (int w = P >> 1; w > 0; w >>= 1) {
-        if (j < w && j + w < npb) s_red[t] += s_red[t + w * k];
+        if (j < w && j + w < npb) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) s_red[q][t] += s_red[q][t + w * k];
+        }
         __syncthreads();
     }
-    if (t < k) out[t] = s_red[t];
+    if (t < k) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) out[q][t] = s_red[q][t];
+    }
     __syncthreads();
 }
 
-// Per-workgroup partial of one quantity: s_red holds one value per thread
-// (thread t belongs to RHS t mod k); writes part[(q*G + b)*k + r].
-template <int WG>
-__device__ inline void write_partial(double* s_red, int k, double* part, int q) {
-    const int t = threadIdx.x, j = t / k, npb = WG / k;
-    __syncthreads();
-    int P = 1;
-    while (P < npb) P <<= 1;
-    for (int w = P >> 1; w > 0; w >>= 1) {
-        if (j < w && j + w < npb) s_red[t] += s_red[t + w * k];
-        __syncthreads();
-    }
-    if (t < k) part[((int64_t)q * gridDim.x + blockIdx.x) * k + t] = s_red[t];
-    __syncthreads();
-}
+#ifdef SEMCOND_PCG_TRACE
+#define PCG_STAMP(ph)                                \
+    if (P.trace && t == 0 && it < kPcgTraceIters) \
+        P.trace[((int64_t)it * 4 + (ph)) * G + b] = wall_clock64();
+#else
+#define PCG_STAMP(ph)
+#endif
 
 template <typename T, int NI, int S>
-__global__ __launch_bounds__(S * apply_threads(NI)) void k_pcg_persistent(PcgArgs<T> P) {
+__global__ __launch_bounds__(S * apply_threads(NI), 2) void k_pcg_persistent(PcgArgs<T> P) {
     constexpr int NT = apply_threads(NI);
     constexpr int WG = S * NT;
     constexpr int KM = kPersistMaxK;
+    constexpr int U = 4;  // nodes per thread whose loads are issued together in phase B
     __shared__ ApplySmem<T, NI> sm[S];
     __shared__ double s_en[S][KM];
     __shared__ double s_rho[KM], s_alpha[KM], s_beta[KM], s_bb[KM], s_rr[KM], s_tot[2][KM];
     __shared__ int s_act[KM], s_iters[KM], s_status[KM];
-    __shared__ double s_red[WG], s_red2[WG];
+    __shared__ double s_red[2][WG];
     __shared__ int s_flag, s_ok;
 
     const int t = threadIdx.x, sub = t / NT, lt = t - sub * NT;
@@ -107,6 +159,7 @@ __global__ __launch_bounds__(S * apply_threads(NI)) void k_pcg_persistent(PcgArg
     const int rfix = t % k, npb = WG / k;
     if (t < k) {
         s_rho[t] = P.rho[t];
+        s_beta[t] = P.beta[t];
         s_rr[t] = P.rr[t];
         s_bb[t] = P.bb[t];
         s_act[t] = P.active[t];
@@ -117,6 +170,7 @@ __global__ __launch_bounds__(S * apply_threads(NI)) void k_pcg_persistent(PcgArg
     __syncthreads();
     const int64_t per_round = (int64_t)G * S;
     const int64_t rounds = (P.n_e + per_round - 1) / per_round;
+    const int64_t vstride = (int64_t)G * npb;
 
     for (int it = 0; it < P.max_iter; ++it) {
         if (t == 0) {
@@ -126,24 +180,26 @@ __global__ __launch_bounds__(S * apply_threads(NI)) void k_pcg_persistent(PcgArg
         }
         __syncthreads();
         if (!s_flag) break;
+        PCG_STAMP(0)
 
-        // ---- A: q = H~^ p, energies p.q
+        // ---- A: q = H~^ p with p = beta p + z formed at the gather, energies p.q
         if (lt < k) s_en[sub][lt] = 0.0;
         __syncthreads();
         for (int64_t m = 0; m < rounds; ++m) {
             const int64_t e = (m * G + b) * S + sub;
             const bool live = e < P.n_e;
-            apply_element<T, NI>(P.A, live ? e : 0, sm[sub], s_en[sub], lt, live);
+            apply_element<T, NI, true>(P.A, live ? e : 0, sm[sub], s_en[sub], lt, live, s_beta);
         }
         if (t < k) {
             double s = 0.0;
             for (int g = 0; g < S; ++g) s += s_en[g][t];
-            P.part[((int64_t)0 * G + b) * k + t] = s;
+            P.part[(int64_t)b * k + t] = s;
         }
+        PCG_STAMP(1)
         if (!grid_barrier(P.bar, P.err, P.spin_limit, &s_ok)) return;
 
-        // ---- B: alpha, x and r updates
-        reduce_partials<WG>(P.part, 0, k, s_red, s_tot[0]);
+        // ---- B: alpha; p, x, r updates on this workgroup's nodes; r.z, r.r
+        reduce_partials<WG, 1>(P.part, k, s_red, s_tot);
         if (t < k) {
             const double pq = s_tot[0][t];
             if (s_act[t]) {
@@ -163,34 +219,66 @@ __global__ __launch_bounds__(S * apply_threads(NI)) void k_pcg_persistent(PcgArg
             }
         }
         __syncthreads();
+        PCG_STAMP(2)
         {
-            const T alpha = (T)s_alpha[rfix];
+            const T alpha = (T)s_alpha[rfix], beta = (T)s_beta[rfix];
             const bool act = s_act[rfix] != 0;
             double arz = 0.0, arr = 0.0;
-            for (int64_t n = (int64_t)b * npb + t / k; n < P.Ns; n += (int64_t)G * npb) {
-                const int64_t idx = n * k + rfix;
-                T rv = P.r[idx];
-                const T qv = P.q[idx];
-                P.q[idx] = (T)0;
-                if (act) {
-                    P.x[idx] += alpha * P.p[idx];
-                    rv -= alpha * qv;
-                    P.r[idx] = rv;
+            for (int64_t n0 = (int64_t)b * npb + t / k; n0 < P.Ns; n0 += U * vstride) {
+                T rv[U], qv[U], pv[U], xv[U], pn[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t n = n0 + u * vstride;
+                    const bool in = n < P.Ns;
+                    const int64_t idx = n * k + rfix;
+                    rv[u] = in ? P.r[idx] : (T)0;
+                    qv[u] = in ? P.q[idx] : (T)0;
+                    pn[u] = in ? P.pinv[n] : (T)0;
+                    pv[u] = in && act ? P.p[idx] : (T)0;
+                    xv[u] = in && act ? P.x[idx] : (T)0;
                 }
-                const T z = P.pinv[n] * rv;
-                arz += (double)rv * (double)z;
-                arr += (double)rv * (double)rv;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t n = n0 + u * vstride;
+                    if (n < P.Ns) {
+                        const int64_t idx = n * k + rfix;
+                        store_dev(P.q + idx, (T)0);
+                        if (act) {
+                            const T pd = fmadd(beta, pv[u], pn[u] * rv[u]);
+                            store_dev(P.p + idx, pd);
+                            store_dev(P.x + idx, xv[u] + alpha * pd);
+                            rv[u] -= alpha * qv[u];
+                            store_dev(P.r + idx, rv[u]);
+                        }
+                        const T z = pn[u] * rv[u];
+                        arz += (double)rv[u] * (double)z;
+                        arr += (double)rv[u] * (double)rv[u];
+                    }
+                }
             }
-            s_red[t] = arz;
-            s_red2[t] = arr;
-            write_partial<WG>(s_red, k, P.part, 1);
-            write_partial<WG>(s_red2, k, P.part, 2);
+            s_red[0][t] = arz;
+            s_red[1][t] = arr;
+            __syncthreads();
+            int Pw = 1;
+            while (Pw < npb) Pw <<= 1;
+            const int j = t / k;
+            for (int w = Pw >> 1; w > 0; w >>= 1) {
+                if (j < w && j + w < npb) {
+                    s_red[0][t] += s_red[0][t + w * k];
+                    s_red[1][t] += s_red[1][t + w * k];
+                }
+                __syncthreads();
+            }
+            if (t < k) {
+                P.part[((int64_t)1 * G + b) * k + t] = s_red[0][t];
+                P.part[((int64_t)2 * G + b) * k + t] = s_red[1][t];
+            }
         }
+        PCG_STAMP(3)
         if (!grid_barrier(P.bar, P.err, P.spin_limit, &s_ok)) return;
 
-        // ---- C: beta, convergence, direction
-        reduce_partials<WG>(P.part, 1, k, s_red, s_tot[0]);
-        reduce_partials<WG>(P.part, 2, k, s_red, s_tot[1]);
+        // ---- beta and convergence per RHS
+        reduce_partials<WG, 2>(P.part + (int64_t)G * k, k, s_red, s_tot);
         if (t < k) {
             const double rz = s_tot[0][t], rr = s_tot[1][t];
             if (s_act[t]) {
@@ -212,17 +300,10 @@ __global__ __launch_bounds__(S * apply_threads(NI)) void k_pcg_persistent(PcgArg
             }
         }
         __syncthreads();
-        if (s_act[rfix]) {
-            const T beta = (T)s_beta[rfix];
-            for (int64_t n = (int64_t)b * npb + t / k; n < P.Ns; n += (int64_t)G * npb) {
-                const int64_t idx = n * k + rfix;
-                P.p[idx] = P.pinv[n] * P.r[idx] + beta * P.p[idx];
-            }
-        }
-        if (!grid_barrier(P.bar, P.err, P.spin_limit, &s_ok)) return;
     }
     if (b == 0 && t < k) {
         P.rho[t] = s_rho[t];
+        P.beta[t] = s_beta[t];
         P.rr[t] = s_rr[t];
         P.active[t] = s_act[t];
         P.iters[t] = s_iters[t];

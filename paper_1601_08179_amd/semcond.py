@@ -20,6 +20,7 @@ PHYSICAL, TRANSFORMED = 0, 1
 COEF_TO_TRANSFORMED, COEF_TO_PHYSICAL, DUAL_TO_TRANSFORMED, DUAL_TO_PHYSICAL = 0, 1, 2, 3
 PREC_F64, PREC_F32, PREC_MIXED_IR = 0, 1, 2
 KERNEL_APPLY, KERNEL_PCG = 0, 1
+CG_STEPWISE, CG_PERSISTENT, CG_AUTO = 0, 1, -1
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -321,7 +322,8 @@ class Context:
                                                 _stream(stream)), self._h)
 
     def autotune(self, k=1, dtype=None, cache_path=None):
-        """Pick the persistent CG launch (element groups S, grid G) by timing; returns (S, G)."""
+        """Pick the CG launch by timing; returns (S, G): the persistent grid, or (0, 0) for one
+        launch per step.  Later solves with persistent=None use the choice."""
         import torch
         code = F32 if dtype == torch.float32 else F64
         S = ctypes.c_int()
@@ -360,8 +362,10 @@ class Context:
 
     def solve(self, f, out=None, tol=1e-10, max_iter=20000, precision=PREC_F64, check_every=8,
               recover_interior=True, x0=None, skel_out=None, inner_tol=1e-5, max_outer=30,
-              rhs_dual=False, persistent=True, stream=None, raise_on_notconv=True):
-        """Solve for nodal right-hand sides f (k, N) or (N,), FP64.  Returns (u, info)."""
+              rhs_dual=False, persistent=None, stream=None, raise_on_notconv=True):
+        """Solve for nodal right-hand sides f (k, N) or (N,), FP64.  Returns (u, info).
+        persistent: True (one persistent CG launch), False (one launch per step) or None
+        (the autotuned choice, else one launch per step)."""
         import torch
         k = self._k_nodal(f, "f")
         if f.dtype != torch.float64:
@@ -380,7 +384,7 @@ class Context:
         o.inner_tol = inner_tol
         o.max_outer = max_outer
         o.rhs_dual = 1 if rhs_dual else 0
-        o.persistent = 1 if persistent else 0
+        o.persistent = CG_AUTO if persistent is None else (CG_PERSISTENT if persistent else CG_STEPWISE)
         info = (SolveInfo * k)()
         allow = (OK, ENOTCONV) if not raise_on_notconv else (OK,)
         _check(_lib.semcond_solve(self._h, _dev(f, "f"), _dev(out, "out"), k, ctypes.byref(o), info,

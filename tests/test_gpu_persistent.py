@@ -65,14 +65,36 @@ def test_autotune_and_cache(lib, tmp_path):
     ctx, op, g, free = both(MESHES["stretched3_p8"]())
     path = str(tmp_path / "tune.txt")
     S, G = ctx.autotune(k=4, dtype=torch.float64, cache_path=path)
-    assert S >= 1 and G >= 1
+    assert (S, G) == (0, 0) or (S >= 1 and G >= 1)       # (0, 0): one launch per step is fastest
     line = open(path).read().split()
     assert [int(v) for v in line[-2:]] == [S, G]
     S2, G2 = ctx.autotune(k=4, dtype=torch.float64, cache_path=path)   # read back from the cache
     assert (S2, G2) == (S, G)
     f = W.random_skeleton_input(op.sizes["N"], k=4, seed=34)
-    u, info = ctx.solve(_t(f), tol=1e-12)
+    u, info = ctx.solve(_t(f), tol=1e-12)                # the tuned launch
     ref = op.recover_interior(f[2], op.solve_condensed(f[2]))
     assert np.abs(u.cpu().numpy()[2] - ref).max() <= 1e-10 * np.abs(ref).max()
     with pytest.raises(lib.SemcondError):
         ctx.autotune(k=3)
+
+
+def test_autotune_cache_entries_both_kinds(lib, tmp_path):
+    """A cache line naming one launch per step (0 0) or a persistent grid is
+    taken as it is; a grid beyond what the device holds is rejected at solve."""
+    import torch
+    ctx, op, g, free = both(MESHES["stretched3_p5"]())
+    f = W.random_skeleton_input(op.sizes["N"], k=2, seed=35)
+    ref = op.recover_interior(f[1], op.solve_condensed(f[1]))
+    key = "%d %d %d %d 2 %d" % (ctx.p, *ctx.n, lib.F64)
+    for S, G in [(0, 0), (1, 16)]:
+        path = str(tmp_path / ("c%d.txt" % S))
+        open(path, "w").write("%s %d %d\n" % (key, S, G))
+        assert ctx.autotune(k=2, dtype=torch.float64, cache_path=path) == (S, G)
+        u, info = ctx.solve(_t(f), tol=1e-12)
+        assert all(i["status"] == 0 for i in info)
+        assert np.abs(u.cpu().numpy()[1] - ref).max() <= 1e-10 * np.abs(ref).max()
+    path = str(tmp_path / "big.txt")
+    open(path, "w").write("%s 1 100000000\n" % key)
+    ctx.autotune(k=2, dtype=torch.float64, cache_path=path)
+    with pytest.raises(lib.SemcondError):
+        ctx.solve(_t(f), tol=1e-12)
