@@ -73,6 +73,128 @@ def cpu_baseline(wmesh, seconds=12.0):
                       "class; no CG vector work) on the same mesh, %.1f s, %s" % (reps, dt, cpu_model())}
 
 
+def _apply_rate(ctx, semcond, torch, k=1, reps=20):
+    """Kernel time (HIP events) of the transformed-basis apply on k random RHS."""
+    xs = torch.randn((ctx.N_s, k) if k > 1 else (ctx.N_s,), dtype=torch.float64, device="cuda")
+    ys = torch.empty_like(xs)
+    for _ in range(3):
+        ctx.apply(xs, out=ys)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    for _ in range(reps):
+        ctx.apply(xs, out=ys)
+    ms, n, _ = ctx.profile_read(semcond.KERNEL_APPLY)
+    ctx.profile_enable(False)
+    return ms / 1e3 / max(n, 1)
+
+
+def suite(args):
+    """Measurements beyond the default line, one JSON line per case:
+    p/aspect-ratio sweep at N = 257^3 (FP64 solve to 1e-10 and apply rate),
+    16 right-hand sides at 24^3 elements, p = 12 (FP64 batched vs mixed
+    precision, each CG launch kind), and the differentiable solve's forward and
+    backward on 8^3 elements, p = 8, k = 8."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1601_08179_amd import autograd as AG
+    from paper_1601_08179_amd import semcond
+
+    def emit(d):
+        print(json.dumps(d), flush=True)
+
+    if "3" in args.suite:
+        for p in (2, 4, 8, 16, 32):
+            for ar in (1, 8, 32, 128):
+                wmesh, f = W.config3(p, ar)
+                ctx = semcond.Context(wmesh)
+                ft = torch.tensor(f, device="cuda")
+                u = torch.zeros_like(ft)
+                ctx.solve(ft, out=u, tol=1e-10)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = ctx.solve(ft, out=u, tol=1e-10)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                ks = _apply_rate(ctx, semcond, torch)
+                bw = 2 * 8 * ctx.N_s / ks / 1e9
+                emit({"case": "p/AR sweep, N=257^3", "p": p, "aspect": ar, "n_e": ctx.n_e, "N": ctx.N,
+                      "N_s": ctx.N_s, "iters": info[0]["iters"], "rel_res": info[0]["rel_res"],
+                      "solve_ms": dt * 1e3, "ns_per_dof_iter": dt / (ctx.N * info[0]["iters"]) * 1e9,
+                      "apply_us": ks * 1e6, "apply_gdof_s": ctx.N / ks / 1e9, "apply_gbs": bw,
+                      "apply_hbm_frac": bw / HBM_PEAK_GBS})
+                del ft, u
+                ctx.close()
+                torch.cuda.empty_cache()
+    if "4" in args.suite:
+        wmesh, f = W.config4()
+        k = f.shape[0]
+        ctx = semcond.Context(wmesh)
+        ft = torch.tensor(f, device="cuda")
+        del f
+        u = torch.zeros_like(ft)
+        res = {"case": "k=16 RHS, 24^3 elements, p=12", "n_e": ctx.n_e, "N": ctx.N, "N_s": ctx.N_s, "k": k}
+        for name, kw in [("f64_stepwise", dict(persistent=False)), ("f64_persistent", dict(persistent=True)),
+                         ("mixed_stepwise", dict(precision=semcond.PREC_MIXED_IR, inner_tol=1e-4,
+                                                 persistent=False)),
+                         ("mixed_persistent", dict(precision=semcond.PREC_MIXED_IR, inner_tol=1e-4,
+                                                   persistent=True))]:
+            ctx.solve(ft, out=u, tol=1e-10, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = ctx.solve(ft, out=u, tol=1e-10, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res[name] = {"ms_per_rhs": dt * 1e3 / k, "iters_max": max(i["iters"] for i in info),
+                         "outer_max": max(i["outer"] for i in info),
+                         "rel_res_max": max(i["rel_res"] for i in info)}
+        for dt_name, dt_t in (("f64", torch.float64), ("f32", torch.float32)):
+            S, G = ctx.autotune(k=k, dtype=dt_t)
+            res["tuned_" + dt_name] = "stepwise" if S == 0 else "persistent S=%d G=%d" % (S, G)
+        ks = _apply_rate(ctx, semcond, torch, k=k, reps=10)
+        bw = 2 * 8 * ctx.N_s * k / ks / 1e9
+        res["apply_k16"] = {"us": ks * 1e6, "gdof_s": ctx.N * k / ks / 1e9, "gbs": bw, "hbm_frac": bw / HBM_PEAK_GBS}
+        emit(res)
+        del ft, u
+        ctx.close()
+        torch.cuda.empty_cache()
+    if "5" in args.suite:
+        wmesh, f, t = W.config5()
+        ctx = semcond.Context(wmesh)
+        ft = torch.tensor(f, device="cuda")
+        tt = torch.tensor(t, device="cuda")
+        lam_e = torch.tensor(wmesh["lam_e"], dtype=torch.float64, requires_grad=True)
+        h = [np.asarray(w) for w in wmesh["widths"]]
+        e1, e2, e3 = np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij")
+        J = (h[0][e1] * h[1][e2] * h[2][e3] / 8.0).transpose(2, 1, 0).reshape(-1)
+        dm = np.stack([J * 4 / h[0][e1].transpose(2, 1, 0).reshape(-1) ** 2,
+                       J * 4 / h[1][e2].transpose(2, 1, 0).reshape(-1) ** 2,
+                       J * 4 / h[2][e3].transpose(2, 1, 0).reshape(-1) ** 2], axis=1)
+        dmetric = torch.tensor(dm, dtype=torch.float64, requires_grad=True)
+        fv = ft.clone().requires_grad_(True)
+        times = []
+        for rep in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            uu = AG.solve(ctx, fv, lam_e, dmetric, tol=1e-12)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            loss = 0.5 * ((uu - tt) ** 2).sum()
+            loss.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            times.append((t1 - t0, t2 - t1))
+            fv.grad = None
+            lam_e.grad = None
+            dmetric.grad = None
+        fw = min(x[0] for x in times)
+        bw_ = min(x[1] for x in times)
+        emit({"case": "differentiable solve, 8^3 elements, p=8, k=8", "N": ctx.N, "forward_ms": fw * 1e3,
+              "backward_ms": bw_ * 1e3})
+        ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,11 +204,16 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--suite", default="", help="extra measurements instead of the default line: "
+                    "any of 3 (p/AR sweep), 4 (16 RHS), 5 (differentiable solve), e.g. --suite 345")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; multi-GPU runs are not part of this build "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.suite:
+        suite(args)
+        return
 
     import torch
 

@@ -26,6 +26,7 @@ class _Solve(torch.autograd.Function):
         fctx.tol = tol
         fctx.precision = precision
         fctx.info = info
+        fctx.devices = (lam_e.device, dmetric.device)
         fctx.save_for_backward(u)
         return u
 
@@ -36,13 +37,15 @@ class _Solve(torch.autograd.Function):
         a, _ = ctx.solve(grad_u.contiguous(), tol=fctx.tol, precision=fctx.precision, rhs_dual=True)
         g = ctx.element_grads(u, a)
         grad_f = ctx.mass_apply(a)
-        return grad_f, g[:, 4], g[:, 1:4], None, None, None
+        dev_lam, dev_d = fctx.devices
+        return grad_f, g[:, 4].to(dev_lam), g[:, 1:4].to(dev_d), None, None, None
 
 
 def solve(ctx, f, lam_e, dmetric, tol=1e-12, precision=semcond.PREC_F64):
     """Differentiable u(f, lambda_e, d_{e,1..3}) on the mesh of `ctx` (a semcond.Context).
 
     f: [k, N] or [N] float64 CUDA tensor; lam_e: [n_e]; dmetric: [n_e, 3]
-    (the metric coefficients d_{e,1}, d_{e,2}, d_{e,3}).  Returns nodal u like f.
+    (the metric coefficients d_{e,1}, d_{e,2}, d_{e,3}), on the host or the
+    device (their gradients come back on the same device).  Returns nodal u like f.
     """
     return _Solve.apply(f, lam_e, dmetric, ctx, tol, precision)

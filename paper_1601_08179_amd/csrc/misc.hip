@@ -601,16 +601,18 @@ template hipError_t launch_cg_init<double>(const double*, double*, const double*
 template hipError_t launch_cg_init<float>(const float*, float*, const float*, float*, float*, int64_t, int, double*,
                                           hipStream_t);
 
-// One block of B = k * floor(1024/k) threads: thread t sums RHS t mod k over
-// the parts t/k, t/k + B/k, ... (all loads of a thread issued together), a
-// fixed-shape tree adds the B/k sums; then the CG scalar step per RHS.
-constexpr int kReduceThreads = 1024;
+// One block of B = k * floor(256/k) threads: thread t sums RHS t mod k over
+// the parts t/k, t/k + B/k, ... (all loads of a thread issued together).  For
+// k a power of two up to 64 the B/k sums of one RHS are combined inside each
+// wave by a fixed xor-shuffle tree and the waves' sums in wave order; otherwise
+// a fixed-shape shared-memory tree adds them.  Then the CG scalar step per RHS.
+constexpr int kReduceThreads = 256;
 
 __global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __restrict__ partials, int64_t nparts,
                                                               int nq, int k, CgState s, int mode) {
     __shared__ double sh[3][kReduceThreads];
     const int t = threadIdx.x, r = t % k, j = t / k, npb = blockDim.x / k;
-    constexpr int U = 8;
+    constexpr int U = 16;
     // per-RHS state read before anything is written, so that no load waits on a store
     int act = 0, its = 0;
     double rho = 0.0, bb = 0.0, tol2 = 0.0;
@@ -636,20 +638,47 @@ __global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __re
 #pragma unroll
             for (int u = 0; u < U; ++u) acc[q] += v[q][u];
     }
+    const bool pow2 = k <= 64 && (k & (k - 1)) == 0;
+    if (pow2) {
+        // lanes l and l ^ off (off >= k, a multiple of k) hold the same RHS
+        for (int off = 32; off >= k; off >>= 1) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) sh[q][t] = acc[q];
-    __syncthreads();
-    int P = 1;
-    while (P < npb) P <<= 1;
-    for (int w = P >> 1; w > 0; w >>= 1) {
-        if (j < w && j + w < npb) {
+            for (int q = 0; q < 3; ++q) acc[q] += __shfl_xor(acc[q], off, 64);
+        }
+        const int lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+        if (lane < k) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) sh[q][t] += sh[q][t + w * k];
+            for (int q = 0; q < 3; ++q) sh[q][wv * k + lane] = acc[q];
         }
         __syncthreads();
+        if (t < k) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                double sum = sh[q][t];
+                for (int w = 1; w < nw; ++w) sum += sh[q][w * k + t];
+                acc[q] = sum;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) sh[q][t] = acc[q];
+        __syncthreads();
+        int P = 1;
+        while (P < npb) P <<= 1;
+        for (int w = P >> 1; w > 0; w >>= 1) {
+            if (j < w && j + w < npb) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) sh[q][t] += sh[q][t + w * k];
+            }
+            __syncthreads();
+        }
+        if (t < k) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc[q] = sh[q][t];
+        }
     }
     if (t < k) {
-        const double t0 = sh[0][t], t1 = sh[1][t], t2 = sh[2][t];
+        const double t0 = acc[0], t1 = acc[1], t2 = acc[2];
         if (mode == RED_INIT) {
             const double rz = t0, rr = t1, b2 = t2;
             s.rho[r] = rz;

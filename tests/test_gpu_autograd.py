@@ -107,3 +107,29 @@ def test_grads_vs_central_fd_config5(lib):
     for fd, ad in checks:
         print("directional FD %.12e autograd %.12e noise %.2e" % (fd, ad, noise))
         assert abs(fd - ad) <= 1e-6 * abs(ad) + noise
+
+
+def test_host_coefficient_inputs_get_host_gradients(lib):
+    """lambda_e and d_{e,1..3} given as host tensors: their gradients come back
+    on the host and equal those of device inputs."""
+    import torch
+    from paper_1601_08179_amd import autograd
+    rng = np.random.default_rng(22)
+    lam_e = np.exp(rng.uniform(np.log(0.1), np.log(100), 8))
+    wmesh = W.mesh(3, (2, 2, 2), lam=None, lam_e=lam_e)
+    N = W.num_nodes(3, (2, 2, 2))
+    f = rng.standard_normal((1, N))
+    t = rng.standard_normal((1, N))
+    d, J = _metric(wmesh)
+    grads = []
+    for dev in ("cpu", "cuda"):
+        ctx, idx, ft, tt = _setup(wmesh, f, t)
+        lam_t = torch.tensor(lam_e, device=dev, requires_grad=True)
+        dm_t = torch.tensor(d[:, 1:], device=dev, requires_grad=True)
+        loss = _loss(autograd.solve(ctx, ft, lam_t, dm_t, tol=1e-14), tt, idx)
+        loss.backward()
+        assert lam_t.grad.device.type == dev and dm_t.grad.device.type == dev
+        grads.append((lam_t.grad.cpu().numpy(), dm_t.grad.cpu().numpy(), ft.grad.cpu().numpy()))
+        ctx.close()
+    for a, b in zip(*grads):   # the scatter's atomic order may differ between runs
+        np.testing.assert_allclose(a, b, rtol=1e-10, atol=1e-10 * np.abs(b).max())
