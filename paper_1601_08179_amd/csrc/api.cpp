@@ -53,6 +53,7 @@ struct semcond_ctx {
     DevTables<double> t64;
     DevTables<float> t32;
     double* d_widths = nullptr;  // n1 + n2 + n3
+    double* d_ax = nullptr;      // [n1 + n2 + n3][2]: h/2, 4/h^2
     double* d_lam_e = nullptr;
     double* d_dcoef = nullptr;
     double* d_diag = nullptr;    // [N_s]
@@ -167,10 +168,12 @@ int check_k(semcond_ctx* c, int k) {
 
 template <typename T>
 const DevTab<T>& tabs(semcond_ctx* c);
+
 template <>
 const DevTab<double>& tabs<double>(semcond_ctx* c) { return c->t64.tab; }
 template <>
 const DevTab<float>& tabs<float>(semcond_ctx* c) { return c->t32.tab; }
+
 
 template <typename T>
 const T* pinv(semcond_ctx* c);
@@ -200,6 +203,20 @@ int profile_end(semcond_ctx* c, hipStream_t st) {
     return SEMCOND_OK;
 }
 
+// Apply arguments of this context (operand, result and options set by the caller).
+template <typename T>
+ApplyArgs<T> apply_args(semcond_ctx* c) {
+    ApplyArgs<T> a;
+    a.g = c->geo;
+    a.tab = tabs<T>(c);
+    a.u = nullptr;
+    a.v = nullptr;
+    a.k = 0;
+    a.energy = nullptr;
+    a.e_begin = 0;
+    return a;
+}
+
 template <typename T>
 hipError_t launch_apply(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t st) {
     return launch_apply_tpt<T>(a, n_elem, st);
@@ -212,14 +229,11 @@ template <typename T>
 int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, double* energy, hipStream_t st,
                       bool v_is_zero = false, const T* dir_r = nullptr, const double* dir_beta = nullptr) {
     if (!v_is_zero) HIPCHK(c, launch_fill<T>(v, c->N_s * k, (T)0, st));
-    ApplyArgs<T> a;
-    a.g = c->geo;
-    a.tab = tabs<T>(c);
+    ApplyArgs<T> a = apply_args<T>(c);
     a.u = u;
     a.v = v;
     a.k = k;
     a.energy = energy;
-    a.e_begin = 0;
     if (dir_r) {
         if (!dir_beta) return fail(c, SEMCOND_EINVAL, "fused direction needs beta");
         a.dir_r = dir_r;
@@ -467,8 +481,7 @@ int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, in
     // barrier words and error flag start at zero (bit pattern of 0.0f)
     HIPCHK(c, launch_fill<float>((float*)bar, kBarWords, 0.0f, st));
     PcgArgs<T> P;
-    P.A.g = c->geo;
-    P.A.tab = tabs<T>(c);
+    P.A = apply_args<T>(c);
     P.A.u = p;
     P.A.v = q;
     P.A.k = k;
@@ -664,6 +677,7 @@ int semcond_destroy(semcond_ctx* c) {
     hipFree(c->t64.buf);
     hipFree(c->t32.buf);
     hipFree(c->d_widths);
+    hipFree(c->d_ax);
     hipFree(c->d_lam_e);
     hipFree(c->d_dcoef);
     hipFree(c->d_diag);
@@ -767,6 +781,17 @@ int semcond_create(const semcond_mesh* m, void* stream, semcond_ctx** out) {
     c->geo.hx = c->d_widths;
     c->geo.hy = c->d_widths + m->n[0];
     c->geo.hz = c->d_widths + m->n[0] + m->n[1];
+    {
+        // per axis and element: h/2 and 4/h^2
+        std::vector<double> ax(2 * (size_t)nw);
+        for (int i = 0; i < nw; ++i) {
+            ax[2 * i] = 0.5 * hw[i];
+            ax[2 * i + 1] = 4.0 / (hw[i] * hw[i]);
+        }
+        CHK(hipMalloc(&c->d_ax, ax.size() * sizeof(double)));
+        CHK(hipMemcpy(c->d_ax, ax.data(), ax.size() * sizeof(double), hipMemcpyHostToDevice));
+        c->geo.ax = c->d_ax;
+    }
     CHK(hipMalloc(&c->d_diag, c->N_s * sizeof(double)));
     CHK(hipMalloc(&c->d_pinv64, c->N_s * sizeof(double)));
     CHK(hipMalloc(&c->d_pinv32, c->N_s * sizeof(float)));

@@ -68,8 +68,8 @@ struct ApplySmem {
 // must make the same sequence of calls (the function uses workgroup
 // barriers).  live = false runs the same code without any global write.
 template <typename T, int NI, bool DIR>
-__device__ void apply_element(const ApplyArgs<T>& A, int64_t e, ApplySmem<T, NI>& sm, double* en_acc,
-                              int tid, bool live, const double* beta) {
+__device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem<T, NI>& sm, double* en_acc,
+                                     int tid, bool live, const double* beta) {
     constexpr int NI2 = NI * NI;
     constexpr int NT = apply_threads(NI);
     constexpr int NFACE = 6 * NI2;
@@ -348,6 +348,371 @@ __device__ void apply_element(const ApplyArgs<T>& A, int64_t e, ApplySmem<T, NI>
 #undef UF
 #undef UE
 #undef UV
+}
+
+// Wave-uniform skeleton entities of element (e1,e2,e3): face bases (w, e, s,
+// n, b, t), edge bases of the three directions at boundary bits (0, 0), the
+// vertex base, and the Dirichlet flags of the element's six boundary planes.
+// [N_s][k] offsets stay below 2^31, so node indices are 32-bit.
+struct ElemEnt {
+    uint32_t fb[6];
+    uint32_t eb[3];
+    uint32_t vb;
+    bool cx0, cx1, cy0, cy1, cz0, cz1;
+};
+
+__device__ inline void elem_entities(const Layout& L, int e1, int e2, int e3, ElemEnt& E) {
+    E.fb[0] = (uint32_t)fx_base(L, e3, e2, e1);
+    E.fb[1] = (uint32_t)fx_base(L, e3, e2, e1 + 1);
+    E.fb[2] = (uint32_t)fy_base(L, e3, e2, e1);
+    E.fb[3] = (uint32_t)fy_base(L, e3, e2 + 1, e1);
+    E.fb[4] = (uint32_t)fz_base(L, e3, e2, e1);
+    E.fb[5] = (uint32_t)fz_base(L, e3 + 1, e2, e1);
+    E.eb[0] = (uint32_t)ex_base(L, e3, e2, e1);
+    E.eb[1] = (uint32_t)ey_base(L, e3, e2, e1);
+    E.eb[2] = (uint32_t)ez_base(L, e3, e2, e1);
+    E.vb = (uint32_t)v_base(L, e3, e2, e1);
+    E.cx0 = xcon(L, e1);
+    E.cx1 = xcon(L, e1 + 1);
+    E.cy0 = ycon(L, e2);
+    E.cy1 = ycon(L, e2 + 1);
+    E.cz0 = zcon(L, e3);
+    E.cz1 = zcon(L, e3 + 1);
+}
+
+// Node and Dirichlet flag of the thread's edge node in direction par (edge
+// X(jb,kb), Y(ib,kb), Z(ib,jb) with bits (b0, b1), node m) and of its vertex
+// (ib, jb, kb).
+template <int NI>
+__device__ inline void edge_node(const Layout& L, const ElemEnt& E, int par, int b0, int b1, int m, uint32_t* node,
+                                 bool* con) {
+    const uint32_t n1 = (uint32_t)L.n1, n2 = (uint32_t)L.n2;
+    const uint32_t s0 = par == 0 ? n1 * NI : (uint32_t)NI;
+    const uint32_t s1 = par == 0 ? (n2 + 1) * n1 * NI : (par == 1 ? n2 * (n1 + 1) * NI : (n1 + 1) * NI);
+    *node = E.eb[par] + b0 * s0 + b1 * s1 + m;
+    const bool c0 = par == 0 ? (b0 ? E.cy1 : E.cy0) : (b0 ? E.cx1 : E.cx0);
+    const bool c1 = par == 2 ? (b1 ? E.cy1 : E.cy0) : (b1 ? E.cz1 : E.cz0);
+    *con = c0 || c1;
+}
+__device__ inline void vertex_node(const Layout& L, const ElemEnt& E, int ib, int jb, int kb, uint32_t* node,
+                                   bool* con) {
+    const uint32_t n1 = (uint32_t)L.n1, n2 = (uint32_t)L.n2;
+    *node = E.vb + ib + jb * (n1 + 1) + kb * (n2 + 1) * (n1 + 1);
+    *con = (ib ? E.cx1 : E.cx0) || (jb ? E.cy1 : E.cy0) || (kb ? E.cz1 : E.cz0);
+}
+
+// One thread's gathered values of one (element, RHS): its face slot of the
+// six faces, its edge node in the three directions, its vertex.  With DIR
+// also r and P^-1 at the same nodes.  Constrained or absent slots hold 0.
+template <typename T, bool DIR>
+struct Gathered {
+    T f[6], e[3], v;
+    T rf[6], re[3], rv;
+    T pf[6], pe[3], pv;
+};
+
+// Issue the loads of item (e, r); nothing is waited for here.
+template <typename T, int NI, bool DIR>
+__device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live, uint32_t r, int t,
+                                    Gathered<T, DIR>& G) {
+    constexpr int NI2 = NI * NI;
+    const Layout& L = A.g.L;
+    const uint32_t k = (uint32_t)A.k;
+    int e1, e2, e3;
+    elem_index(L, live ? e : 0, &e1, &e2, &e3);
+    ElemEnt E;
+    elem_entities(L, e1, e2, e3, E);
+    const bool fcon[6] = {E.cx0, E.cx1, E.cy0, E.cy1, E.cz0, E.cz1};
+    auto load = [&](uint32_t node, bool on, T& u, T& rr, T& pp) {
+        u = (T)0;
+        rr = (T)0;
+        pp = (T)0;
+        if (on) {
+            u = A.u[node * k + r];
+            if constexpr (DIR) {
+                rr = A.dir_r[node * k + r];
+                pp = A.dir_pinv[node];
+            }
+        }
+    };
+    const bool fown = live && t < NI2;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) load(E.fb[f] + (uint32_t)t, fown && !fcon[f], G.f[f], G.rf[f], G.pf[f]);
+    const int eq = t / NI, em = t - (t / NI) * NI;
+    const bool eown = live && t < 4 * NI;
+#pragma unroll
+    for (int par = 0; par < 3; ++par) {
+        uint32_t node;
+        bool con;
+        edge_node<NI>(L, E, par, eq & 1, (eq >> 1) & 1, em, &node, &con);
+        load(node, eown && !con, G.e[par], G.re[par], G.pe[par]);
+    }
+    {
+        uint32_t node;
+        bool con;
+        vertex_node(L, E, t & 1, (t >> 1) & 1, (t >> 2) & 1, &node, &con);
+        load(node, live && t < 8 && !con, G.v, G.rv, G.pv);
+    }
+}
+
+// Element body for n_I <= 15: the eigenspace cube lives in LDS.  Entity bases
+// and Dirichlet flags are wave-uniform (scalar) values; the 1D coefficients at
+// a uniform index come from the launch arguments.  Thread t < n_I^2 owns the
+// face slot (s1, s2) = (t / n_I, t mod n_I) of every face and the eigenspace
+// column (k, s1, s2), k = 0..n_I-1; thread t < 4 n_I owns edge node t mod n_I
+// of edge t / n_I of each direction; thread t < 8 owns vertex t.
+// With ONE the group computes the single item (element e0, RHS r0) (e0 at or
+// beyond n_end: without global writes); otherwise it walks `count` elements
+// e0, e0 + stride, ... and for each the right-hand sides r0 .. r0 + nr - 1.  (A
+// loop keeps the coefficient scalars live across items; the single-item form
+// lets them live only where they are used.)
+template <typename T, int NI, bool DIR, bool ONE>
+__device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t stride, int64_t count, int64_t n_end,
+                                    uint32_t r0, uint32_t nr, ApplySmem<T, NI>& sm, double* en_acc, int tid,
+                                    const double* beta) {
+    constexpr int NI2 = NI * NI;
+    constexpr int NT = apply_threads(NI);
+    constexpr int NFACE = 6 * NI2;
+    constexpr int NEDGE = 12 * NI;
+    T* const F = sm.F;
+    T* const Wv = sm.Wv;
+    double* const red = sm.red;
+    const Layout& L = A.g.L;
+    const int t = tid;
+    const uint32_t k = (uint32_t)A.k;
+    const T m0 = A.tab.m0, K00 = A.tab.K00, K0p = A.tab.K0p, m02 = m0 * m0;
+
+    // per-thread position and 1D coefficients of the face slot (s1 slow, s2 fast),
+    // edge node and vertex: the same for every element
+    const bool fown = t < NI2, eown = t < 4 * NI, vown = t < 8;
+    const int s1 = t / NI, s2 = t - (t / NI) * NI;
+    const int eq = t / NI, em = s2;                      // edge qq = b0 + 2 b1, node m
+    const int eb0 = eq & 1, eb1 = (eq >> 1) & 1;
+    const int vib = t & 1, vjb = (t >> 1) & 1, vkb = (t >> 2) & 1;
+    T ta1 = 0, tb1 = 0, tl1 = 0, ta2 = 0, tb2 = 0, tl2 = 0;
+    if (fown || eown) {
+        ta1 = A.tab.a[s1 < NI ? s1 : 0];
+        tb1 = A.tab.b[s1 < NI ? s1 : 0];
+        tl1 = A.tab.lam[s1 < NI ? s1 : 0];
+        ta2 = A.tab.a[s2];
+        tb2 = A.tab.b[s2];
+        tl2 = A.tab.lam[s2];
+    }
+
+#define UE(q, m) F[NFACE + (q) * NI + (m)]
+#define UV(q) F[NFACE + NEDGE + (q)]
+
+    // the 1D coefficients at wave-uniform indices: an LDS copy (broadcast reads)
+    T* const ctL = sm.tl;
+    T* const ctA = sm.tl + NI;
+    T* const ctB = sm.tl + 2 * NI;
+    if (t < NI) {
+        ctL[t] = A.tab.lam[t];
+        ctA[t] = A.tab.a[t];
+        ctB[t] = A.tab.b[t];
+    }  // read after the first item's gather barrier
+
+    auto item = [&](const int64_t e, const bool live, const uint32_t r) __attribute__((always_inline)) {
+        const T bt = DIR ? (T)beta[r] : (T)0;
+        Gathered<T, DIR> G;
+        gather_issue<T, NI, DIR>(A, e, live, r, t, G);
+        // ---- commit the gathered values (R^T) to LDS
+        {
+            auto val = [&](T u, T rr, T pp) -> T {
+                if constexpr (DIR) return fmadd(bt, u, pp * rr);
+                return u;
+            };
+            if (fown) {
+#pragma unroll
+                for (int f = 0; f < 6; ++f) F[f * NI2 + t] = val(G.f[f], G.rf[f], G.pf[f]);
+            }
+            if (eown) {
+#pragma unroll
+                for (int par = 0; par < 3; ++par) F[NFACE + par * 4 * NI + t] = val(G.e[par], G.re[par], G.pe[par]);
+            }
+            if (vown) UV(t) = val(G.v, G.rv, G.pv);
+        }
+        __syncthreads();
+
+        int e1, e2, e3;
+        elem_index(L, live ? e : 0, &e1, &e2, &e3);
+        double dd[4];
+        elem_metric(A.g, live ? e : 0, e1, e2, e3, dd);
+        const T d0 = (T)dd[0], d1 = (T)dd[1], d2 = (T)dd[2], d3 = (T)dd[3];
+        ElemEnt E;
+        elem_entities(L, e1, e2, e3, E);
+        const bool fcon[6] = {E.cx0, E.cx1, E.cy0, E.cy1, E.cz0, E.cz1};
+
+        // ---- condensed part (Table 2): v = D^-1 sum_f H~_EF u_f on column (k, s1, s2);
+        // the b/t line reductions along k stay in registers
+        T accb = 0, acct = 0;
+        if (fown) {
+            const T Dij = d0 + d1 * tl2 + d2 * tl1;
+            const T wa = d1 * ta2, wb = d1 * tb2, sa = d2 * ta1, sb = d2 * tb1;
+            const T ub = d3 * F[4 * NI2 + t], ut = d3 * F[5 * NI2 + t];
+#pragma unroll
+            for (int kk = 0; kk < NI; ++kk) {
+                const T ak = ctA[kk], bk = ctB[kk];
+                const T uc = wa * F[kk * NI + s1] + wb * F[NI2 + kk * NI + s1] + sa * F[2 * NI2 + kk * NI + s2] +
+                             sb * F[3 * NI2 + kk * NI + s2] + ak * ub + bk * ut;
+                const T v = uc * recip<T>(Dij + d3 * ctL[kk]);
+                Wv[kk * NI2 + t] = v;
+                accb += ak * v;
+                acct += bk * v;
+            }
+        }
+        __syncthreads();
+
+        double en = 0.0;
+        T* const vr = A.v + r;
+        // ---- faces: primary part (Sec. 6) + condensed part (Table 2), pairs w/e, s/n, b/t.
+        // Face f has slots (k,j), (k,j), (k,i), (k,i), (j,i), (j,i); bordering edges (UE index)
+        // fast-lo, fast-hi, slow-lo, slow-hi: w {8,10,4,6} e {9,11,5,7} s {8,9,0,2}
+        // n {10,11,1,3} b {4,5,0,1} t {6,7,2,3}.
+        if (fown) {
+            T cnd[6];
+            {
+                T sw = 0, se = 0, ss = 0, sn = 0;
+#pragma unroll
+                for (int m = 0; m < NI; ++m) {
+                    const T vw = Wv[t * NI + m];              // line along i at (k, j) = (s1, s2)
+                    const T vs = Wv[s1 * NI2 + m * NI + s2];  // line along j at (k, i) = (s1, s2)
+                    const T am = ctA[m], bm = ctB[m];
+                    sw += am * vw;
+                    se += bm * vw;
+                    ss += am * vs;
+                    sn += bm * vs;
+                }
+                cnd[0] = -d1 * sw;
+                cnd[1] = -d1 * se;
+                cnd[2] = -d2 * ss;
+                cnd[3] = -d2 * sn;
+                cnd[4] = -d3 * accb;
+                cnd[5] = -d3 * acct;
+            }
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                constexpr int efl_t[6] = {8, 9, 8, 10, 4, 6}, efh_t[6] = {10, 11, 9, 11, 5, 7};
+                constexpr int esl_t[6] = {4, 5, 0, 1, 0, 2}, esh_t[6] = {6, 7, 2, 3, 1, 3};
+                const T dn = f < 2 ? d1 : (f < 4 ? d2 : d3);
+                const T dfast = f < 2 ? d2 : d1;
+                const T dslow = f < 4 ? d3 : d2;
+                const T uf = F[f * NI2 + t];
+                const T out = (d0 * m0 + dn * K00 + dfast * m0 * tl2 + dslow * m0 * tl1) * uf +
+                              dn * K0p * F[(f ^ 1) * NI2 + t] +
+                              dfast * m0 * (ta2 * UE(efl_t[f], s1) + tb2 * UE(efh_t[f], s1)) +
+                              dslow * m0 * (ta1 * UE(esl_t[f], s2) + tb1 * UE(esh_t[f], s2)) + cnd[f];
+                if (!fcon[f] && live) {
+                    atomic_add(vr + (E.fb[f] + (uint32_t)t) * k, out);
+                    en += (double)uf * (double)out;
+                }
+            }
+        }
+        // ---- edges, one direction per round: edge q = 4 par + b0 + 2 b1; the face
+        // couplings are line sums of the two bordering faces.
+        if (eown) {
+#pragma unroll
+            for (int par = 0; par < 3; ++par) {
+                const T dpar = par == 0 ? d1 : (par == 1 ? d2 : d3);
+                const T do1 = par == 0 ? d2 : d1;
+                const T do2 = par == 2 ? d2 : d3;
+                const T dg0 = d0 * m02 + (do1 + do2) * m0 * K00;
+                const int q = 4 * par + eq;
+                // X(jb,kb): sum_j c^jb_j b/t(kb)[j][m], sum_k c^kb_k s/n(jb)[k][m]
+                // Y(ib,kb): sum_i c^ib_i b/t(kb)[m][i], sum_k c^kb_k w/e(ib)[k][m]
+                // Z(ib,jb): sum_i c^ib_i s/n(jb)[m][i], sum_j c^jb_j w/e(ib)[m][j]
+                const int f1 = (par == 2 ? 2 : 4) + eb1, f2 = (par == 0 ? 2 : 0) + eb0;
+                const int base1 = f1 * NI2 + (par == 0 ? em : em * NI);
+                const int base2 = f2 * NI2 + (par == 2 ? em * NI : em);
+                constexpr int st1_t[3] = {NI, 1, 1}, st2_t[3] = {NI, NI, 1};
+                // both coefficient rows, then the thread's pick (no per-term selects)
+                T l1a = 0, l1b = 0, l2a = 0, l2b = 0;
+#pragma unroll
+                for (int m2 = 0; m2 < NI; ++m2) {
+                    const T am = ctA[m2], bm = ctB[m2];
+                    const T x1 = F[base1 + m2 * st1_t[par]], x2 = F[base2 + m2 * st2_t[par]];
+                    l1a += am * x1;
+                    l1b += bm * x1;
+                    l2a += am * x2;
+                    l2b += bm * x2;
+                }
+                const T l1 = eb0 ? l1b : l1a, l2 = eb1 ? l2b : l2a;
+                const int vlo = par == 0 ? 2 * eb0 + 4 * eb1 : (par == 1 ? eb0 + 4 * eb1 : eb0 + 2 * eb1);
+                const int vhi = vlo + (par == 0 ? 1 : (par == 1 ? 2 : 4));
+                const T ue = UE(q, em);
+                // tl2, ta2, tb2 are the 1D coefficients at the edge node m = s2
+                const T out = (dg0 + dpar * m02 * tl2) * ue + m0 * K0p * (do1 * UE(q ^ 1, em) + do2 * UE(q ^ 2, em)) +
+                              dpar * m02 * (ta2 * UV(vlo) + tb2 * UV(vhi)) + m0 * (do1 * l1 + do2 * l2);
+                uint32_t node;
+                bool con;
+                edge_node<NI>(L, E, par, eb0, eb1, em, &node, &con);
+                if (!con && live) {
+                    atomic_add(vr + node * k, out);
+                    en += (double)ue * (double)out;
+                }
+            }
+        }
+        // ---- vertices
+        if (vown) {
+            const int q = t;
+            T sxa = 0, sxb = 0, sya = 0, syb = 0, sza = 0, szb = 0;
+#pragma unroll
+            for (int m2 = 0; m2 < NI; ++m2) {
+                const T am = ctA[m2], bm = ctB[m2];
+                const T x = UE(vjb + 2 * vkb, m2), y = UE(4 + vib + 2 * vkb, m2), z = UE(8 + vib + 2 * vjb, m2);
+                sxa += am * x;
+                sxb += bm * x;
+                sya += am * y;
+                syb += bm * y;
+                sza += am * z;
+                szb += bm * z;
+            }
+            const T sx = vib ? sxb : sxa, sy = vjb ? syb : sya, sz = vkb ? szb : sza;
+            const T out = (d0 * m02 * m0 + (d1 + d2 + d3) * m02 * K00) * UV(q) +
+                          m02 * K0p * (d1 * UV(q ^ 1) + d2 * UV(q ^ 2) + d3 * UV(q ^ 4)) +
+                          m02 * (d1 * sx + d2 * sy + d3 * sz);
+            uint32_t node;
+            bool con;
+            vertex_node(L, E, vib, vjb, vkb, &node, &con);
+            if (!con && live) {
+                atomic_add(vr + node * k, out);
+                en += (double)UV(q) * (double)out;
+            }
+        }
+        if (A.energy || en_acc) {
+            en = wave_sum(en);
+            if ((t & 63) == 0) red[t >> 6] = en;
+            __syncthreads();
+            if (t == 0) {
+                double sum = 0.0;
+                for (int w = 0; w < NT / 64; ++w) sum += red[w];
+                if (A.energy && live) A.energy[e * k + r] = sum;
+                if (en_acc && live) en_acc[r] += sum;
+            }
+        }
+        __syncthreads();
+    };
+    if constexpr (ONE) {
+        item(e0, e0 < n_end, r0);
+    } else {
+        for (int64_t i = 0; i < count; ++i) {
+            const int64_t e = e0 + i * stride;
+            for (uint32_t r = r0; r < r0 + nr; ++r) item(e, e < n_end, r);
+        }
+    }
+#undef UE
+#undef UV
+}
+
+// One element (all k right-hand sides); live = false runs the same code
+// without any global write.
+template <typename T, int NI, bool DIR>
+__device__ void apply_element(const ApplyArgs<T>& A, int64_t e, ApplySmem<T, NI>& sm, double* en_acc,
+                              int tid, bool live, const double* beta) {
+    if constexpr (NI <= 15)
+        apply_elements_cube<T, NI, DIR, false>(A, e, 1, 1, live ? e + 1 : e, 0, (uint32_t)A.k, sm, en_acc, tid, beta);
+    else
+        apply_element_planes<T, NI, DIR>(A, e, sm, en_acc, tid, live, beta);
 }
 
 }  // namespace semcond

@@ -27,45 +27,53 @@ struct DevTab {
 
 // Mesh metric data.  d_e = (h1 h2 h3/8)(lambda, 4/h1^2, 4/h2^2, 4/h3^2)
 // (Sec. 3, eq. metriccoeffelement) from per-axis widths and lambda, unless a
-// per-element table dcoef[n_e][4] is given.
+// per-element table dcoef[n_e][4] is given.  ax holds per axis and element
+// (h/2, 4/h^2), formed on the host, so kernels only multiply.
 struct Geo {
     Layout L;
     const double* hx;
     const double* hy;
     const double* hz;
+    const double* ax;     // [n1 + n2 + n3][2]
     double lam;
     const double* lam_e;  // nullable, n_e
     const double* dcoef;  // nullable, n_e x 4 (column 0 unused when lam_e is given)
 };
 
+// e = e1 + n1 (e2 + n2 e3); element counts stay below 2^31.
 __device__ inline void elem_index(const Layout& L, int64_t e, int* e1, int* e2, int* e3) {
-    *e1 = (int)(e % L.n1);
-    int64_t r = e / L.n1;
-    *e2 = (int)(r % L.n2);
-    *e3 = (int)(r / L.n2);
+    const uint32_t ee = (uint32_t)e, n1 = (uint32_t)L.n1, n2 = (uint32_t)L.n2;
+    const uint32_t q = ee / n1, z = q / n2;
+    *e1 = (int)(ee - q * n1);
+    *e2 = (int)(q - z * n2);
+    *e3 = (int)z;
+}
+
+// J_e = h1 h2 h3 / 8 (factor of the GLL-lumped element mass matrix).
+__device__ inline double elem_jacobian(const Geo& g, int e1, int e2, int e3) {
+    const double* a1 = g.ax + 2 * e1;
+    const double* a2 = g.ax + 2 * (g.L.n1 + e2);
+    const double* a3 = g.ax + 2 * (g.L.n1 + g.L.n2 + e3);
+    return a1[0] * a2[0] * a3[0];
 }
 
 __device__ inline void elem_metric(const Geo& g, int64_t e, int e1, int e2, int e3, double d[4]) {
     if (g.dcoef) {
         // metric terms from the table; d_0 = J_e lambda_e when lambda_e is also given
-        d[0] = g.lam_e ? g.hx[e1] * g.hy[e2] * g.hz[e3] / 8.0 * g.lam_e[e] : g.dcoef[4 * e + 0];
+        d[0] = g.lam_e ? elem_jacobian(g, e1, e2, e3) * g.lam_e[e] : g.dcoef[4 * e + 0];
         d[1] = g.dcoef[4 * e + 1];
         d[2] = g.dcoef[4 * e + 2];
         d[3] = g.dcoef[4 * e + 3];
         return;
     }
-    const double h1 = g.hx[e1], h2 = g.hy[e2], h3 = g.hz[e3];
-    const double J = h1 * h2 * h3 / 8.0;
-    const double lam = g.lam_e ? g.lam_e[e] : g.lam;
-    d[0] = J * lam;
-    d[1] = J * 4.0 / (h1 * h1);
-    d[2] = J * 4.0 / (h2 * h2);
-    d[3] = J * 4.0 / (h3 * h3);
-}
-
-// J_e = h1 h2 h3 / 8 (factor of the GLL-lumped element mass matrix).
-__device__ inline double elem_jacobian(const Geo& g, int e1, int e2, int e3) {
-    return g.hx[e1] * g.hy[e2] * g.hz[e3] / 8.0;
+    const double* a1 = g.ax + 2 * e1;
+    const double* a2 = g.ax + 2 * (g.L.n1 + e2);
+    const double* a3 = g.ax + 2 * (g.L.n1 + g.L.n2 + e3);
+    const double J = a1[0] * a2[0] * a3[0];
+    d[0] = J * (g.lam_e ? g.lam_e[e] : g.lam);
+    d[1] = J * a1[1];
+    d[2] = J * a2[1];
+    d[3] = J * a3[1];
 }
 
 // 1/x from the hardware reciprocal refined by Newton steps (two in FP64, one

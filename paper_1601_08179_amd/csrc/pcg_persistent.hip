@@ -185,11 +185,8 @@ __global__ __launch_bounds__(S * apply_threads(NI), 2) void k_pcg_persistent(Pcg
         // ---- A: q = H~^ p with p = beta p + z formed at the gather, energies p.q
         if (lt < k) s_en[sub][lt] = 0.0;
         __syncthreads();
-        for (int64_t m = 0; m < rounds; ++m) {
-            const int64_t e = (m * G + b) * S + sub;
-            const bool live = e < P.n_e;
-            apply_element<T, NI, true>(P.A, live ? e : 0, sm[sub], s_en[sub], lt, live, s_beta);
-        }
+        apply_elements_cube<T, NI, true, false>(P.A, (int64_t)b * S + sub, (int64_t)G * S, rounds, P.n_e, 0,
+                                                (uint32_t)k, sm[sub], s_en[sub], lt, s_beta);
         if (t < k) {
             double s = 0.0;
             for (int g = 0; g < S; ++g) s += s_en[g][t];
