@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -225,14 +226,20 @@ hipError_t launch_apply(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t st) {
 // v = H~^ u (transformed).  v is zeroed first unless v_is_zero.  energy: optional [n_e][k].
 // With dir_r set, the operand is the CG direction fmadd(beta, u, pinv r) (u:
 // previous direction) and q = v must be zero on entry.
+// Multivector layouts: [N_s][k] (RHS innermost, the library's interface) and
+// [k][N_s] (RHS-major, inside the conjugate gradients).
+enum VecLayout { NODE_MAJOR = 0, RHS_MAJOR = 1 };
+
 template <typename T>
-int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, double* energy, hipStream_t st,
+int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, double* energy, hipStream_t st,
                       bool v_is_zero = false, const T* dir_r = nullptr, const double* dir_beta = nullptr) {
     if (!v_is_zero) HIPCHK(c, launch_fill<T>(v, c->N_s * k, (T)0, st));
     ApplyArgs<T> a = apply_args<T>(c);
     a.u = u;
     a.v = v;
     a.k = k;
+    a.ns = lay == RHS_MAJOR ? 1u : (uint32_t)k;
+    a.rs = lay == RHS_MAJOR ? (uint32_t)c->N_s : 1u;
     a.energy = energy;
     if (dir_r) {
         if (!dir_beta) return fail(c, SEMCOND_EINVAL, "fused direction needs beta");
@@ -302,7 +309,7 @@ int condense_rhs64(semcond_ctx* c, const double* f, double* fhat, int k, hipStre
 
 struct CgWork {
     CgState s;
-    double* partials;  // [3][kVecBlocks][k]
+    double* partials;  // [3][vec_blocks(k)][k] (room for [3][kVecBlocks][k])
     double* energy;    // [n_e][k]
 };
 
@@ -371,7 +378,7 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     const double tol2 = tol * tol;
     HIPCHK(c, hipMemcpyAsync(w.s.tol2, &tol2, sizeof(double), hipMemcpyHostToDevice, st));
     if (x0_given) {
-        int rc = apply_transformed<T>(c, x, q, k, nullptr, st);
+        int rc = apply_transformed<T>(c, x, q, k, RHS_MAJOR, nullptr, st);
         if (rc) return rc;
         HIPCHK(c, launch_cg_init<T>(b, q, pinv<T>(c), r, p, Ns, k, w.partials, st));
     } else {
@@ -379,7 +386,7 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
         HIPCHK(c, launch_fill<T>(q, Ns * k, (T)0, st));
         HIPCHK(c, launch_cg_init<T>(b, (T*)nullptr, pinv<T>(c), r, p, Ns, k, w.partials, st));
     }
-    HIPCHK(c, launch_cg_reduce(w.partials, kVecBlocks, 3, k, w.s, RED_INIT, st));
+    HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 3, k, w.s, RED_INIT, st));
     if (check_every < 1) check_every = 1;
     for (int it = 0; it < max_iter; ++it) {
         if (it % check_every == 0) {
@@ -391,11 +398,11 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
         }
         // q is zero here: zeroed at start and by every step.  The apply forms
         // the direction p = beta p + z at its gather; the step stores it.
-        int rc = apply_transformed<T>(c, p, q, k, w.energy, st, true, r, w.s.beta);
+        int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta);
         if (rc) return rc;
         HIPCHK(c, launch_cg_reduce(w.energy, c->n_e, 1, k, w.s, RED_PQ, st));
         HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, st));
-        HIPCHK(c, launch_cg_reduce(w.partials, kVecBlocks, 2, k, w.s, RED_RZ, st));
+        HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 2, k, w.s, RED_RZ, st));
     }
     return SEMCOND_OK;
 }
@@ -485,6 +492,8 @@ int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, in
     P.A.u = p;
     P.A.v = q;
     P.A.k = k;
+    P.A.ns = 1u;  // RHS-major vectors
+    P.A.rs = (uint32_t)c->N_s;
     P.A.energy = nullptr;
     P.A.e_begin = 0;
     // the kernel forms the direction at its gather from r, pinv and its own beta
@@ -585,7 +594,7 @@ int run_cg_any(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double
     const double tol2 = tol * tol;
     HIPCHK(c, hipMemcpyAsync(w.s.tol2, &tol2, sizeof(double), hipMemcpyHostToDevice, st));
     if (x0_given) {
-        int rc = apply_transformed<T>(c, x, q, k, nullptr, st);
+        int rc = apply_transformed<T>(c, x, q, k, RHS_MAJOR, nullptr, st);
         if (rc) return rc;
         HIPCHK(c, launch_cg_init<T>(b, q, pinv<T>(c), r, p, Ns, k, w.partials, st));
     } else {
@@ -593,7 +602,7 @@ int run_cg_any(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double
         HIPCHK(c, launch_fill<T>(q, Ns * k, (T)0, st));
         HIPCHK(c, launch_cg_init<T>(b, (T*)nullptr, pinv<T>(c), r, p, Ns, k, w.partials, st));
     }
-    HIPCHK(c, launch_cg_reduce(w.partials, kVecBlocks, 3, k, w.s, RED_INIT, st));
+    HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 3, k, w.s, RED_INIT, st));
     return run_persistent<T>(c, x, r, p, q, k, tol, max_iter, w, S, G, st);
 }
 
@@ -627,7 +636,7 @@ int autotune_persistent(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int 
             HIPCHK(c, launch_fill<T>(x, c->N_s * k, (T)0, st));
             HIPCHK(c, launch_fill<T>(q, c->N_s * k, (T)0, st));
             HIPCHK(c, launch_cg_init<T>(b, (T*)nullptr, pinv<T>(c), r, p, c->N_s, k, w.partials, st));
-            HIPCHK(c, launch_cg_reduce(w.partials, kVecBlocks, 3, k, w.s, RED_INIT, st));
+            HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 3, k, w.s, RED_INIT, st));
             HIPCHK(c, hipStreamSynchronize(st));
             auto t0 = std::chrono::steady_clock::now();
             int rc;
@@ -647,6 +656,42 @@ int autotune_persistent(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int 
             *bestG = cc.second;
         }
     }
+    return SEMCOND_OK;
+}
+
+// The library's apply on [N_s][k] arrays: the element kernels run on
+// RHS-major copies when k > 1 (per-RHS gathers and scatters stay coalesced);
+// the physical basis adds S^-1 before and S^-T after (Sec. 6).  Temporaries:
+// ws_vec, 2 N_s k values.
+template <typename T>
+int apply_public(semcond_ctx* c, const T* u, T* v, int k, int basis, hipStream_t st) {
+    const int64_t Ns = c->N_s;
+    T* t1 = (T*)c->ws_vec.ptr;
+    T* t2 = t1 + Ns * k;
+    const DevTab<T>& tb = tabs<T>(c);
+    const T* in = u;
+    if (basis == SEMCOND_PHYSICAL) {
+        HIPCHK(c, launch_transform<T>(c->L, tb.Sinv, u, t1, k, st));
+        in = t1;
+    }
+    if (k == 1) {
+        int rc = apply_transformed<T>(c, in, t2, k, NODE_MAJOR, nullptr, st);
+        if (rc) return rc;
+    } else {
+        T* tin = in == t1 ? t2 : t1;
+        HIPCHK(c, launch_transpose<T>(in, tin, Ns, k, st));
+        T* tout = tin == t1 ? t2 : t1;
+        int rc = apply_transformed<T>(c, tin, tout, k, RHS_MAJOR, nullptr, st);
+        if (rc) return rc;
+        if (basis == SEMCOND_TRANSFORMED) {
+            HIPCHK(c, launch_transpose<T>(tout, v, k, Ns, st));
+            return SEMCOND_OK;
+        }
+        HIPCHK(c, launch_transpose<T>(tout, tin, k, Ns, st));
+        HIPCHK(c, launch_transform<T>(c->L, tb.SinvT, tin, v, k, st));
+        return SEMCOND_OK;
+    }
+    HIPCHK(c, launch_transform<T>(c->L, tb.SinvT, t2, v, k, st));
     return SEMCOND_OK;
 }
 
@@ -838,28 +883,14 @@ int semcond_apply(semcond_ctx* c, const void* u, void* v, int k, int dtype, int 
     if (basis != SEMCOND_PHYSICAL && basis != SEMCOND_TRANSFORMED) return fail(c, SEMCOND_EINVAL, "bad basis");
     hipStream_t st = S(stream);
     const size_t es = dtype == SEMCOND_F64 ? sizeof(double) : sizeof(float);
-    if (basis == SEMCOND_TRANSFORMED) {
-        if (dtype == SEMCOND_F64) return apply_transformed<double>(c, (const double*)u, (double*)v, k, nullptr, st);
-        return apply_transformed<float>(c, (const float*)u, (float*)v, k, nullptr, st);
+    if (basis == SEMCOND_TRANSFORMED && k == 1) {
+        if (dtype == SEMCOND_F64) return apply_transformed<double>(c, (const double*)u, (double*)v, k, NODE_MAJOR, nullptr, st);
+        return apply_transformed<float>(c, (const float*)u, (float*)v, k, NODE_MAJOR, nullptr, st);
     }
     rc = grow(c, c->ws_vec, 2 * es * (size_t)c->N_s * k);
     if (rc) return rc;
-    if (dtype == SEMCOND_F64) {
-        double* t1 = (double*)c->ws_vec.ptr;
-        double* t2 = t1 + c->N_s * k;
-        HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.Sinv, (const double*)u, t1, k, st));
-        rc = apply_transformed<double>(c, t1, t2, k, nullptr, st);
-        if (rc) return rc;
-        HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.SinvT, t2, (double*)v, k, st));
-    } else {
-        float* t1 = (float*)c->ws_vec.ptr;
-        float* t2 = t1 + c->N_s * k;
-        HIPCHK(c, launch_transform<float>(c->L, c->t32.tab.Sinv, (const float*)u, t1, k, st));
-        rc = apply_transformed<float>(c, t1, t2, k, nullptr, st);
-        if (rc) return rc;
-        HIPCHK(c, launch_transform<float>(c->L, c->t32.tab.SinvT, t2, (float*)v, k, st));
-    }
-    return SEMCOND_OK;
+    if (dtype == SEMCOND_F64) return apply_public<double>(c, (const double*)u, (double*)v, k, basis, st);
+    return apply_public<float>(c, (const float*)u, (float*)v, k, basis, st);
 }
 
 int semcond_transform(semcond_ctx* c, const void* in, void* out, int k, int dtype, int direction, void* stream) {
@@ -1084,7 +1115,17 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
     if (rc) return rc;
     rc = condense_rhs64(c, (const double*)f, b, k, st);
     if (rc) return rc;
-    if (o.x0) HIPCHK(c, hipMemcpyAsync(x, o.x0, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // the conjugate gradients run on RHS-major vectors [k][N_s]
+    if (k > 1) {
+        HIPCHK(c, launch_transpose<double>(b, p, Ns, k, st));
+        std::swap(b, p);
+    }
+    if (o.x0) {
+        if (k > 1)
+            HIPCHK(c, launch_transpose<double>((const double*)o.x0, x, Ns, k, st));
+        else
+            HIPCHK(c, hipMemcpyAsync(x, o.x0, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
 
     std::vector<int> iters(k, 0), status(k, 0), outer(k, 0);
     std::vector<double> relres(k, 0.0);
@@ -1120,10 +1161,10 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
         if (rc) return rc;
         const double tol2 = o.tol * o.tol;
         HIPCHK(c, hipMemcpyAsync(wo.s.tol2, &tol2, sizeof(double), hipMemcpyHostToDevice, st));
-        rc = apply_transformed<double>(c, x, q, k, nullptr, st);
+        rc = apply_transformed<double>(c, x, q, k, RHS_MAJOR, nullptr, st);
         if (rc) return rc;
         HIPCHK(c, launch_cg_init<double>(b, q, c->d_pinv64, r, p, Ns, k, wo.partials, st));
-        HIPCHK(c, launch_cg_reduce(wo.partials, kVecBlocks, 3, k, wo.s, RED_INIT, st));
+        HIPCHK(c, launch_cg_reduce(wo.partials, vec_blocks(k), 3, k, wo.s, RED_INIT, st));
         CgHost ho;
         rc = read_state(c, wo, k, &ho, st);
         if (rc) return rc;
@@ -1142,11 +1183,11 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
         for (;; ++step) {
             // r = b - A64 x (q holds A64 x; zeroed again by cg_init), convergence per RHS
             if (step > 0 || o.x0) {
-                rc = apply_transformed<double>(c, x, q, k, nullptr, st, true);
+                rc = apply_transformed<double>(c, x, q, k, RHS_MAJOR, nullptr, st, true);
                 if (rc) return rc;
             }
             HIPCHK(c, launch_cg_init<double>(b, q, c->d_pinv64, r, p, Ns, k, wo.partials, st));
-            HIPCHK(c, launch_cg_reduce(wo.partials, kVecBlocks, 3, k, wo.s, RED_INIT, st));
+            HIPCHK(c, launch_cg_reduce(wo.partials, vec_blocks(k), 3, k, wo.s, RED_INIT, st));
             CgHost ho;
             rc = read_state(c, wo, k, &ho, st);
             if (rc) return rc;
@@ -1180,18 +1221,23 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
         }
     }
 
-    // back to the physical basis and the nodal array (Algorithm 4, second loop)
-    HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.S, x, p, k, st));
+    // back to [N_s][k], the physical basis and the nodal array (Algorithm 4, second loop)
+    double* xs = x;
+    if (k > 1) {
+        HIPCHK(c, launch_transpose<double>(x, q, k, Ns, st));
+        xs = q;
+    }
+    HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.S, xs, p, k, st));
     HIPCHK(c, launch_skel_to_nodal(c->L, p, (double*)u, c->N, k, st));
     if (o.recover_interior) {
         int grid;
         double* scratch;
         rc = scratch_for_cubes(c, &grid, &scratch);
         if (rc) return rc;
-        HIPCHK(c, launch_recover_interior(c->geo, c->t64.tab, (const double*)f, c->N, x, (double*)u, k, scratch,
+        HIPCHK(c, launch_recover_interior(c->geo, c->t64.tab, (const double*)f, c->N, xs, (double*)u, k, scratch,
                                           grid, st));
     }
-    if (o.skel_out) HIPCHK(c, hipMemcpyAsync(o.skel_out, x, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (o.skel_out) HIPCHK(c, hipMemcpyAsync(o.skel_out, xs, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipStreamSynchronize(st));
     int worst = SEMCOND_OK;
     for (int i = 0; i < k; ++i) {

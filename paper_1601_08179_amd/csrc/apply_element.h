@@ -141,14 +141,14 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
             }
             T val[NG];
 #pragma unroll
-            for (int g = 0; g < NG; ++g) val[g] = (tid + g * NT < NSLOT) ? A.u[node[g] * k + r] : (T)0;
+            for (int g = 0; g < NG; ++g) val[g] = (tid + g * NT < NSLOT) ? A.u[node[g] * A.ns + r * A.rs] : (T)0;
             if constexpr (DIR) {
                 const T bt = (T)beta[r];
                 T rv[NG], pv[NG];
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
                     const bool in = tid + g * NT < NSLOT;
-                    rv[g] = in ? A.dir_r[node[g] * k + r] : (T)0;
+                    rv[g] = in ? A.dir_r[node[g] * A.ns + r * A.rs] : (T)0;
                     pv[g] = in ? A.dir_pinv[node[g]] : (T)0;
                 }
 #pragma unroll
@@ -230,7 +230,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
         __syncthreads();
 
         double en = 0.0;
-        T* const vr = A.v + r;
+        T* const vr = A.v + (size_t)r * A.rs;
         // ---- faces, one algebraic form for all six (Sec. 6 primary part, Table 2
         // condensed part), one face per round so that every face-dependent
         // quantity is wave-uniform.  Face f = w,e,s,n,b,t has slot (s1,s2) =
@@ -269,7 +269,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                               dfast * m0 * (ca[s2] * UE(efl, s1) + cb[s2] * UE(efh, s1)) +
                               dslow * m0 * (ca[s1] * UE(esl, s2) + cb[s1] * UE(esh, s2)) + cond;
                 if (!con && live) {
-                    atomic_add(vr + (fbase + (uint32_t)loc) * (uint32_t)k, out);
+                    atomic_add(vr + (fbase + (uint32_t)loc) * (uint32_t)A.ns, out);
                     en += (double)uf * (double)out;
                 }
             }
@@ -306,7 +306,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                 const T out = (dg0 + dpar * m02 * lam[m]) * ue + m0 * K0p * (do1 * UE(q ^ 1, m) + do2 * UE(q ^ 2, m)) +
                               dpar * m02 * (ca[m] * UV(vlo) + cb[m] * UV(vhi)) + m0 * (do1 * l1 + do2 * l2);
                 if (!econ[6 + q] && live) {
-                    atomic_add(vr + ((uint32_t)ebase[6 + q] + (uint32_t)m) * (uint32_t)k, out);
+                    atomic_add(vr + ((uint32_t)ebase[6 + q] + (uint32_t)m) * (uint32_t)A.ns, out);
                     en += (double)ue * (double)out;
                 }
             }
@@ -328,7 +328,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                           m02 * K0p * (d1 * UV(q ^ 1) + d2 * UV(q ^ 2) + d3 * UV(q ^ 4)) +
                           m02 * (d1 * sx + d2 * sy + d3 * sz);
             if (!econ[18 + q] && live) {
-                atomic_add(vr + (uint32_t)ebase[18 + q] * (uint32_t)k, out);
+                atomic_add(vr + (uint32_t)ebase[18 + q] * (uint32_t)A.ns, out);
                 en += (double)UV(q) * (double)out;
             }
         }
@@ -417,7 +417,6 @@ __device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live,
                                     Gathered<T, DIR>& G) {
     constexpr int NI2 = NI * NI;
     const Layout& L = A.g.L;
-    const uint32_t k = (uint32_t)A.k;
     int e1, e2, e3;
     elem_index(L, live ? e : 0, &e1, &e2, &e3);
     ElemEnt E;
@@ -428,9 +427,9 @@ __device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live,
         rr = (T)0;
         pp = (T)0;
         if (on) {
-            u = A.u[node * k + r];
+            u = A.u[node * A.ns + r * A.rs];
             if constexpr (DIR) {
-                rr = A.dir_r[node * k + r];
+                rr = A.dir_r[node * A.ns + r * A.rs];
                 pp = A.dir_pinv[node];
             }
         }
@@ -564,7 +563,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
         __syncthreads();
 
         double en = 0.0;
-        T* const vr = A.v + r;
+        T* const vr = A.v + (size_t)r * A.rs;
         // ---- faces: primary part (Sec. 6) + condensed part (Table 2), pairs w/e, s/n, b/t.
         // Face f has slots (k,j), (k,j), (k,i), (k,i), (j,i), (j,i); bordering edges (UE index)
         // fast-lo, fast-hi, slow-lo, slow-hi: w {8,10,4,6} e {9,11,5,7} s {8,9,0,2}
@@ -603,7 +602,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                               dfast * m0 * (ta2 * UE(efl_t[f], s1) + tb2 * UE(efh_t[f], s1)) +
                               dslow * m0 * (ta1 * UE(esl_t[f], s2) + tb1 * UE(esh_t[f], s2)) + cnd[f];
                 if (!fcon[f] && live) {
-                    atomic_add(vr + (E.fb[f] + (uint32_t)t) * k, out);
+                    atomic_add(vr + (E.fb[f] + (uint32_t)t) * A.ns, out);
                     en += (double)uf * (double)out;
                 }
             }
@@ -647,7 +646,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                 bool con;
                 edge_node<NI>(L, E, par, eb0, eb1, em, &node, &con);
                 if (!con && live) {
-                    atomic_add(vr + node * k, out);
+                    atomic_add(vr + node * A.ns, out);
                     en += (double)ue * (double)out;
                 }
             }
@@ -675,7 +674,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
             bool con;
             vertex_node(L, E, vib, vjb, vkb, &node, &con);
             if (!con && live) {
-                atomic_add(vr + node * k, out);
+                atomic_add(vr + node * A.ns, out);
                 en += (double)UV(q) * (double)out;
             }
         }

@@ -12,9 +12,11 @@ template <typename T>
 struct ApplyArgs {
     Geo g;
     DevTab<T> tab;
-    const T* u;       // [N_s][k] transformed basis
-    T* v;             // [N_s][k], accumulated into (zero it first)
+    const T* u;       // k skeleton vectors, transformed basis: value (node, r) at node*ns + r*rs
+    T* v;             // same layout, accumulated into (zero it first)
     int k;
+    uint32_t ns = 0;  // node stride: k for [N_s][k] (RHS innermost), 1 for [k][N_s]
+    uint32_t rs = 0;  // RHS stride: 1 for [N_s][k], N_s for [k][N_s]
     double* energy;   // nullable, [n_elem][k]: element energies u_e . (H~^ u)_e
     int64_t e_begin;  // first element of this launch
     // Fused CG direction (all null for a plain apply): when dir_r is set the
@@ -71,15 +73,17 @@ template <typename T>
 hipError_t launch_fill(T* x, int64_t n, T val, hipStream_t st);
 template <typename Tin, typename Tout>
 hipError_t launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t st);
-// out = active[r] ? float(in) : 0 per right-hand side r of an [N_s][k] array.
+// out = active[r] ? float(in) : 0 per right-hand side r of a [k][n/k] array.
 hipError_t launch_convert_masked(const double* in, float* out, int64_t n, int k, const int* active, hipStream_t st);
 // x += double(d).
 hipError_t launch_add_mixed(double* x, const float* d, int64_t n, hipStream_t st);
 
 // ---------------------------------------------------------------------------
-// Conjugate gradients (BT solver, Sec. 8) on [N_s][k] multivectors.
-// Device state holds per-RHS scalars; reductions are two-stage and in a fixed
-// order, so results do not depend on scheduling.
+// Conjugate gradients (BT solver, Sec. 8) on RHS-major multivectors [k][N_s]
+// (each right-hand side contiguous, so the apply's per-RHS gathers and
+// scatters are as coalesced as for one RHS).  Device state holds per-RHS
+// scalars; reductions are two-stage and in a fixed order, so results do not
+// depend on scheduling.
 // ---------------------------------------------------------------------------
 struct CgState {
     double* rho;     // r.z
@@ -94,13 +98,18 @@ struct CgState {
     int* status;
 };
 
-constexpr int kVecBlocks = 2048;  // fixed grid of the vector kernels (partials per RHS)
+constexpr int kVecBlocks = 2048;  // vector-kernel blocks over all RHS
 
-int vec_block_threads(int k);
+// Blocks per RHS of the vector kernels (the partials per RHS): kVecBlocks / k.
+int vec_blocks(int k);
+
+// out = in^T for an R x C row-major array ([N_s][k] <-> [k][N_s]).
+template <typename T>
+hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, hipStream_t st);
 
 // r = b - q0 (q0 nullable: then r = b; else q0 is zeroed after use), p = 0
 // (the previous direction of the first step, whose beta is 0),
-// partials[0]: r.z, [1]: r.r, [2]: b.b  ([3][kVecBlocks][k] doubles).
+// partials[0]: r.z, [1]: r.r, [2]: b.b  ([3][vec_blocks(k)][k] doubles).
 template <typename T>
 hipError_t launch_cg_init(const T* b, T* q0, const T* pinv, T* r, T* p, int64_t Ns, int k,
                           double* partials, hipStream_t st);

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 #include "tables.h"
@@ -492,8 +494,9 @@ template hipError_t launch_convert<double, float>(const double*, float*, int64_t
 template <typename Tin, typename Tout>
 __global__ void k_convert_masked(const Tin* __restrict__ in, Tout* __restrict__ out, int64_t n, int k,
                                  const int* __restrict__ active) {
+    const int64_t len = n / k;  // [k][len], RHS-major
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = active[i % k] ? (Tout)in[i] : (Tout)0;
+        out[i] = active[i / len] ? (Tout)in[i] : (Tout)0;
 }
 
 hipError_t launch_convert_masked(const double* in, float* out, int64_t n, int k, const int* active, hipStream_t st) {
@@ -518,61 +521,40 @@ template hipError_t launch_convert<float, double>(const float*, double*, int64_t
 template hipError_t launch_convert<double, double>(const double*, double*, int64_t, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Conjugate-gradient vector kernels.  Block size B = k * floor(256/k): every
-// thread keeps one right-hand side r = t mod k for the whole grid-stride loop,
-// so per-RHS block sums are formed in a fixed order.
+// Conjugate-gradient vector kernels on RHS-major multivectors [k][N_s]: block
+// (x, r) of a grid (vec_blocks(k), k) works on right-hand side r, nodes
+// x*256 + t + m*256*vec_blocks(k); its sums are formed in a fixed order.
 // ---------------------------------------------------------------------------
 
-int vec_block_threads(int k) { return k * (256 / k); }
+int vec_blocks(int k) { return std::max(1, kVecBlocks / k); }
 
-// Per-RHS block sums: the block holds npb = B/k values of each right-hand side
-// (value j of RHS r at position j*k + r); a fixed-shape tree adds them.
+// Block sums of NQ quantities (all threads of the block belong to one RHS):
+// partials[(q * gridDim.x + blockIdx.x) * k + blockIdx.y].
 template <int NQ>
 __device__ inline void block_partials(double (&acc)[NQ], int k, double* __restrict__ partials) {
-    __shared__ double sh[NQ][256];
-    const int t = threadIdx.x, npb = blockDim.x / k;
+    __shared__ double sh[NQ][4];
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) sh[q][t] = acc[q];
+    for (int q = 0; q < NQ; ++q) acc[q] = wave_sum(acc[q]);
+    if ((t & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sh[q][t >> 6] = acc[q];
+    }
     __syncthreads();
-    int P = 1;
-    while (P < npb) P <<= 1;
-    const int j = t / k;
-    for (int w = P >> 1; w > 0; w >>= 1) {
-        if (j < w && j + w < npb) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) sh[q][t] += sh[q][t + w * k];
-        }
-        __syncthreads();
+    if (t < NQ) {
+        const double s = sh[t][0] + sh[t][1] + sh[t][2] + sh[t][3];
+        partials[((int64_t)t * gridDim.x + blockIdx.x) * k + blockIdx.y] = s;
     }
-    if (t < k) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) partials[((int64_t)q * gridDim.x + blockIdx.x) * k + t] = sh[q][t];
-    }
-}
-
-// Thread t of a block of B = k * (256/k) threads works on right-hand side
-// t mod k and on the nodes blockIdx.x * (B/k) + t/k + m * (B/k) * gridDim.x.
-struct VecIter {
-    int64_t s0, stride;
-    int rhs;
-};
-__device__ inline VecIter vec_iter(int k) {
-    VecIter it;
-    const int npb = blockDim.x / k;
-    it.rhs = threadIdx.x % k;
-    it.s0 = (int64_t)blockIdx.x * npb + threadIdx.x / k;
-    it.stride = (int64_t)npb * gridDim.x;
-    return it;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_init(const T* __restrict__ b, T* __restrict__ q0,
                                                  const T* __restrict__ pinv, T* __restrict__ r, T* __restrict__ p,
                                                  int64_t Ns, int k, double* __restrict__ partials) {
-    const VecIter it = vec_iter(k);
+    const int64_t off = (int64_t)blockIdx.y * Ns, stride = (int64_t)gridDim.x * blockDim.x;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t s = it.s0; s < Ns; s += it.stride) {
-        const int64_t idx = s * k + it.rhs;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < Ns; s += stride) {
+        const int64_t idx = off + s;
         const T bv = b[idx];
         T rv = bv;
         if (q0) {
@@ -592,8 +574,7 @@ __global__ __launch_bounds__(256) void k_cg_init(const T* __restrict__ b, T* __r
 template <typename T>
 hipError_t launch_cg_init(const T* b, T* q0, const T* pinv, T* r, T* p, int64_t Ns, int k, double* partials,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_init<T>, dim3(kVecBlocks), dim3(vec_block_threads(k)), 0, st, b, q0, pinv, r, p, Ns, k,
-                       partials);
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(vec_blocks(k), k), dim3(256), 0, st, b, q0, pinv, r, p, Ns, k, partials);
     return hipGetLastError();
 }
 template hipError_t launch_cg_init<double>(const double*, double*, const double*, double*, double*, int64_t, int,
@@ -739,13 +720,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
                                                  T* __restrict__ q, const T* __restrict__ pinv, int64_t Ns, int k,
                                                  CgState s, double* __restrict__ partials) {
-    const VecIter it = vec_iter(k);
-    const T alpha = (T)s.alpha[it.rhs];
-    const T beta = (T)s.beta[it.rhs];
-    const bool act = s.active[it.rhs] != 0;
+    const int rhs = blockIdx.y;
+    const int64_t off = (int64_t)rhs * Ns, stride = (int64_t)gridDim.x * blockDim.x;
+    const T alpha = (T)s.alpha[rhs];
+    const T beta = (T)s.beta[rhs];
+    const bool act = s.active[rhs] != 0;
     double acc[2] = {0.0, 0.0};
-    for (int64_t n = it.s0; n < Ns; n += it.stride) {
-        const int64_t idx = n * k + it.rhs;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < Ns; n += stride) {
+        const int64_t idx = off + n;
         T rv = r[idx];
         const T qv = q[idx];
         const T pn = pinv[n];
@@ -767,14 +749,45 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
 template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s, double* partials,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_step<T>, dim3(kVecBlocks), dim3(vec_block_threads(k)), 0, st, x, r, p, q, pinv, Ns, k, s,
-                       partials);
+    hipLaunchKernelGGL(k_cg_step<T>, dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q, pinv, Ns, k, s, partials);
     return hipGetLastError();
 }
 template hipError_t launch_cg_step<double>(double*, double*, double*, double*, const double*, int64_t, int, CgState,
                                            double*, hipStream_t);
 template hipError_t launch_cg_step<float>(float*, float*, float*, float*, const float*, int64_t, int, CgState, double*,
                                           hipStream_t);
+
+// out[c][r] = in[r][c] for an R x C row-major array, 32 x 32 tiles through LDS;
+// a one-dimensional grid of tiles (tile t: rows (t / tc) * 32, columns
+// (t mod tc) * 32, tc = ceil(C / 32)).
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const T* __restrict__ in, T* __restrict__ out, int64_t R,
+                                                   int64_t C, int64_t tc) {
+    __shared__ T tile[32][33];
+    const int64_t tid = blockIdx.x;
+    const int64_t r0 = tid / tc * 32, c0 = tid % tc * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int i = ty; i < 32; i += 8) {
+        const int64_t rr = r0 + i, cc = c0 + tx;
+        if (rr < R && cc < C) tile[i][tx] = in[rr * C + cc];
+    }
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) {
+        const int64_t cc = c0 + i, rr = r0 + tx;
+        if (rr < R && cc < C) out[cc * R + rr] = tile[tx][i];
+    }
+}
+
+template <typename T>
+hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, hipStream_t st) {
+    if (R <= 0 || C <= 0) return hipSuccess;
+    const int64_t tr = (R + 31) / 32, tc = (C + 31) / 32;
+    if (tr * tc > (int64_t(1) << 24)) return hipErrorInvalidValue;  // work-items stay below 2^32
+    hipLaunchKernelGGL(k_transpose<T>, dim3((unsigned)(tr * tc)), dim3(256), 0, st, in, out, R, C, tc);
+    return hipGetLastError();
+}
+template hipError_t launch_transpose<double>(const double*, double*, int64_t, int64_t, hipStream_t);
+template hipError_t launch_transpose<float>(const float*, float*, int64_t, int64_t, hipStream_t);
 
 }  // namespace semcond
 

@@ -17,7 +17,8 @@ constexpr int kBarWords = (kBarGroups + 3) * kBarSlot;
 
 template <typename T>
 struct PcgArgs {
-    ApplyArgs<T> A;  // operator: A.u = p, A.v = q, A.k = k, A.energy = nullptr
+    ApplyArgs<T> A;  // operator: A.u = p, A.v = q, A.k = k, A.energy = nullptr, RHS-major strides
+    // x, r, p, q: RHS-major [k][N_s]
     T* x;
     T* r;
     T* p;            // previous direction (0 with beta = 0 before the first step)

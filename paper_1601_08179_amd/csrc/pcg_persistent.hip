@@ -156,7 +156,7 @@ __global__ __launch_bounds__(S * apply_threads(NI), 2) void k_pcg_persistent(Pcg
 
     const int t = threadIdx.x, sub = t / NT, lt = t - sub * NT;
     const int k = P.k, G = gridDim.x, b = blockIdx.x;
-    const int rfix = t % k, npb = WG / k;
+    const int npb = WG / k;
     if (t < k) {
         s_rho[t] = P.rho[t];
         s_beta[t] = P.beta[t];
@@ -218,16 +218,20 @@ __global__ __launch_bounds__(S * apply_threads(NI), 2) void k_pcg_persistent(Pcg
         __syncthreads();
         PCG_STAMP(2)
         {
-            const T alpha = (T)s_alpha[rfix], beta = (T)s_beta[rfix];
-            const bool act = s_act[rfix] != 0;
+            // RHS-major vectors: thread t works on RHS rb = t / npb, nodes
+            // b*npb + jb + m*G*npb (consecutive threads, consecutive nodes)
+            const int rb = t / npb, jb = t - rb * npb;
+            const T alpha = (T)s_alpha[rb], beta = (T)s_beta[rb];
+            const bool act = s_act[rb] != 0;
+            const int64_t off = (int64_t)rb * P.Ns;
             double arz = 0.0, arr = 0.0;
-            for (int64_t n0 = (int64_t)b * npb + t / k; n0 < P.Ns; n0 += U * vstride) {
+            for (int64_t n0 = (int64_t)b * npb + jb; n0 < P.Ns; n0 += U * vstride) {
                 T rv[U], qv[U], pv[U], xv[U], pn[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int64_t n = n0 + u * vstride;
                     const bool in = n < P.Ns;
-                    const int64_t idx = n * k + rfix;
+                    const int64_t idx = off + n;
                     rv[u] = in ? P.r[idx] : (T)0;
                     qv[u] = in ? P.q[idx] : (T)0;
                     pn[u] = in ? P.pinv[n] : (T)0;
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(S * apply_threads(NI), 2) void k_pcg_persistent(Pcg
                 for (int u = 0; u < U; ++u) {
                     const int64_t n = n0 + u * vstride;
                     if (n < P.Ns) {
-                        const int64_t idx = n * k + rfix;
+                        const int64_t idx = off + n;
                         store_dev(P.q + idx, (T)0);
                         if (act) {
                             const T pd = fmadd(beta, pv[u], pn[u] * rv[u]);
@@ -258,17 +262,16 @@ __global__ __launch_bounds__(S * apply_threads(NI), 2) void k_pcg_persistent(Pcg
             __syncthreads();
             int Pw = 1;
             while (Pw < npb) Pw <<= 1;
-            const int j = t / k;
             for (int w = Pw >> 1; w > 0; w >>= 1) {
-                if (j < w && j + w < npb) {
-                    s_red[0][t] += s_red[0][t + w * k];
-                    s_red[1][t] += s_red[1][t + w * k];
+                if (jb < w && jb + w < npb) {
+                    s_red[0][t] += s_red[0][t + w];
+                    s_red[1][t] += s_red[1][t + w];
                 }
                 __syncthreads();
             }
-            if (t < k) {
-                P.part[((int64_t)1 * G + b) * k + t] = s_red[0][t];
-                P.part[((int64_t)2 * G + b) * k + t] = s_red[1][t];
+            if (jb == 0) {
+                P.part[((int64_t)1 * G + b) * k + rb] = s_red[0][t];
+                P.part[((int64_t)2 * G + b) * k + rb] = s_red[1][t];
             }
         }
         PCG_STAMP(3)

@@ -132,3 +132,20 @@ def test_manufactured_solution(lib):
     assert np.abs(u - ref).max() <= 1e-10 * np.abs(ref).max()
     err = np.abs(u - uex).max()
     assert 1e-6 < err < 1e-4
+
+
+@pytest.mark.parametrize("basis", ["PHYSICAL", "TRANSFORMED"])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_apply_batched_equals_single_columns(lib, basis, dtype):
+    """k = 5 right-hand sides in one call (RHS-major kernels behind the [N_s][k]
+    interface) equal five single-RHS applies, up to the scatter's rounding order."""
+    import torch
+    ctx, op, g, free = both(MESHES["stretched3_p5"]())
+    dt = getattr(torch, dtype)
+    u = torch.as_tensor(np.random.default_rng(8).standard_normal((ctx.N_s, 5)), device="cuda").to(dt)
+    b = getattr(lib, basis)
+    out = ctx.apply(u, basis=b).double().cpu().numpy()
+    tol = 1e-13 if dtype == "float64" else 1e-5
+    for r in range(5):
+        one = ctx.apply(u[:, r].contiguous(), basis=b).double().cpu().numpy()
+        assert np.abs(out[:, r] - one).max() <= tol * np.abs(one).max(), (basis, dtype, r)
