@@ -195,6 +195,123 @@ def suite(args):
         ctx.close()
 
 
+# ---------------------------------------------------------------------------
+# HBM traffic of the dominant kernel from rocprofv3 counters
+# ---------------------------------------------------------------------------
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_config2_p8.md")
+DOMINANT = "k_apply_tpt<double, 7, true>"
+KERNEL_SOURCES = ["apply.hip", "apply_element.h", "device_common.h", "kernels.h", "layout.h"]
+COPY_BYTES = 256 << 20
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1601_08179_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_workload():
+    """Dispatches the counter runs read: a plain device copy of COPY_BYTES
+    (calibration), one timed-workload FP64 solve (its CG applies are the
+    dominant kernel) and standalone applies."""
+    import torch
+
+    import workloads as W
+    from paper_1601_08179_amd import semcond
+
+    x = torch.randn(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        torch.mul(x, 1.0, out=y)  # a plain streaming kernel: reads and writes COPY_BYTES
+    torch.cuda.synchronize()
+    wmesh, f = W.config2(k=1)
+    ctx = semcond.Context(wmesh)
+    ft = torch.tensor(f, device="cuda")
+    u = torch.zeros_like(ft)
+    ctx.solve(ft, out=u, tol=1e-10, persistent=False)
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def pmc_summary(fetch_csv, write_csv, commands):
+    """Per-launch HBM bytes of the dominant kernel from FETCH_SIZE / WRITE_SIZE
+    (KiB per dispatch), each scaled by what the counter reads for the
+    calibration copy; written to TRAFFIC_FILE."""
+    import csv
+
+    def read(path, counter):
+        rows = {}
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                rows.setdefault(row["Kernel_Name"], []).append((int(row["Grid_Size"]), float(row["Counter_Value"])))
+        return rows
+
+    fe, wr = read(fetch_csv, "FETCH_SIZE"), read(write_csv, "WRITE_SIZE")
+
+    def copy_value(rows):
+        # the calibration kernel: torch's elementwise multiply by a scalar (largest grid)
+        cand = [(g, v) for name, lst in rows.items()
+                if "elementwise" in name and ("Mul" in name or "UnaryFunctor" in name) for g, v in lst]
+        gmax = max(g for g, _ in cand)
+        big = [v for g, v in cand if g == gmax]
+        return sum(big) / len(big)
+
+    def dominant(rows):
+        for name, lst in rows.items():
+            if name.startswith("void semcond::" + DOMINANT):
+                return sum(v for _, v in lst) / len(lst), len(lst)
+        raise KeyError(DOMINANT)
+
+    ff = COPY_BYTES / (copy_value(fe) * 1024.0)
+    fw = COPY_BYTES / (copy_value(wr) * 1024.0)
+    (fk, nf), (wk, nw) = dominant(fe), dominant(wr)
+    fetch_b, write_b = fk * 1024.0 * ff, wk * 1024.0 * fw
+    lines = [
+        "# HBM traffic of %s (bench.py workload, FP64 CG apply, MI355X)" % DOMINANT,
+        "",
+        "Commands (from the repository root, on one MI355X):",
+        "",
+        "```",
+    ] + commands + [
+        "```",
+        "",
+        "| quantity | value |",
+        "|---|---|",
+        "| calibration: FETCH_SIZE of a streaming kernel reading and writing %d MiB | %.0f KiB (factor %.4f) |" % (
+            COPY_BYTES >> 20, copy_value(fe), ff),
+        "| calibration: WRITE_SIZE of the same kernel | %.0f KiB (factor %.4f) |" % (copy_value(wr), fw),
+        "| dominant kernel FETCH_SIZE per dispatch (%d dispatches) | %.1f KiB |" % (nf, fk),
+        "| dominant kernel WRITE_SIZE per dispatch (%d dispatches) | %.1f KiB |" % (nw, wk),
+        "| scaled HBM read bytes per launch | %.0f |" % fetch_b,
+        "| scaled HBM write bytes per launch | %.0f |" % write_b,
+        "",
+        "traffic_bytes_per_launch: %.0f" % (fetch_b + write_b),
+        "kernel_sources_sha256: %s" % kernel_sources_hash(),
+        "",
+    ]
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def stored_traffic():
+    """Per-launch HBM bytes of the dominant kernel from TRAFFIC_FILE, or None when
+    absent or taken from kernel sources other than the current ones."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes", "kernel_sources")))
+    if vals.get("kernel_sources_sha256", "").strip() != kernel_sources_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,13 +323,25 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--suite", default="", help="extra measurements instead of the default line: "
                     "any of 3 (p/AR sweep), 4 (16 RHS), 5 (differentiable solve), e.g. --suite 345")
+    ap.add_argument("--pmc-workload", action="store_true",
+                    help="run only the dispatches the rocprofv3 counter runs read")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic summary from the two counter runs' CSV files")
+    ap.add_argument("--pmc-command", action="append", default=[],
+                    help="command line recorded in the traffic summary (repeatable)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_command)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only; multi-GPU runs are not part of this build "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.suite:
         suite(args)
+        return
+    if args.pmc_workload:
+        pmc_workload()
         return
 
     import torch
@@ -290,10 +419,10 @@ def main():
     # reads r, q, P^-1, p, x and writes q, p, x, r).
     if cg_ms >= ap_ms:
         dom = {"kernel": "k_pcg_persistent<double,7,%d>" % tS, "ms": cg_ms, "launches": cg_launches,
-               "bytes": 13 * 8 * Ns * cg_iters}
+               "bytes": 13 * 8 * Ns * cg_iters, "traffic": None}
     else:
         dom = {"kernel": "k_apply_tpt<double,7,true>", "ms": ap_ms, "launches": ap_launches,
-               "bytes": 4 * 8 * Ns * ap_launches}
+               "bytes": 4 * 8 * Ns * ap_launches, "traffic": stored_traffic()}
     dom_achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
     apply_bytes = 2 * 8 * Ns
     apply_achieved = apply_bytes / kern_s / 1e9
@@ -322,7 +451,8 @@ def main():
                      "inner_iterations": minfo[0]["iters"], "outer_steps": minfo[0]["outer"],
                      "rel_res": minfo[0]["rel_res"]},
         "roofline": {"bound": "hbm", "achieved": dom_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom_achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": dom_achieved / HBM_PEAK_GBS, "traffic": dom["traffic"],
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": dom["kernel"], "launches": dom["launches"],
                      "bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
                      "kernel_us_per_launch": dom["ms"] * 1e3 / max(dom["launches"], 1)},
