@@ -11,23 +11,27 @@ namespace semcond {
 
 template <typename T, int NI, bool DIR>
 __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A, int64_t n_elem) {
-    __shared__ ApplySmem<T, NI> sm;
     if constexpr (NI <= 15) {
-        // workgroup (x, y): element e_begin + x, right-hand side y
-        apply_elements_cube<T, NI, DIR, true>(A, A.e_begin + blockIdx.x, 1, 1, A.e_begin + n_elem, blockIdx.y, 1, sm,
-                                              nullptr, threadIdx.x, A.dir_beta);
+        // workgroup (x, y): elements e_begin + x*E .. + E - 1, right-hand side y
+        constexpr int E = apply_pack(NI);
+        __shared__ ApplySmem<T, NI> sm[E];
+        apply_elements_cube<T, NI, DIR, true, E>(A, A.e_begin + (int64_t)blockIdx.x * E, 1, 1, A.e_begin + n_elem,
+                                                 blockIdx.y, 1, sm, nullptr, threadIdx.x, A.dir_beta);
     } else {
+        __shared__ ApplySmem<T, NI> sm;
         apply_element<T, NI, DIR>(A, (int64_t)blockIdx.x + A.e_begin, sm, nullptr, threadIdx.x, true, A.dir_beta);
     }
 }
 
-// Grid of the apply: one workgroup per element and, for n_I <= 15, per
-// right-hand side (measured faster on gfx950 than workgroups that walk several
-// items).  Element counts stay below 2^31 (the skeleton is larger than the
-// element count and N_s k < 2^31); k <= 256.
+// Grid of the apply: for n_I <= 15 one workgroup per apply_pack(n_I) elements
+// and right-hand side (measured faster on gfx950 than workgroups that walk
+// several items), else one per element.  Element counts stay below 2^31 (the
+// skeleton is larger than the element count and N_s k < 2^31); k <= 256.
 template <int NI>
 static dim3 apply_grid(int64_t n_elem, int k) {
-    return dim3((unsigned)n_elem, NI <= 15 ? (unsigned)k : 1u);
+    if (NI > 15) return dim3((unsigned)n_elem);
+    constexpr int E = apply_pack(NI);
+    return dim3((unsigned)((n_elem + E - 1) / E), (unsigned)k);
 }
 
 template <typename T>

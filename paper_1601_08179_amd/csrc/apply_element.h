@@ -41,6 +41,18 @@ constexpr int apply_threads(int NI) {
     return NI * NI <= 64 ? 64 : ((NI * NI + 63) / 64) * 64;
 }
 
+// Lanes that one element of the cube body needs: max(n_I^2, 4 n_I, 8) rounded
+// up to a power of two; for n_I <= 5 a 64-lane wave then holds several
+// elements (apply_pack), one per group of apply_lanes lanes.
+constexpr int apply_lanes(int NI) {
+    int need = NI * NI > 4 * NI ? NI * NI : 4 * NI;
+    if (need < 8) need = 8;
+    int l = 8;
+    while (l < need) l *= 2;
+    return NI <= 5 ? l : apply_threads(NI);
+}
+constexpr int apply_pack(int NI) { return apply_threads(NI) / apply_lanes(NI); }
+
 // Shared memory of one element.
 template <typename T, int NI>
 struct ApplySmem {
@@ -465,19 +477,24 @@ __device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live,
 // e0, e0 + stride, ... and for each the right-hand sides r0 .. r0 + nr - 1.  (A
 // loop keeps the coefficient scalars live across items; the single-item form
 // lets them live only where they are used.)
-template <typename T, int NI, bool DIR, bool ONE>
+// With NE > 1 (ONE only) the workgroup holds NE groups of NT / NE lanes; group g
+// computes element e0 + g with its own LDS block smv[g].
+template <typename T, int NI, bool DIR, bool ONE, int NE = 1>
 __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t stride, int64_t count, int64_t n_end,
-                                    uint32_t r0, uint32_t nr, ApplySmem<T, NI>& sm, double* en_acc, int tid,
+                                    uint32_t r0, uint32_t nr, ApplySmem<T, NI>* smv, double* en_acc, int tid,
                                     const double* beta) {
+    static_assert(NE == 1 || ONE, "packed elements only in the single-item form");
     constexpr int NI2 = NI * NI;
-    constexpr int NT = apply_threads(NI);
+    constexpr int NT = apply_threads(NI) / NE;  // lanes per element
     constexpr int NFACE = 6 * NI2;
     constexpr int NEDGE = 12 * NI;
+    const int grp = NE == 1 ? 0 : tid / NT;
+    ApplySmem<T, NI>& sm = smv[grp];
     T* const F = sm.F;
     T* const Wv = sm.Wv;
     double* const red = sm.red;
     const Layout& L = A.g.L;
-    const int t = tid;
+    const int t = NE == 1 ? tid : tid - grp * NT;
     const uint32_t k = (uint32_t)A.k;
     const T m0 = A.tab.m0, K00 = A.tab.K00, K0p = A.tab.K0p, m02 = m0 * m0;
 
@@ -679,20 +696,28 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
             }
         }
         if (A.energy || en_acc) {
-            en = wave_sum(en);
-            if ((t & 63) == 0) red[t >> 6] = en;
-            __syncthreads();
-            if (t == 0) {
-                double sum = 0.0;
-                for (int w = 0; w < NT / 64; ++w) sum += red[w];
-                if (A.energy && live) A.energy[e * k + r] = sum;
-                if (en_acc && live) en_acc[r] += sum;
+            if constexpr (NE > 1) {
+                // sum over the element's lane group (aligned, power of two)
+#pragma unroll
+                for (int off = NT / 2; off > 0; off >>= 1) en += __shfl_xor(en, off, 64);
+                if (t == 0 && live) A.energy[e * k + r] = en;
+            } else {
+                en = wave_sum(en);
+                if ((t & 63) == 0) red[t >> 6] = en;
+                __syncthreads();
+                if (t == 0) {
+                    double sum = 0.0;
+                    for (int w = 0; w < NT / 64; ++w) sum += red[w];
+                    if (A.energy && live) A.energy[e * k + r] = sum;
+                    if (en_acc && live) en_acc[r] += sum;
+                }
             }
         }
         __syncthreads();
     };
     if constexpr (ONE) {
-        item(e0, e0 < n_end, r0);
+        const int64_t e = e0 + grp;
+        item(e, e < n_end, r0);
     } else {
         for (int64_t i = 0; i < count; ++i) {
             const int64_t e = e0 + i * stride;
@@ -709,7 +734,8 @@ template <typename T, int NI, bool DIR>
 __device__ void apply_element(const ApplyArgs<T>& A, int64_t e, ApplySmem<T, NI>& sm, double* en_acc,
                               int tid, bool live, const double* beta) {
     if constexpr (NI <= 15)
-        apply_elements_cube<T, NI, DIR, false>(A, e, 1, 1, live ? e + 1 : e, 0, (uint32_t)A.k, sm, en_acc, tid, beta);
+        apply_elements_cube<T, NI, DIR, false>(A, e, 1, 1, live ? e + 1 : e, 0, (uint32_t)A.k, &sm, en_acc, tid,
+                                               beta);
     else
         apply_element_planes<T, NI, DIR>(A, e, sm, en_acc, tid, live, beta);
 }

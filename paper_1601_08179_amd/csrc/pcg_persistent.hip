@@ -186,7 +186,7 @@ __global__ __launch_bounds__(S * apply_threads(NI), 2) void k_pcg_persistent(Pcg
         if (lt < k) s_en[sub][lt] = 0.0;
         __syncthreads();
         apply_elements_cube<T, NI, true, false>(P.A, (int64_t)b * S + sub, (int64_t)G * S, rounds, P.n_e, 0,
-                                                (uint32_t)k, sm[sub], s_en[sub], lt, s_beta);
+                                                (uint32_t)k, &sm[sub], s_en[sub], lt, s_beta);
         if (t < k) {
             double s = 0.0;
             for (int g = 0; g < S; ++g) s += s_en[g][t];
