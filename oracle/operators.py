@@ -185,6 +185,33 @@ class CondensedOperator:
         out[fs] = lu.solve(rhs[fs])
         return out
 
+    def solve_full_dirichlet(self, f, g):
+        """Full uncondensed direct solve with prescribed values on the Dirichlet nodes.
+
+        u = g on the nodes of the Dirichlet domain faces; on the free nodes
+        (R H_L R^T)_FF u_F = (R F_L)_F - (R H_L R^T)_FD g_D, i.e. the discrete
+        system of Sec. 3 with the known values moved to the right-hand side.
+        f, g: nodal arrays (N,); returns the full nodal solution (N,).
+        """
+        rows, cols, vals = [], [], []
+        for e in range(len(self.gmap)):
+            H = self.H[self.cls[e]]
+            gm = self.gmap[e]
+            rows.append(np.repeat(gm, len(gm)))
+            cols.append(np.tile(gm, len(gm)))
+            vals.append(H.ravel())
+        N = self.sizes["N"]
+        A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=(N, N)).tocsr()
+        F = np.bincount(self.gmap.ravel(), weights=self.element_rhs(f).ravel(), minlength=N)
+        fr = np.nonzero(~self.cons)[0]
+        dn = np.nonzero(self.cons)[0]
+        u = np.zeros(N)
+        u[dn] = np.asarray(g, dtype=np.float64)[dn]
+        rhs = F[fr] - A[fr][:, dn] @ u[dn]
+        u[fr] = spla.splu(A[fr][:, fr].tocsc()).solve(rhs)
+        return u
+
     def solve_full(self, f):
         """Full uncondensed direct solve of R H_L R^T u = R F_L on free nodes."""
         A, fr = self.assembled_full()

@@ -118,3 +118,87 @@ def config5(k=8, n=8, p=8):
 def random_skeleton_input(N, k=1, seed=0):
     """Dense random nodal vectors (k, N); the operator reads the skeleton part."""
     return np.random.default_rng(SEED_BASE + 7 + int(seed)).standard_normal(size=(k, N))
+
+
+# ---------------------------------------------------------------------------
+# Manufactured solution with inhomogeneous Dirichlet values (solver experiment
+# on (0, 2 pi)^3, Sec. 8): u = cos(k(x1 - 3 x2 + 2 x3)) sin(k(1 + x1))
+# sin(k(1 - x2)) sin(k(2 x1 + x2)) sin(k(3 x1 - 2 x2 + 2 x3)), f = lam u - Lap u.
+# Each factor is a sinusoid of a linear form; the Laplacian of the product is
+# sum_j f_j'' |w_j|^2 prod_{l != j} f_l + 2 sum_{j<l} f_j' f_l' (w_j . w_l) prod_{m != j,l} f_m.
+# ---------------------------------------------------------------------------
+_MS_FORMS = [  # (is_cos, direction w, offset c): factor trig(k (w . x + c))
+    (True, (1.0, -3.0, 2.0), 0.0),
+    (False, (1.0, 0.0, 0.0), 1.0),
+    (False, (0.0, -1.0, 0.0), 1.0),
+    (False, (2.0, 1.0, 0.0), 0.0),
+    (False, (3.0, -2.0, 2.0), 0.0),
+]
+
+
+def _ms_factors(X, k):
+    """Values, first and second derivatives (w.r.t. the linear form) of the factors."""
+    out = []
+    for is_cos, w, c in _MS_FORMS:
+        t = k * (X @ np.asarray(w) + c)
+        if is_cos:
+            out.append((np.cos(t), -k * np.sin(t), -k * k * np.cos(t), np.asarray(w)))
+        else:
+            out.append((np.sin(t), k * np.cos(t), -k * k * np.sin(t), np.asarray(w)))
+    return out
+
+
+def manufactured_u(X, k=5.0):
+    """u_ex at points X (n, 3)."""
+    u = np.ones(len(X))
+    for v, _, _, _ in _ms_factors(X, k):
+        u = u * v
+    return u
+
+
+def manufactured_laplacian(X, k=5.0):
+    """Lap u_ex at points X (n, 3), from the product rule above."""
+    F = _ms_factors(X, k)
+    n = len(F)
+    lap = np.zeros(len(X))
+    for j in range(n):
+        term = F[j][2] * float(F[j][3] @ F[j][3])
+        for l in range(n):
+            if l != j:
+                term = term * F[l][0]
+        lap += term
+        for l in range(j + 1, n):
+            term = 2.0 * F[j][1] * F[l][1] * float(F[j][3] @ F[l][3])
+            for m in range(n):
+                if m != j and m != l:
+                    term = term * F[m][0]
+            lap += term
+    return lap
+
+
+def one_sided_widths(n, alpha, length=1.0):
+    """Widths with the constant expansion factor alpha, h_i proportional to alpha^i."""
+    h = float(alpha) ** np.arange(int(n))
+    return h * (float(length) / h.sum())
+
+
+def solver_experiment_mesh(p, alpha, n=8):
+    """n^3 elements on (0, 2 pi)^3, expansion factor alpha on every axis, lambda = 0,
+    Dirichlet on all faces."""
+    w = one_sided_widths(n, alpha, 2.0 * np.pi)
+    return mesh(p, (n, n, n), widths=[w, w, w], lam=0.0)
+
+
+def nodal_coordinates(p, n, widths, x_gll):
+    """(N, 3) coordinates of the global nodes (I1 fastest) from per-axis widths and
+    the p+1 reference GLL nodes x_gll on [-1, 1] (origin 0)."""
+    axes = []
+    for a in range(3):
+        h = np.asarray(widths[a], dtype=np.float64)
+        left = np.concatenate(([0.0], np.cumsum(h)[:-1]))
+        pts = [0.0]
+        for e in range(int(n[a])):
+            pts.extend(left[e] + 0.5 * h[e] * (1.0 + np.asarray(x_gll[1:])))
+        axes.append(np.array(pts))
+    X3, X2, X1 = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return np.stack([X1.ravel(), X2.ravel(), X3.ravel()], axis=1)
