@@ -127,6 +127,12 @@ typedef struct {
                             /*   (k, type), else stepwise.  Persistent kernels exist for  */
                             /*   n_I <= 15 and k dividing the workgroup (k <= 32); other  */
                             /*   cases run stepwise                                       */
+    const void* g_dirichlet;/* optional, nodal [k][N] FP64: prescribed values u = g on the */
+                            /* nodes of the Dirichlet domain faces (other entries are     */
+                            /* ignored); NULL: homogeneous.  The known values are moved  */
+                            /* to the right-hand side (lifting; Sec. 8's solver test has */
+                            /* inhomogeneous Dirichlet conditions).  x0 holds unknowns   */
+                            /* only; skel_out returns the full skeleton values           */
 } semcond_solve_opts;
 
 #define SEMCOND_CG_STEPWISE   0

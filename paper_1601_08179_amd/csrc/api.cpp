@@ -67,6 +67,7 @@ struct semcond_ctx {
     Buffer ws_state;    // CG scalars (device)
     Buffer ws_nodal;    // nodal right-hand sides of dual solves
     Buffer ws_persist;  // partials and barrier words of the persistent CG
+    Buffer ws_lift;     // prescribed Dirichlet values (transformed) and a temporary
     int* h_active = nullptr;  // pinned host copy of CG activity flags
     int h_active_cap = 0;
     // persistent CG launch configuration per (k, dtype): (S, G)
@@ -232,7 +233,8 @@ enum VecLayout { NODE_MAJOR = 0, RHS_MAJOR = 1 };
 
 template <typename T>
 int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, double* energy, hipStream_t st,
-                      bool v_is_zero = false, const T* dir_r = nullptr, const double* dir_beta = nullptr) {
+                      bool v_is_zero = false, const T* dir_r = nullptr, const double* dir_beta = nullptr,
+                      int read_con = 0) {
     if (!v_is_zero) HIPCHK(c, launch_fill<T>(v, c->N_s * k, (T)0, st));
     ApplyArgs<T> a = apply_args<T>(c);
     a.u = u;
@@ -240,6 +242,7 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, do
     a.k = k;
     a.ns = lay == RHS_MAJOR ? 1u : (uint32_t)k;
     a.rs = lay == RHS_MAJOR ? (uint32_t)c->N_s : 1u;
+    a.read_con = read_con;
     a.energy = energy;
     if (dir_r) {
         if (!dir_beta) return fail(c, SEMCOND_EINVAL, "fused direction needs beta");
@@ -733,6 +736,7 @@ int semcond_destroy(semcond_ctx* c) {
     hipFree(c->ws_state.ptr);
     hipFree(c->ws_nodal.ptr);
     hipFree(c->ws_persist.ptr);
+    hipFree(c->ws_lift.ptr);
     if (c->h_active) hipHostFree(c->h_active);
     for (hipEvent_t e : c->ev) hipEventDestroy(e);
     delete c;
@@ -945,7 +949,7 @@ int semcond_skeleton_to_nodal(semcond_ctx* c, const void* skel, void* nodal, int
     if (!skel || !nodal) return fail(c, SEMCOND_EINVAL, "NULL pointer");
     int rc = check_k(c, k);
     if (rc) return rc;
-    HIPCHK(c, launch_skel_to_nodal(c->L, (const double*)skel, (double*)nodal, c->N, k, S(stream)));
+    HIPCHK(c, launch_skel_to_nodal(c->L, (const double*)skel, (double*)nodal, c->N, k, 0, S(stream)));
     return SEMCOND_OK;
 }
 
@@ -1069,6 +1073,7 @@ void semcond_solve_opts_default(semcond_solve_opts* o) {
     o->max_outer = 30;
     o->rhs_dual = 0;
     o->persistent = SEMCOND_CG_AUTO;
+    o->g_dirichlet = nullptr;
 }
 
 int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_solve_opts* opts,
@@ -1115,6 +1120,27 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
     if (rc) return rc;
     rc = condense_rhs64(c, (const double*)f, b, k, st);
     if (rc) return rc;
+    // Prescribed Dirichlet values: g~ = T^-1 g on the Dirichlet entities (zero
+    // elsewhere; the transform keeps every entity to itself), and the lift
+    // F^~_free -= (H~^ g~)_free with the apply reading the Dirichlet entities.
+    double* gl = nullptr;
+    if (o.g_dirichlet) {
+        rc = grow(c, c->ws_lift, 2 * nv * sizeof(double));
+        if (rc) return rc;
+        gl = (double*)c->ws_lift.ptr;
+        double* tmp = gl + nv;
+        HIPCHK(c, launch_nodal_to_skel(c->L, (const double*)o.g_dirichlet, tmp, c->N, k, st));
+        HIPCHK(c, launch_mask_nodes(c->L, tmp, k, KEEP_CONSTRAINED, st));
+        HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.Sinv, tmp, gl, k, st));
+        rc = apply_transformed<double>(c, gl, tmp, k, NODE_MAJOR, nullptr, st, false, nullptr, nullptr, 1);
+        if (rc) return rc;
+        HIPCHK(c, launch_axpy(b, tmp, -1.0, (int64_t)nv, st));
+    }
+    // the initial guess holds unknowns only (entries on Dirichlet entities are ignored)
+    if (o.x0) {
+        HIPCHK(c, hipMemcpyAsync(q, o.x0, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, launch_mask_nodes(c->L, q, k, KEEP_FREE, st));
+    }
     // the conjugate gradients run on RHS-major vectors [k][N_s]
     if (k > 1) {
         HIPCHK(c, launch_transpose<double>(b, p, Ns, k, st));
@@ -1122,9 +1148,9 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
     }
     if (o.x0) {
         if (k > 1)
-            HIPCHK(c, launch_transpose<double>((const double*)o.x0, x, Ns, k, st));
+            HIPCHK(c, launch_transpose<double>(q, x, Ns, k, st));
         else
-            HIPCHK(c, hipMemcpyAsync(x, o.x0, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipMemcpyAsync(x, q, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
     }
 
     std::vector<int> iters(k, 0), status(k, 0), outer(k, 0);
@@ -1227,15 +1253,17 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
         HIPCHK(c, launch_transpose<double>(x, q, k, Ns, st));
         xs = q;
     }
+    if (gl) HIPCHK(c, launch_axpy(xs, gl, 1.0, (int64_t)nv, st));  // u~ = unknowns + g~
+    const int keep = gl ? 1 : 0;
     HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.S, xs, p, k, st));
-    HIPCHK(c, launch_skel_to_nodal(c->L, p, (double*)u, c->N, k, st));
+    HIPCHK(c, launch_skel_to_nodal(c->L, p, (double*)u, c->N, k, keep, st));
     if (o.recover_interior) {
         int grid;
         double* scratch;
         rc = scratch_for_cubes(c, &grid, &scratch);
         if (rc) return rc;
         HIPCHK(c, launch_recover_interior(c->geo, c->t64.tab, (const double*)f, c->N, xs, (double*)u, k, scratch,
-                                          grid, st));
+                                          grid, keep, st));
     }
     if (o.skel_out) HIPCHK(c, hipMemcpyAsync(o.skel_out, xs, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipStreamSynchronize(st));

@@ -148,7 +148,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                 } else if (s < NSLOT) {
                     ent = 18 + (s - NFACE - NEDGE);
                 }
-                keep[g] = s < NSLOT && !econ[ent];
+                keep[g] = s < NSLOT && (!econ[ent] || A.read_con);
                 node[g] = keep[g] ? ebase[ent] + loc : 0;
             }
             T val[NG];
@@ -448,7 +448,7 @@ __device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live,
     };
     const bool fown = live && t < NI2;
 #pragma unroll
-    for (int f = 0; f < 6; ++f) load(E.fb[f] + (uint32_t)t, fown && !fcon[f], G.f[f], G.rf[f], G.pf[f]);
+    for (int f = 0; f < 6; ++f) load(E.fb[f] + (uint32_t)t, fown && (!fcon[f] || A.read_con), G.f[f], G.rf[f], G.pf[f]);
     const int eq = t / NI, em = t - (t / NI) * NI;
     const bool eown = live && t < 4 * NI;
 #pragma unroll
@@ -456,13 +456,13 @@ __device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live,
         uint32_t node;
         bool con;
         edge_node<NI>(L, E, par, eq & 1, (eq >> 1) & 1, em, &node, &con);
-        load(node, eown && !con, G.e[par], G.re[par], G.pe[par]);
+        load(node, eown && (!con || A.read_con), G.e[par], G.re[par], G.pe[par]);
     }
     {
         uint32_t node;
         bool con;
         vertex_node(L, E, t & 1, (t >> 1) & 1, (t >> 2) & 1, &node, &con);
-        load(node, live && t < 8 && !con, G.v, G.rv, G.pv);
+        load(node, live && t < 8 && (!con || A.read_con), G.v, G.rv, G.pv);
     }
 }
 

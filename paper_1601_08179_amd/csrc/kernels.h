@@ -17,6 +17,8 @@ struct ApplyArgs {
     int k;
     uint32_t ns = 0;  // node stride: k for [N_s][k] (RHS innermost), 1 for [k][N_s]
     uint32_t rs = 0;  // RHS stride: 1 for [N_s][k], N_s for [k][N_s]
+    int read_con = 0; // 1: read entities on Dirichlet faces too (lifting of prescribed values);
+                      //    their outputs are never written either way
     double* energy;   // nullable, [n_elem][k]: element energies u_e . (H~^ u)_e
     int64_t e_begin;  // first element of this launch
     // Fused CG direction (all null for a plain apply): when dir_r is set the
@@ -50,13 +52,22 @@ int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch);
 
 // Interior recovery (Algorithm 4, second loop): u_I = (S(x)S(x)S) D^-1 (F~_I - H~_IB u~_B),
 // written into the interior nodes of the nodal array u [k][N].
+// keep_con: faces on Dirichlet planes contribute their values in xskel (prescribed
+// boundary values) instead of 0.
 hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
                                    const double* xskel, double* u, int k, double* scratch, int grid,
-                                   hipStream_t st);
+                                   int keep_con, hipStream_t st);
 
 // Skeleton <-> nodal copies (FP64).
+// keep_con: copy the values of Dirichlet nodes too (else they are written as 0).
 hipError_t launch_skel_to_nodal(const Layout& L, const double* skel, double* nodal, int64_t N, int k,
-                                hipStream_t st);
+                                int keep_con, hipStream_t st);
+// Zero the entries of free nodes (keep = constrained) or of Dirichlet nodes
+// (keep = free) of an [N_s][k] array.
+enum KeepNodes { KEEP_FREE = 0, KEEP_CONSTRAINED = 1 };
+hipError_t launch_mask_nodes(const Layout& L, double* x, int k, int keep, hipStream_t st);
+// y += a x (n values).
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st);
 hipError_t launch_nodal_to_skel(const Layout& L, const double* nodal, double* skel, int64_t N, int k,
                                 hipStream_t st);
 

@@ -349,7 +349,8 @@ hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const do
 
 __global__ __launch_bounds__(256) void k_recover_interior(Geo g, DevTab<double> tab, const double* __restrict__ f,
                                                           int64_t N, const double* __restrict__ xs,
-                                                          double* __restrict__ u, int k, double* scratch) {
+                                                          double* __restrict__ u, int k, double* scratch,
+                                                          int keep_con) {
     extern __shared__ double cube_lds[];
     __shared__ int64_t fb[6];
     __shared__ int fc[6];
@@ -371,7 +372,7 @@ __global__ __launch_bounds__(256) void k_recover_interior(Geo g, DevTab<double> 
         }
         for (int r = 0; r < k; ++r) {
             cube_transformed_rhs(cube, g, tab, tab.St, f, N, r, e1, e2, e3);
-#define UF(face, s1, s2) (fc[face] ? 0.0 : xs[(fb[face] + (int64_t)(s1) * NI + (s2)) * k + r])
+#define UF(face, s1, s2) ((fc[face] && !keep_con) ? 0.0 : xs[(fb[face] + (int64_t)(s1) * NI + (s2)) * k + r])
             for (int idx = threadIdx.x; idx < NI2 * NI; idx += blockDim.x) {
                 const int i = idx % NI, j = (idx / NI) % NI, kk = idx / NI2;
                 const double uc = d[1] * (tab.a[i] * UF(0, kk, j) + tab.b[i] * UF(1, kk, j)) +
@@ -402,10 +403,11 @@ __global__ __launch_bounds__(256) void k_recover_interior(Geo g, DevTab<double> 
 
 hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
                                    const double* xskel, double* u, int k, double* scratch, int grid,
-                                   hipStream_t st) {
+                                   int keep_con, hipStream_t st) {
     const int n = g.L.p + 1;
     const size_t shm = scratch ? 0 : (size_t)n * n * n * sizeof(double);
-    hipLaunchKernelGGL(k_recover_interior, dim3(grid), dim3(256), shm, st, g, tab, f, N, xskel, u, k, scratch);
+    hipLaunchKernelGGL(k_recover_interior, dim3(grid), dim3(256), shm, st, g, tab, f, N, xskel, u, k, scratch,
+                       keep_con);
     return hipGetLastError();
 }
 
@@ -421,12 +423,27 @@ __device__ inline int64_t skel_nodal_index(const Layout& L, int64_t s, bool* con
 }
 
 __global__ void k_skel_to_nodal(Layout L, const double* __restrict__ skel, double* __restrict__ nodal, int64_t N,
-                                int k) {
+                                int k, int keep_con) {
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < L.Ns; s += (int64_t)gridDim.x * blockDim.x) {
         bool con;
         const int64_t g = skel_nodal_index(L, s, &con);
-        for (int r = 0; r < k; ++r) nodal[(int64_t)r * N + g] = con ? 0.0 : skel[s * k + r];
+        for (int r = 0; r < k; ++r) nodal[(int64_t)r * N + g] = (con && !keep_con) ? 0.0 : skel[s * k + r];
     }
+}
+
+__global__ void k_mask_nodes(Layout L, double* __restrict__ x, int k, int keep) {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < L.Ns; s += (int64_t)gridDim.x * blockDim.x) {
+        int I1, I2, I3;
+        bool con;
+        skeleton_node(L, s, &I1, &I2, &I3, &con);
+        if (con != (keep == KEEP_CONSTRAINED))
+            for (int r = 0; r < k; ++r) x[s * k + r] = 0.0;
+    }
+}
+
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += a * x[i];
 }
 
 __global__ void k_nodal_to_skel(Layout L, const double* __restrict__ nodal, double* __restrict__ skel, int64_t N,
@@ -446,8 +463,20 @@ static int grid_for(int64_t n, int threads) {
 }
 
 hipError_t launch_skel_to_nodal(const Layout& L, const double* skel, double* nodal, int64_t N, int k,
-                                hipStream_t st) {
-    hipLaunchKernelGGL(k_skel_to_nodal, dim3(grid_for(L.Ns, 256)), dim3(256), 0, st, L, skel, nodal, N, k);
+                                int keep_con, hipStream_t st) {
+    hipLaunchKernelGGL(k_skel_to_nodal, dim3(grid_for(L.Ns, 256)), dim3(256), 0, st, L, skel, nodal, N, k,
+                       keep_con);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_nodes(const Layout& L, double* x, int k, int keep, hipStream_t st) {
+    hipLaunchKernelGGL(k_mask_nodes, dim3(grid_for(L.Ns, 256)), dim3(256), 0, st, L, x, k, keep);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(n, 256)), dim3(256), 0, st, y, x, a, n);
     return hipGetLastError();
 }
 

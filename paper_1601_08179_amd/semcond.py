@@ -36,7 +36,7 @@ class SolveOpts(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("recover_interior", ctypes.c_int),
                 ("x0", ctypes.c_void_p), ("skel_out", ctypes.c_void_p),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("rhs_dual", ctypes.c_int),
-                ("persistent", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("g_dirichlet", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -362,10 +362,11 @@ class Context:
 
     def solve(self, f, out=None, tol=1e-10, max_iter=20000, precision=PREC_F64, check_every=8,
               recover_interior=True, x0=None, skel_out=None, inner_tol=1e-5, max_outer=30,
-              rhs_dual=False, persistent=None, stream=None, raise_on_notconv=True):
+              rhs_dual=False, persistent=None, stream=None, raise_on_notconv=True, g=None):
         """Solve for nodal right-hand sides f (k, N) or (N,), FP64.  Returns (u, info).
         persistent: True (one persistent CG launch), False (one launch per step) or None
-        (the autotuned choice, else one launch per step)."""
+        (the autotuned choice, else one launch per step).  g: optional nodal array like f
+        with the prescribed values on the Dirichlet faces (inhomogeneous conditions)."""
         import torch
         k = self._k_nodal(f, "f")
         if f.dtype != torch.float64:
@@ -385,6 +386,10 @@ class Context:
         o.max_outer = max_outer
         o.rhs_dual = 1 if rhs_dual else 0
         o.persistent = CG_AUTO if persistent is None else (CG_PERSISTENT if persistent else CG_STEPWISE)
+        if g is not None:
+            if g.shape != f.shape or g.dtype != torch.float64:
+                raise ValueError("g must match f (shape, float64)")
+            o.g_dirichlet = _dev(g, "g").value
         info = (SolveInfo * k)()
         allow = (OK, ENOTCONV) if not raise_on_notconv else (OK,)
         _check(_lib.semcond_solve(self._h, _dev(f, "f"), _dev(out, "out"), k, ctypes.byref(o), info,
