@@ -92,8 +92,10 @@ def suite(args):
     """Measurements beyond the default line, one JSON line per case:
     p/aspect-ratio sweep at N = 257^3 (FP64 solve to 1e-10 and apply rate),
     16 right-hand sides at 24^3 elements, p = 12 (FP64 batched vs mixed
-    precision, each CG launch kind), and the differentiable solve's forward and
-    backward on 8^3 elements, p = 8, k = 8."""
+    precision, each CG launch kind), the differentiable solve's forward and
+    backward on 8^3 elements, p = 8, k = 8, and the paper's solver experiment
+    (manufactured solution with inhomogeneous Dirichlet values, lambda = 0,
+    8^3 elements, expansion factors 1, 1.5, 2, p = 8..32)."""
     import numpy as np
     import torch
 
@@ -159,6 +161,50 @@ def suite(args):
         del ft, u
         ctx.close()
         torch.cuda.empty_cache()
+    if "D" in args.suite:
+        # Solver experiment of Sec. 8: manufactured u (stiffness 5) on (0, 2 pi)^3,
+        # lambda = 0, 8^3 elements with expansion factor alpha, inhomogeneous
+        # Dirichlet values u_ex, stop at a 1e-12 residual reduction.  For alpha = 2
+        # the paper's BT iteration counts follow from Table 3 as solution time per
+        # DOF / iteration time per DOF (upper bounds: the solution time includes
+        # the precomputation).
+        table3 = {8: (4.25, 25.6), 12: (3.73, 20.3), 16: (3.47, 17.7), 20: (3.31, 16.1), 24: (3.09, 14.4),
+                  28: (2.88, 13.1), 32: (2.81, 12.4)}
+        for alpha in (1.0, 1.5, 2.0):
+            for p in (8, 12, 16, 20, 24, 28, 32):
+                wm = W.solver_experiment_mesh(p, alpha)
+                X = W.nodal_coordinates(p, wm["n"], wm["widths"], semcond.host_tables(p)["x"])
+                uex = W.manufactured_u(X, 5.0)
+                f = -W.manufactured_laplacian(X, 5.0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx = semcond.Context(wm)
+                torch.cuda.synchronize()
+                setup_s = time.perf_counter() - t0
+                ft = torch.as_tensor(f, device="cuda")
+                gt = torch.as_tensor(uex, device="cuda")
+                u = torch.zeros_like(ft)
+                ctx.solve(ft, out=u, tol=1e-12, g=gt)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = ctx.solve(ft, out=u, tol=1e-12, g=gt)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                err = float(np.abs(u.cpu().numpy() - uex).max() / np.abs(uex).max())
+                rec = {"case": "solver experiment (Sec. 8): 8^3 elements, lambda=0, inhomogeneous Dirichlet",
+                       "alpha": alpha, "p": p, "N": ctx.N, "iters": info[0]["iters"],
+                       "rel_res": info[0]["rel_res"], "solve_ms": dt * 1e3, "setup_ms": setup_s * 1e3,
+                       "ns_per_dof_iter": dt / (ctx.N * info[0]["iters"]) * 1e9,
+                       "us_per_dof_solve_incl_setup": (dt + setup_s) / ctx.N * 1e6,
+                       "max_rel_error_vs_exact": err}
+                if alpha == 2.0:
+                    sol_us, it_ns = table3[p]
+                    rec["paper_bt_iters_from_table3"] = round(sol_us * 1e3 / it_ns)
+                    rec["paper_bt_ns_per_dof_iter"] = it_ns
+                emit(rec)
+                del ft, gt, u
+                ctx.close()
+                torch.cuda.empty_cache()
     if "5" in args.suite:
         wmesh, f, t = W.config5()
         ctx = semcond.Context(wmesh)
@@ -322,7 +368,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--suite", default="", help="extra measurements instead of the default line: "
-                    "any of 3 (p/AR sweep), 4 (16 RHS), 5 (differentiable solve), e.g. --suite 345")
+                    "any of 3 (p/AR sweep), 4 (16 RHS), 5 (differentiable solve), D (the paper's "
+                    "solver experiment with inhomogeneous Dirichlet values), e.g. --suite 345D")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the dispatches the rocprofv3 counter runs read")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

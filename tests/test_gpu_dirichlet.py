@@ -82,3 +82,31 @@ def test_initial_guess_dirichlet_entries_ignored(lib):
     u, info = ctx.solve(_t(f), tol=1e-13, g=_t(g), x0=x0)
     ref = op.solve_full_dirichlet(f, g)
     assert np.abs(u.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("p,paper_iters", [(8, 166), (16, 196)])
+def test_solver_experiment_iteration_counts(lib, p, paper_iters):
+    """Sec. 8's solver test with expansion factor 2 (aspect ratio 128): the BT
+    iteration count to a 1e-12 residual reduction matches the count implied by
+    Table 3 (solution time per DOF / iteration time per DOF) within 3."""
+    import torch
+    wm = W.solver_experiment_mesh(p, 2.0)
+    X = _coords(wm)
+    ctx = lib.Context(wm)
+    f = torch.as_tensor(-W.manufactured_laplacian(X, 5.0), device="cuda")
+    g = torch.as_tensor(W.manufactured_u(X, 5.0), device="cuda")
+    _, info = ctx.solve(f, tol=1e-12, g=g)
+    print("iterations", p, info[0]["iters"], "paper", paper_iters)
+    assert abs(info[0]["iters"] - paper_iters) <= 3
+
+
+def test_solver_experiment_uniform_mesh_converges(lib):
+    """Expansion factor 1: the error against the exact solution at p = 24 is below 1e-6."""
+    import torch
+    wm = W.solver_experiment_mesh(24, 1.0)
+    X = _coords(wm)
+    uex = W.manufactured_u(X, 5.0)
+    ctx = lib.Context(wm)
+    u, _ = ctx.solve(torch.as_tensor(-W.manufactured_laplacian(X, 5.0), device="cuda"), tol=1e-12,
+                     g=torch.as_tensor(uex, device="cuda"))
+    assert np.abs(u.cpu().numpy() - uex).max() <= 1e-6 * np.abs(uex).max()
