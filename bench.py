@@ -205,6 +205,30 @@ def suite(args):
                 del ft, gt, u
                 ctx.close()
                 torch.cuda.empty_cache()
+    if "S" in args.suite:
+        # Element-count scaling of the solver experiment (Sec. 8): expansion factor
+        # 1, p = 16, n^3 elements for n = 2..16.
+        for n in (2, 4, 6, 8, 10, 12, 14, 16):
+            wm = W.solver_experiment_mesh(16, 1.0, n=n)
+            X = W.nodal_coordinates(16, wm["n"], wm["widths"], semcond.host_tables(16)["x"])
+            uex = W.manufactured_u(X, 5.0)
+            ctx = semcond.Context(wm)
+            ft = torch.as_tensor(-W.manufactured_laplacian(X, 5.0), device="cuda")
+            gt = torch.as_tensor(uex, device="cuda")
+            u = torch.zeros_like(ft)
+            ctx.solve(ft, out=u, tol=1e-12, g=gt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = ctx.solve(ft, out=u, tol=1e-12, g=gt)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            emit({"case": "element-count scaling (Sec. 8): expansion factor 1, p=16, lambda=0", "n_e": n ** 3,
+                  "N": ctx.N, "iters": info[0]["iters"], "solve_ms": dt * 1e3,
+                  "ns_per_dof_iter": dt / (ctx.N * info[0]["iters"]) * 1e9,
+                  "max_rel_error_vs_exact": float(np.abs(u.cpu().numpy() - uex).max() / np.abs(uex).max())})
+            del ft, gt, u
+            ctx.close()
+            torch.cuda.empty_cache()
     if "5" in args.suite:
         wmesh, f, t = W.config5()
         ctx = semcond.Context(wmesh)
@@ -369,7 +393,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--suite", default="", help="extra measurements instead of the default line: "
                     "any of 3 (p/AR sweep), 4 (16 RHS), 5 (differentiable solve), D (the paper's "
-                    "solver experiment with inhomogeneous Dirichlet values), e.g. --suite 345D")
+                    "solver experiment with inhomogeneous Dirichlet values), S (its element-count "
+                    "scaling), e.g. --suite 345DS")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the dispatches the rocprofv3 counter runs read")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

@@ -713,7 +713,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                 }
             }
         }
-        __syncthreads();
+        if constexpr (!ONE) __syncthreads();  // LDS is reused by the next item
     };
     if constexpr (ONE) {
         const int64_t e = e0 + grp;
