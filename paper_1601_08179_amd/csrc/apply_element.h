@@ -102,7 +102,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
     elem_index(A.g.L, e, &e1, &e2, &e3);
     double dd[4];
     elem_metric(A.g, e, e1, e2, e3, dd);
-    const T d0 = (T)dd[0], d1 = (T)dd[1], d2 = (T)dd[2], d3 = (T)dd[3];
+    const T d0e = (T)dd[0], d1e = (T)dd[1], d2e = (T)dd[2], d3e = (T)dd[3];
     const T m0 = A.tab.m0, K00 = A.tab.K00, K0p = A.tab.K0p, m02 = m0 * m0;
     const int k = A.k;
 
@@ -120,12 +120,28 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
     const T* lam = tl;
     const T* ca = tl + NI;
     const T* cb = tl + 2 * NI;
+    // line-sum split of the plane path: RG lanes per line (largest power of
+    // two <= 16 with all 2 n_I lines in one round), RT terms per lane
+    constexpr int RG = 2 * NI * 16 <= NT ? 16 : (2 * NI * 8 <= NT ? 8 : 4);
+    constexpr int RT = (NI + RG - 1) / RG;
+    const int rh = tid & (RG - 1);
+    T rca[RT], rcb[RT];
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+        const int m = rh + RG * q;
+        rca[q] = m < NI ? ca[m] : (T)0;
+        rcb[q] = m < NI ? cb[m] : (T)0;
+    }
 
 #define UF(f, s1, s2) F[(f) * NI2 + (s1) * NI + (s2)]
 #define UE(q, m) F[NFACE + (q) * NI + (m)]
 #define UV(q) F[NFACE + NEDGE + (q)]
 
     for (int r = 0; r < k; ++r) {
+        // The products of the metric terms are formed anew for every right-hand
+        // side instead of being kept live across the loop (register pressure).
+        T d0 = d0e, d1 = d1e, d2 = d2e, d3 = d3e;
+        asm volatile("" : "+v"(d0), "+v"(d1), "+v"(d2), "+v"(d3));
         // ---- gather R^T: skeleton -> element boundary (constrained entities read as 0).
         // All loads of a thread are issued before any is consumed: the slot
         // addresses are formed first, constrained slots read index r (a valid
@@ -213,25 +229,31 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                     acct += bk * vc;
                 }
                 __syncthreads();
-                if (tid < NI) {
-                    T sw = 0, se = 0;
-                    for (int m = 0; m < NI; ++m) {
-                        const T v = P[tid * NI + m];
-                        sw += ca[m] * v;
-                        se += cb[m] * v;
+                // Line sums of the plane (Table 2): w/e along i for row j = l,
+                // s/n along j for column i = l, with both coefficient rows.
+                // Each line takes an aligned group of RG lanes, lane h summing
+                // the terms h, h + RG, ... with its preloaded coefficients; the
+                // group's partial sums are combined by a fixed in-row tree.
+                for (int line = tid / RG; line < 2 * NI; line += NT / RG) {
+                    const bool row = line < NI;
+                    const int l = row ? line : line - NI;
+                    const int sl = row ? NI : 1, sm = row ? 1 : NI;
+                    T sa = 0, sb = 0;
+#pragma unroll
+                    for (int q = 0; q < RT; ++q) {
+                        const int m = rh + RG * q;
+                        const T v = m < NI ? P[l * sl + m * sm] : (T)0;
+                        sa += rca[q] * v;
+                        sb += rcb[q] * v;
                     }
-                    OF[0 * NI2 + kk * NI + tid] = -d1 * sw;
-                    OF[1 * NI2 + kk * NI + tid] = -d1 * se;
-                } else if (tid < 2 * NI) {
-                    const int c = tid - NI;
-                    T ss = 0, sn = 0;
-                    for (int m = 0; m < NI; ++m) {
-                        const T v = P[m * NI + c];
-                        ss += ca[m] * v;
-                        sn += cb[m] * v;
+                    sa = group_sum<RG>(sa);
+                    sb = group_sum<RG>(sb);
+                    if (rh == 0) {
+                        const T dl = row ? -d1 : -d2;
+                        const int o = (row ? 0 : 2) * NI2 + kk * NI + l;
+                        OF[o] = dl * sa;
+                        OF[o + NI2] = dl * sb;
                     }
-                    OF[2 * NI2 + kk * NI + c] = -d2 * ss;
-                    OF[3 * NI2 + kk * NI + c] = -d2 * sn;
                 }
             }
             if (tid < NI2) {
@@ -298,20 +320,24 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
             for (int idx = tid; idx < 4 * NI; idx += NT) {
                 const int qq = idx / NI, m = idx - (idx / NI) * NI;
                 const int b0 = qq & 1, b1 = qq >> 1, q = 4 * par + qq;
-                const T* c0 = b0 ? cb : ca;
-                const T* c1 = b1 ? cb : ca;
                 // X(jb,kb): sum_j c^jb_j b/t(kb)[j][m], sum_k c^kb_k s/n(jb)[k][m]
                 // Y(ib,kb): sum_i c^ib_i b/t(kb)[m][i], sum_k c^kb_k w/e(ib)[k][m]
                 // Z(ib,jb): sum_i c^ib_i s/n(jb)[m][i], sum_j c^jb_j w/e(ib)[m][j]
                 const int f1 = (par == 2 ? 2 : 4) + b1, f2 = (par == 0 ? 2 : 0) + b0;
                 const int base1 = f1 * NI2 + (par == 0 ? m : m * NI), st1 = par == 0 ? NI : 1;
                 const int base2 = f2 * NI2 + (par == 2 ? m * NI : m), st2 = par == 2 ? 1 : NI;
-                T l1 = 0, l2 = 0;
-#pragma unroll
+                // both coefficient rows, then the thread's pick (no per-term selects)
+                T l1a = 0, l1b = 0, l2a = 0, l2b = 0;
+#pragma unroll 2
                 for (int m2 = 0; m2 < NI; ++m2) {
-                    l1 += c0[m2] * F[base1 + m2 * st1];
-                    l2 += c1[m2] * F[base2 + m2 * st2];
+                    const T am = ca[m2], bm = cb[m2];
+                    const T x1 = F[base1 + m2 * st1], x2 = F[base2 + m2 * st2];
+                    l1a += am * x1;
+                    l1b += bm * x1;
+                    l2a += am * x2;
+                    l2b += bm * x2;
                 }
+                const T l1 = b0 ? l1b : l1a, l2 = b1 ? l2b : l2a;
                 const int vlo = par == 0 ? 2 * b0 + 4 * b1 : (par == 1 ? b0 + 4 * b1 : b0 + 2 * b1);
                 const int vhi = vlo + (par == 0 ? 1 : (par == 1 ? 2 : 4));
                 const T ue = UE(q, m);
@@ -326,16 +352,19 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
         // ---- vertices
         if (tid < 8) {
             const int q = tid, ib = q & 1, jb = (q >> 1) & 1, kb = q >> 2;
-            const T* ci_ = ib ? cb : ca;
-            const T* cj_ = jb ? cb : ca;
-            const T* ck_ = kb ? cb : ca;
-            T sx = 0, sy = 0, sz = 0;
-#pragma unroll
+            T sxa = 0, sxb = 0, sya = 0, syb = 0, sza = 0, szb = 0;
+#pragma unroll 2
             for (int m2 = 0; m2 < NI; ++m2) {
-                sx += ci_[m2] * UE(jb + 2 * kb, m2);
-                sy += cj_[m2] * UE(4 + ib + 2 * kb, m2);
-                sz += ck_[m2] * UE(8 + ib + 2 * jb, m2);
+                const T am = ca[m2], bm = cb[m2];
+                const T x = UE(jb + 2 * kb, m2), y = UE(4 + ib + 2 * kb, m2), z = UE(8 + ib + 2 * jb, m2);
+                sxa += am * x;
+                sxb += bm * x;
+                sya += am * y;
+                syb += bm * y;
+                sza += am * z;
+                szb += bm * z;
             }
+            const T sx = ib ? sxb : sxa, sy = jb ? syb : sya, sz = kb ? szb : sza;
             const T out = (d0 * m02 * m0 + (d1 + d2 + d3) * m02 * K00) * UV(q) +
                           m02 * K0p * (d1 * UV(q ^ 1) + d2 * UV(q ^ 2) + d3 * UV(q ^ 4)) +
                           m02 * (d1 * sx + d2 * sy + d3 * sz);

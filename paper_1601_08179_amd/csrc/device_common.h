@@ -105,6 +105,36 @@ __device__ inline void atomic_add(T* p, T v) {
     unsafeAtomicAdd(p, v);
 }
 
+// x plus the value of the lane that the data-parallel-primitive control CTRL
+// selects (a permutation inside each row of 16 lanes; every lane of the row
+// must be active).  Controls used: 0xB1 quad_perm(1,0,3,2) = lane ^ 1,
+// 0x4E quad_perm(2,3,0,1) = lane ^ 2, 0x141 row_half_mirror (7 - lane within
+// 8), 0x140 row_mirror (15 - lane within 16).  Applied in that order, the first
+// 1, 2, 3 or 4 of them leave every lane of an aligned group of 2, 4, 8 or 16
+// lanes holding the sum over its group, the same in every lane.
+template <int CTRL>
+__device__ inline float dpp_add(float x) {
+    const int y = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false);
+    return x + __builtin_bit_cast(float, y);
+}
+template <int CTRL>
+__device__ inline double dpp_add(double x) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return x + __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// Sum over aligned groups of G lanes (G = 1, 2, 4, 8, 16), same in every lane of
+// the group.
+template <int G, typename T>
+__device__ inline T group_sum(T x) {
+    if constexpr (G >= 2) x = dpp_add<0xB1>(x);
+    if constexpr (G >= 4) x = dpp_add<0x4E>(x);
+    if constexpr (G >= 8) x = dpp_add<0x141>(x);
+    if constexpr (G >= 16) x = dpp_add<0x140>(x);
+    return x;
+}
+
 // Wave64 sum.
 template <typename T>
 __device__ inline T wave_sum(T v) {

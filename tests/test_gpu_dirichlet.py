@@ -110,3 +110,26 @@ def test_solver_experiment_uniform_mesh_converges(lib):
     u, _ = ctx.solve(torch.as_tensor(-W.manufactured_laplacian(X, 5.0), device="cuda"), tol=1e-12,
                      g=torch.as_tensor(uex, device="cuda"))
     assert np.abs(u.cpu().numpy() - uex).max() <= 1e-6 * np.abs(uex).max()
+
+
+@pytest.mark.parametrize("p", [17, 24, 32])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_harmonic_quadratics_high_order(lib, p, precision):
+    """The k-plane element path (n_I >= 16, every line-sum split it uses):
+    two harmonic quadratics prescribed on the boundary of a stretched 2x1x2 mesh
+    come back at every node to rounding, in FP64 and with the FP32 inner solve of
+    the mixed iterative refinement.  Exact at any p (the GLL quadrature
+    integrates the stiffness of a quadratic exactly), so it needs no oracle."""
+    print("case", p, precision, flush=True)
+    wm = W.mesh(p, (2, 1, 2), widths=[[0.3, 0.7], [1.0], [0.6, 0.4]], lam=0.0)
+    X = _coords(wm)
+    u1 = X[:, 0] * X[:, 1] * X[:, 2] + X[:, 0] ** 2 - X[:, 1] ** 2
+    u2 = 2.0 * X[:, 2] ** 2 - X[:, 0] ** 2 - X[:, 1] ** 2 + 3.0 * X[:, 1] + 1.0
+    uex = np.stack([u1, u2])
+    ctx = lib.Context(wm)
+    kw = dict(precision=lib.PREC_MIXED_IR, inner_tol=1e-5) if precision == "mixed" else {}
+    u, info = ctx.solve(_t(np.zeros_like(uex)), tol=1e-13, g=_t(uex), **kw)
+    err = np.abs(u.cpu().numpy() - uex).max() / np.abs(uex).max()
+    print("p", p, precision, "iters", [i["iters"] for i in info], "max rel err", err, flush=True)
+    assert err <= 1e-10
+    ctx.close()
