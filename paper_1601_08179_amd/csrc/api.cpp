@@ -70,6 +70,7 @@ struct semcond_ctx {
     Buffer ws_lift;     // prescribed Dirichlet values (transformed) and a temporary
     int* h_active = nullptr;  // pinned host copy of CG activity flags
     int h_active_cap = 0;
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};  // lagged convergence polls of the fused CG loop
     // persistent CG launch configuration per (k, dtype): (S, G)
     std::map<std::pair<int, int>, std::pair<int, int>> tuned;
     // tracing: event pairs around kernel launches, with the kernel id
@@ -234,7 +235,7 @@ enum VecLayout { NODE_MAJOR = 0, RHS_MAJOR = 1 };
 template <typename T>
 int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, double* energy, hipStream_t st,
                       bool v_is_zero = false, const T* dir_r = nullptr, const double* dir_beta = nullptr,
-                      int read_con = 0) {
+                      int read_con = 0, const CgFuse* fz = nullptr) {
     if (!v_is_zero) HIPCHK(c, launch_fill<T>(v, c->N_s * k, (T)0, st));
     ApplyArgs<T> a = apply_args<T>(c);
     a.u = u;
@@ -249,6 +250,7 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, do
         a.dir_r = dir_r;
         a.dir_pinv = pinv<T>(c);
         a.dir_beta = dir_beta;
+        if (fz) a.fz = *fz;
     }
     if (c->prof) {
         int rc = profile_begin(c, SEMCOND_KERNEL_APPLY, st);
@@ -314,13 +316,15 @@ struct CgWork {
     CgState s;
     double* partials;  // [3][vec_blocks(k)][k] (room for [3][kVecBlocks][k])
     double* energy;    // [n_e][k]
+    double* rho1;      // second slots of rho and active (fused loop, odd iterations)
+    int* act1;
 };
 
 // Device state layout inside ws_state: two independent CG states (slot 0 for
 // the CG iteration, slot 1 for the outer refinement loop of MIXED_IR).
 int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
-    const size_t nd = 7 * (size_t)k + 1;               // rho pq alpha beta rr bb (6k) + spare k + tol2
-    const size_t ni = 3 * (size_t)k;                    // active iters status
+    const size_t nd = 7 * (size_t)k + 1;               // rho pq alpha beta rr bb (6k) + rho slot 1 + tol2
+    const size_t ni = 4 * (size_t)k;                    // active iters status + active slot 1
     const size_t np = 3 * (size_t)kVecBlocks * k;
     const size_t ne = (size_t)c->n_e * k;
     const size_t one = ((nd + np + ne) * sizeof(double) + ni * sizeof(int) + 255) / 256 * 256;
@@ -334,12 +338,14 @@ int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
     w->s.rr = d + 4 * k;
     w->s.bb = d + 5 * k;
     w->s.tol2 = d + 7 * k;
+    w->rho1 = d + 6 * k;
     w->partials = d + nd;
     w->energy = w->partials + np;
     int* ip = (int*)(w->energy + ne);
     w->s.active = ip;
     w->s.iters = ip + k;
     w->s.status = ip + 2 * k;
+    w->act1 = ip + 3 * k;
     if (c->h_active_cap < 3 * k) {
         if (c->h_active) hipHostFree(c->h_active);
         c->h_active = nullptr;
@@ -371,6 +377,36 @@ int read_state(semcond_ctx* c, const CgWork& w, int k, CgHost* h, hipStream_t st
     return SEMCOND_OK;
 }
 
+// Largest n_e k for which the CG loop completes its reductions inside the
+// consuming kernels.
+constexpr int64_t kFusedMaxItems = 16384;
+
+// Views of the CG state for iteration parity ph (slot ph: this iteration's
+// rho / active; slot 1 - ph: the previous iteration's); the apply's partial
+// sums are set by the caller from the second iteration on.
+CgFuse fuse_view(const CgWork& w, int k, int ph, int64_t n_e) {
+    CgFuse f = {};
+    double* rho[2] = {w.s.rho, w.rho1};
+    int* act[2] = {w.s.active, w.act1};
+    f.part = w.partials;
+    f.nsb = fused_step_blocks(k);
+    f.energy = w.energy;
+    f.n_e = n_e;
+    f.rho_prev = rho[1 - ph];
+    f.act_prev = act[1 - ph];
+    f.rho = rho[ph];
+    f.act = act[ph];
+    f.beta = w.s.beta;
+    f.rr = w.s.rr;
+    f.iters = w.s.iters;
+    f.status = w.s.status;
+    f.bb = w.s.bb;
+    f.tol2 = w.s.tol2;
+    f.pq = w.s.pq;
+    f.alpha = w.s.alpha;
+    return f;
+}
+
 // Preconditioned CG on the transformed condensed system, k RHS, type T.
 // b, x, r, p, q: [N_s][k] of T.  x holds the initial guess on entry (x0_given)
 // or is zeroed.  Returns per-RHS iterations/status through the state.
@@ -391,21 +427,71 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     }
     HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 3, k, w.s, RED_INIT, st));
     if (check_every < 1) check_every = 1;
+    // Small problems complete both reductions inside the kernels that consume
+    // them (two launches per iteration instead of four); the redundant reads
+    // of the partial sums grow with n_e k.
+    const bool fused = c->n_e * (int64_t)k <= kFusedMaxItems;
+    if (fused)
+        for (hipEvent_t& e : c->poll_ev)
+            if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    auto none_active = [&](const int* h) {
+        for (int i = 0; i < k; ++i)
+            if (h[i]) return false;
+        return true;
+    };
+    int n_it = 0, pending = -1;
     for (int it = 0; it < max_iter; ++it) {
         if (it % check_every == 0) {
-            HIPCHK(c, hipMemcpyAsync(c->h_active, w.s.active, k * sizeof(int), hipMemcpyDeviceToHost, st));
-            HIPCHK(c, hipStreamSynchronize(st));
-            bool any = false;
-            for (int i = 0; i < k; ++i) any |= c->h_active[i] != 0;
-            if (!any) break;
+            if (fused && it > 0) {
+                // Lagged poll: copy the latest flags with an event and look at
+                // the copy made one check interval earlier, so the queue never
+                // drains; iterations queued after convergence exit at once.
+                const int b = (it / check_every) & 1;
+                const int* act = ((it - 1) & 1) ? w.act1 : w.s.active;
+                HIPCHK(c, hipMemcpyAsync(c->h_active + b * k, act, k * sizeof(int), hipMemcpyDeviceToHost, st));
+                HIPCHK(c, hipEventRecord(c->poll_ev[b], st));
+                if (pending >= 0) {
+                    HIPCHK(c, hipEventSynchronize(c->poll_ev[pending]));
+                    if (none_active(c->h_active + pending * k)) break;
+                }
+                pending = b;
+            } else {
+                HIPCHK(c, hipMemcpyAsync(c->h_active, w.s.active, k * sizeof(int), hipMemcpyDeviceToHost, st));
+                HIPCHK(c, hipStreamSynchronize(st));
+                if (none_active(c->h_active)) break;
+            }
         }
         // q is zero here: zeroed at start and by every step.  The apply forms
         // the direction p = beta p + z at its gather; the step stores it.
-        int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta);
-        if (rc) return rc;
-        HIPCHK(c, launch_cg_reduce(w.energy, c->n_e, 1, k, w.s, RED_PQ, st));
-        HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, st));
-        HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 2, k, w.s, RED_RZ, st));
+        if (fused) {
+            // slot it & 1 is this iteration's rho / active, the other the previous one's
+            const CgFuse f = fuse_view(w, k, it & 1, c->n_e);
+            int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta, 0,
+                                          it > 0 ? &f : nullptr);
+            if (rc) return rc;
+            HIPCHK(c, launch_cg_step_fused<T>(x, r, p, q, pinv<T>(c), Ns, k, f, w.partials, st));
+        } else {
+            int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta);
+            if (rc) return rc;
+            HIPCHK(c, launch_cg_reduce(w.energy, c->n_e, 1, k, w.s, RED_PQ, st));
+            HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, st));
+            HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 2, k, w.s, RED_RZ, st));
+        }
+        n_it = it + 1;
+    }
+    if (fused && n_it > 0) {
+        // the last step's r.z reduction, then the state back in slot 0
+        const bool odd = ((n_it - 1) & 1) != 0;
+        CgState v = w.s;
+        if (odd) {
+            v.rho = w.rho1;
+            v.active = w.act1;
+        }
+        HIPCHK(c, launch_cg_reduce(w.partials, fused_step_blocks(k), 2, k, v, RED_RZ, st));
+        if (odd) {
+            HIPCHK(c, hipMemcpyAsync(w.s.rho, w.rho1, k * sizeof(double), hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipMemcpyAsync(w.s.active, w.act1, k * sizeof(int), hipMemcpyDeviceToDevice, st));
+        }
     }
     return SEMCOND_OK;
 }
@@ -738,6 +824,8 @@ int semcond_destroy(semcond_ctx* c) {
     hipFree(c->ws_persist.ptr);
     hipFree(c->ws_lift.ptr);
     if (c->h_active) hipHostFree(c->h_active);
+    for (hipEvent_t e : c->poll_ev)
+        if (e) hipEventDestroy(e);
     for (hipEvent_t e : c->ev) hipEventDestroy(e);
     delete c;
     return SEMCOND_OK;

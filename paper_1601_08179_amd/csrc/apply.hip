@@ -6,20 +6,49 @@
 #include <hip/hip_runtime.h>
 
 #include "apply_element.h"
+#include "cg_device.h"
 
 namespace semcond {
 
 template <typename T, int NI, bool DIR>
 __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A, int64_t n_elem) {
-    if constexpr (NI <= 15) {
+    constexpr int NT = apply_threads(NI);
+    constexpr bool CUBE = NI <= 15;
+    const double* beta = A.dir_beta;
+    if constexpr (DIR) {
+        // CG direction with the previous step's r.z completed here: every
+        // workgroup reduces the step's partial sums for its right-hand sides
+        // (the cube form: RHS y; the plane form: all) in one fixed order
+        __shared__ double s_beta[kMaxRhs];
+        __shared__ double s_red[2 * (NT / 64)];
+        if (A.fz.part) {
+            const int r0 = CUBE ? (int)blockIdx.y : 0, nr = CUBE ? 1 : A.k;
+            const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+            bool any = false;
+            for (int r = r0; r < r0 + nr; ++r) {
+                double t[2];
+                block_sums<NT, 2>(A.fz.part + r, (int64_t)A.fz.nsb * A.k, A.fz.nsb, A.k, s_red, t);
+                bool still;
+                const double b = cg_rz_complete(A.fz, r, t[0], t[1], writer, &still);
+                any |= still;
+                if (threadIdx.x == 0) s_beta[r] = b;
+            }
+            // nothing to apply once every RHS of the workgroup has stopped (the
+            // step ignores the energies of stopped RHS); the same in all threads
+            if (!any) return;
+            __syncthreads();
+            beta = s_beta;
+        }
+    }
+    if constexpr (CUBE) {
         // workgroup (x, y): elements e_begin + x*E .. + E - 1, right-hand side y
         constexpr int E = apply_pack(NI);
         __shared__ ApplySmem<T, NI> sm[E];
         apply_elements_cube<T, NI, DIR, true, E>(A, A.e_begin + (int64_t)blockIdx.x * E, 1, 1, A.e_begin + n_elem,
-                                                 blockIdx.y, 1, sm, nullptr, threadIdx.x, A.dir_beta);
+                                                 blockIdx.y, 1, sm, nullptr, threadIdx.x, beta);
     } else {
         __shared__ ApplySmem<T, NI> sm;
-        apply_element<T, NI, DIR>(A, (int64_t)blockIdx.x + A.e_begin, sm, nullptr, threadIdx.x, true, A.dir_beta);
+        apply_element<T, NI, DIR>(A, (int64_t)blockIdx.x + A.e_begin, sm, nullptr, threadIdx.x, true, beta);
     }
 }
 

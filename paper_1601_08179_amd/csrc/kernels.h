@@ -8,6 +8,45 @@
 
 namespace semcond {
 
+// Per-RHS scalars of the conjugate gradients (device arrays of k entries).
+struct CgState {
+    double* rho;     // r.z
+    double* pq;      // p.q
+    double* alpha;
+    double* beta;
+    double* rr;      // r.r
+    double* bb;      // b.b
+    double* tol2;    // tol^2 (same for all RHS)
+    int* active;     // 1 while iterating
+    int* iters;
+    int* status;
+};
+
+// Per-iteration view of the CG state for kernels that complete a reduction of
+// their producer themselves (every workgroup reduces the partial sums in one
+// fixed order, so all take identical decisions; one workgroup per RHS stores
+// the state).  rho and active have two slots that alternate with the
+// iteration's parity: *_prev is the previous iteration's, rho / act this one's,
+// so no kernel reads a slot that it writes.
+struct CgFuse {
+    const double* part;    // apply: previous step's partials [2][nsb][k] (r.z, r.r); null: none
+    int nsb;
+    const double* energy;  // step: element energies [n_e][k] of this iteration's apply
+    int64_t n_e;
+    const double* rho_prev;
+    const int* act_prev;
+    double* rho;
+    int* act;
+    double* beta;
+    double* rr;
+    int* iters;
+    int* status;
+    const double* bb;
+    const double* tol2;
+    double* pq;
+    double* alpha;
+};
+
 template <typename T>
 struct ApplyArgs {
     Geo g;
@@ -27,7 +66,13 @@ struct ApplyArgs {
     const T* dir_r = nullptr;
     const T* dir_pinv = nullptr;
     const double* dir_beta = nullptr;
+    // With DIR and fz.part set, beta is not read from dir_beta: every
+    // workgroup completes the previous step's r.z reduction itself (RED_RZ),
+    // and the workgroups of x = 0 store the new state.
+    CgFuse fz = {};
 };
+
+constexpr int kMaxRhs = 256;  // right-hand sides per call
 
 template <typename T>
 hipError_t launch_apply_tpt(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t st);
@@ -96,18 +141,6 @@ hipError_t launch_add_mixed(double* x, const float* d, int64_t n, hipStream_t st
 // scalars; reductions are two-stage and in a fixed order, so results do not
 // depend on scheduling.
 // ---------------------------------------------------------------------------
-struct CgState {
-    double* rho;     // r.z
-    double* pq;      // p.q
-    double* alpha;
-    double* beta;
-    double* rr;      // r.r
-    double* bb;      // b.b
-    double* tol2;    // tol^2 (same for all RHS)
-    int* active;     // 1 while iterating
-    int* iters;
-    int* status;
-};
 
 constexpr int kVecBlocks = 2048;  // vector-kernel blocks over all RHS
 
@@ -134,5 +167,14 @@ hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int 
 template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s,
                           double* partials, hipStream_t st);
+// The same step with p.q completed by every block from the element energies
+// f.energy (RED_PQ on slot f.rho / f.act; blocks x = 0 store pq, alpha and a
+// breakdown); partials [2][fused_step_blocks(k)][k] of r.z and r.r for the next
+// apply's fused completion.
+constexpr int kFusedStepThreads = 1024;
+int fused_step_blocks(int k);
+template <typename T>
+hipError_t launch_cg_step_fused(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, const CgFuse& f,
+                                double* partials, hipStream_t st);
 
 }  // namespace semcond

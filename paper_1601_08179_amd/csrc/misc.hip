@@ -6,6 +6,7 @@
 
 #include <algorithm>
 
+#include "cg_device.h"
 #include "device_common.h"
 #include "kernels.h"
 #include "tables.h"
@@ -785,6 +786,71 @@ template hipError_t launch_cg_step<double>(double*, double*, double*, double*, c
                                            double*, hipStream_t);
 template hipError_t launch_cg_step<float>(float*, float*, float*, float*, const float*, int64_t, int, CgState, double*,
                                           hipStream_t);
+
+int fused_step_blocks(int k) { return std::max(1, 256 / k); }
+
+// The CG step with p.q completed by every block from the element energies
+// (blocks of kFusedStepThreads threads, fused_step_blocks(k) per RHS: few
+// blocks, so that each apply workgroup's later reduction of their partials
+// stays small).
+template <typename T>
+__global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restrict__ x, T* __restrict__ r,
+                                                                     T* __restrict__ p, T* __restrict__ q,
+                                                                     const T* __restrict__ pinv, int64_t Ns, int k,
+                                                                     CgFuse f, double* __restrict__ partials) {
+    constexpr int NT = kFusedStepThreads;
+    __shared__ double s_red[2 * (NT / 64)];
+    const int rhs = blockIdx.y;
+    double pq[1];
+    block_sums<NT, 1>(f.energy + rhs, 0, f.n_e, k, s_red, pq);
+    bool act;
+    const T alpha = (T)cg_pq_complete(f, rhs, pq[0], blockIdx.x == 0 && threadIdx.x == 0, &act);
+    // a stopped RHS keeps x, r and p; its q and partial sums are not read again
+    if (!act) return;
+    const T beta = (T)f.beta[rhs];
+    const int64_t off = (int64_t)rhs * Ns, stride = (int64_t)gridDim.x * NT;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t n = (int64_t)blockIdx.x * NT + threadIdx.x; n < Ns; n += stride) {
+        const int64_t idx = off + n;
+        T rv = r[idx];
+        const T qv = q[idx];
+        const T pn = pinv[n];
+        q[idx] = (T)0;  // q is accumulated from zero by the next operator application
+        const T pv = fmadd(beta, p[idx], pn * rv);  // the direction the apply used
+        p[idx] = pv;
+        x[idx] += alpha * pv;
+        rv -= alpha * qv;
+        r[idx] = rv;
+        const T z = pn * rv;
+        acc[0] += (double)rv * (double)z;
+        acc[1] += (double)rv * (double)rv;
+    }
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) acc[qq] = wave_sum(acc[qq]);
+    __syncthreads();  // s_red is free
+    if ((threadIdx.x & 63) == 0) {
+        s_red[threadIdx.x >> 6] = acc[0];
+        s_red[NT / 64 + (threadIdx.x >> 6)] = acc[1];
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double sum = 0.0;
+        for (int w = 0; w < NT / 64; ++w) sum += s_red[threadIdx.x * (NT / 64) + w];
+        partials[((int64_t)threadIdx.x * gridDim.x + blockIdx.x) * k + rhs] = sum;
+    }
+}
+
+template <typename T>
+hipError_t launch_cg_step_fused(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, const CgFuse& f,
+                                double* partials, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_step_fused<T>, dim3(fused_step_blocks(k), k), dim3(kFusedStepThreads), 0, st, x, r, p, q,
+                       pinv, Ns, k, f, partials);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_step_fused<double>(double*, double*, double*, double*, const double*, int64_t, int,
+                                                 const CgFuse&, double*, hipStream_t);
+template hipError_t launch_cg_step_fused<float>(float*, float*, float*, float*, const float*, int64_t, int,
+                                                const CgFuse&, double*, hipStream_t);
 
 // out[c][r] = in[r][c] for an R x C row-major array, 32 x 32 tiles through LDS;
 // a one-dimensional grid of tiles (tile t: rows (t / tc) * 32, columns
