@@ -135,12 +135,39 @@ __device__ inline T group_sum(T x) {
     return x;
 }
 
-// Wave64 sum.
+// x plus the value that a row broadcast (CTRL 0x142: lane 15 of the row
+// before, 0x143: lane 31) moves into the rows of ROWS; other rows add 0.
+template <int CTRL, int ROWS>
+__device__ inline float dpp_row_add(float x) {
+    const int y = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROWS, 0xF, false);
+    return x + __builtin_bit_cast(float, y);
+}
+template <int CTRL, int ROWS>
+__device__ inline double dpp_row_add(double x) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, false);
+    return x + __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ inline float lane63(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+}
+__device__ inline double lane63(double x) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Wave64 sum in a fixed order, returned to every lane: each row of 16 lanes by
+// its in-row tree, then rows 1 and 3 add rows 0 and 2, rows 2 and 3 add row 1;
+// lane 63 then holds the total.  Every lane of the wave must be active.
 template <typename T>
 __device__ inline T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = group_sum<16>(v);
+    v = dpp_row_add<0x142, 0xA>(v);
+    v = dpp_row_add<0x143, 0xC>(v);
+    return lane63(v);
 }
 
 }  // namespace semcond
