@@ -10,22 +10,23 @@
 
 namespace semcond {
 
-template <typename T, int NI, bool DIR>
+// FZ (with DIR): the previous CG step's r.z is completed in the kernel
+// (A.fz), a separate instantiation so that plain launches keep their registers.
+template <typename T, int NI, bool DIR, bool FZ>
 __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A, int64_t n_elem) {
     constexpr int NT = apply_threads(NI);
     constexpr bool CUBE = NI <= 15;
     const double* beta = A.dir_beta;
-    if constexpr (DIR) {
+    if constexpr (DIR && FZ && !CUBE) {
         // CG direction with the previous step's r.z completed here: every
-        // workgroup reduces the step's partial sums for its right-hand sides
-        // (the cube form: RHS y; the plane form: all) in one fixed order
+        // workgroup reduces the step's partial sums for all right-hand sides
+        // in one fixed order (the cube form does this inside its gather)
         __shared__ double s_beta[kMaxRhs];
         __shared__ double s_red[2 * (NT / 64)];
-        if (A.fz.part) {
-            const int r0 = CUBE ? (int)blockIdx.y : 0, nr = CUBE ? 1 : A.k;
+        {
             const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
             bool any = false;
-            for (int r = r0; r < r0 + nr; ++r) {
+            for (int r = 0; r < A.k; ++r) {
                 double t[2];
                 block_sums<NT, 2>(A.fz.part + r, (int64_t)A.fz.nsb * A.k, A.fz.nsb, A.k, s_red, t);
                 bool still;
@@ -44,8 +45,9 @@ __global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A,
         // workgroup (x, y): elements e_begin + x*E .. + E - 1, right-hand side y
         constexpr int E = apply_pack(NI);
         __shared__ ApplySmem<T, NI> sm[E];
-        apply_elements_cube<T, NI, DIR, true, E>(A, A.e_begin + (int64_t)blockIdx.x * E, 1, 1, A.e_begin + n_elem,
-                                                 blockIdx.y, 1, sm, nullptr, threadIdx.x, beta);
+        apply_elements_cube<T, NI, DIR, true, E, FZ>(A, A.e_begin + (int64_t)blockIdx.x * E, 1, 1,
+                                                     A.e_begin + n_elem, blockIdx.y, 1, sm, nullptr, threadIdx.x,
+                                                     beta);
     } else {
         __shared__ ApplySmem<T, NI> sm;
         apply_element<T, NI, DIR>(A, (int64_t)blockIdx.x + A.e_begin, sm, nullptr, threadIdx.x, true, beta);
@@ -69,11 +71,14 @@ hipError_t launch_apply_tpt(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t s
     if (n_elem <= 0) return hipSuccess;
 #define CASE(N)                                                                                                    \
     case N:                                                                                                        \
-        if (a.dir_r)                                                                                               \
-            hipLaunchKernelGGL((k_apply_tpt<T, N, true>), apply_grid<N>(n_elem, a.k), dim3(apply_threads(N)), \
+        if (a.dir_r && a.fz.part)                                                                                  \
+            hipLaunchKernelGGL((k_apply_tpt<T, N, true, true>), apply_grid<N>(n_elem, a.k), dim3(apply_threads(N)), \
                                0, st, a, n_elem);                                                                  \
+        else if (a.dir_r)                                                                                          \
+            hipLaunchKernelGGL((k_apply_tpt<T, N, true, false>), apply_grid<N>(n_elem, a.k),                      \
+                               dim3(apply_threads(N)), 0, st, a, n_elem);                                          \
         else                                                                                                       \
-            hipLaunchKernelGGL((k_apply_tpt<T, N, false>), apply_grid<N>(n_elem, a.k),                  \
+            hipLaunchKernelGGL((k_apply_tpt<T, N, false, false>), apply_grid<N>(n_elem, a.k),                     \
                                dim3(apply_threads(N)), 0, st, a, n_elem);                                          \
         break;
     switch (NI) {

@@ -32,6 +32,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "cg_device.h"
 #include "device_common.h"
 #include "kernels.h"
 
@@ -508,7 +509,7 @@ __device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live,
 // lets them live only where they are used.)
 // With NE > 1 (ONE only) the workgroup holds NE groups of NT / NE lanes; group g
 // computes element e0 + g with its own LDS block smv[g].
-template <typename T, int NI, bool DIR, bool ONE, int NE = 1>
+template <typename T, int NI, bool DIR, bool ONE, int NE = 1, bool FZ = false>
 __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t stride, int64_t count, int64_t n_end,
                                     uint32_t r0, uint32_t nr, ApplySmem<T, NI>* smv, double* en_acc, int tid,
                                     const double* beta) {
@@ -557,10 +558,26 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
         ctB[t] = A.tab.b[t];
     }  // read after the first item's gather barrier
 
+    // fused completion of the previous CG step's r.z (single-item form): the
+    // workgroup's threads reduce the step's partial sums while the gather's
+    // loads are in flight
+    constexpr int WG = apply_threads(NI);
+    __shared__ double s_fz[FZ ? 2 * (WG / 64) : 1];
+
     auto item = [&](const int64_t e, const bool live, const uint32_t r) __attribute__((always_inline)) {
-        const T bt = DIR ? (T)beta[r] : (T)0;
         Gathered<T, DIR> G;
         gather_issue<T, NI, DIR>(A, e, live, r, t, G);
+        T bt = DIR ? (T)beta[r] : (T)0;
+        if constexpr (DIR && ONE && FZ) {
+            {
+                double sums[2];
+                block_sums<WG, 2, (NI <= 5 ? 2 : 4)>(A.fz.part + r, (int64_t)A.fz.nsb * A.k, A.fz.nsb, A.k, s_fz, sums);
+                bool still;
+                bt = (T)cg_rz_complete(A.fz, (int)r, sums[0], sums[1], blockIdx.x == 0 && tid == 0, &still);
+                // a stopped RHS is not applied (the step ignores its energies)
+                if (!still) return;
+            }
+        }
         // ---- commit the gathered values (R^T) to LDS
         {
             auto val = [&](T u, T rr, T pp) -> T {

@@ -13,13 +13,12 @@ namespace semcond {
 
 // Sums of NQ strided arrays, out[q] = sum of v[q * qstride + i * stride] for i
 // in [0, n), over the NT threads of a workgroup in a fixed order (thread t:
-// i = t, t + NT, ... in sequence, U loads in flight; then each wave by its
+// i = t, t + NT, ... in sequence, U loads per quantity in flight; then each wave by its
 // shuffle tree, waves in index order).  Every thread receives the sums;
 // s_red holds NQ * NT / 64 doubles.
-template <int NT, int NQ>
+template <int NT, int NQ, int U = 8>
 __device__ inline void block_sums(const double* v, int64_t qstride, int64_t n, int64_t stride, double* s_red,
                                   double (&out)[NQ]) {
-    constexpr int U = 8;
     const int t = threadIdx.x;
     double acc[NQ];
 #pragma unroll
