@@ -324,6 +324,216 @@ __global__ __launch_bounds__(256) void k_condense_rhs(Geo g, DevTab<double> tab,
 #undef C
 }
 
+// ---------------------------------------------------------------------------
+// The same two element passes for n_I <= 15, compiled per n_I: the element
+// cube and the 1D tables in LDS (the tables read at wave-uniform indices, as
+// broadcasts), lines transformed with their values in registers, and D^-1
+// applied once per interior node so that the face sums are plain products.
+// One workgroup of kRhsThreads threads per element.
+// ---------------------------------------------------------------------------
+
+constexpr int kRhsThreads = 256;
+
+template <int NI>
+struct RhsSmem {
+    static constexpr int n = NI + 2;
+    double C[n * n * n];  // C(kk, jj, ii) at (kk n + jj) n + ii
+    double A[NI * NI];    // S^T (condensation) or S (recovery), row-major
+    double w[n];
+    double a[NI], b[NI], lam[NI];
+};
+
+template <int NI>
+__device__ void rhs_tables(RhsSmem<NI>& sm, const DevTab<double>& tab, const double* __restrict__ A) {
+    for (int t = threadIdx.x; t < NI * NI; t += blockDim.x) sm.A[t] = A[t];
+    if (threadIdx.x < NI + 2) sm.w[threadIdx.x] = tab.w[threadIdx.x];
+    if (threadIdx.x < NI) {
+        sm.a[threadIdx.x] = tab.a[threadIdx.x];
+        sm.b[threadIdx.x] = tab.b[threadIdx.x];
+        sm.lam[threadIdx.x] = tab.lam[threadIdx.x];
+    }
+}
+
+// x <- A x on the interior part (entries 1 .. n_I) of every line along AXIS
+// (0: ii, 1: jj, 2: kk) whose two fixed indices lie in [lo, n - lo).
+template <int NI, int AXIS>
+__device__ void rhs_lines(double* C, const double* A, int lo) {
+    constexpr int n = NI + 2;
+    constexpr int st = AXIS == 0 ? 1 : (AXIS == 1 ? n : n * n);
+    const int m = n - 2 * lo;
+    for (int l = threadIdx.x; l < m * m; l += blockDim.x) {
+        const int u = l / m + lo, v = l - (l / m) * m + lo;  // (slow, fast) fixed indices
+        const int base = AXIS == 0 ? (u * n + v) * n : (AXIS == 1 ? u * n * n + v : u * n + v);
+        double x[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) x[i] = C[base + (1 + i) * st];
+#pragma unroll
+        for (int o = 0; o < NI; ++o) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < NI; ++i) acc += A[o * NI + i] * x[i];
+            C[base + (1 + o) * st] = acc;
+        }
+    }
+}
+
+// C(kk,jj,ii) = J w_ii w_jj w_kk f(node) of RHS r, then (S1 (x) S1 (x) S1)-type
+// transform by sm.A along the three axes (all lines).
+template <int NI>
+__device__ void rhs_cube(RhsSmem<NI>& sm, const Geo& g, const double* __restrict__ f, int64_t N, int r, int e1,
+                         int e2, int e3, double J) {
+    constexpr int n = NI + 2, p = NI + 1;
+    const Layout& L = g.L;
+    const int64_t N1 = (int64_t)L.n1 * p + 1, N2 = (int64_t)L.n2 * p + 1;
+    for (int idx = threadIdx.x; idx < n * n * n; idx += blockDim.x) {
+        const int ii = idx % n, jj = (idx / n) % n, kk = idx / (n * n);
+        const int64_t node = ((int64_t)e1 * p + ii) + N1 * (((int64_t)e2 * p + jj) + N2 * ((int64_t)e3 * p + kk));
+        sm.C[idx] = J * sm.w[ii] * sm.w[jj] * sm.w[kk] * f[(int64_t)r * N + node];
+    }
+    __syncthreads();
+    rhs_lines<NI, 0>(sm.C, sm.A, 0);
+    __syncthreads();
+    rhs_lines<NI, 1>(sm.C, sm.A, 0);
+    __syncthreads();
+    rhs_lines<NI, 2>(sm.C, sm.A, 0);
+    __syncthreads();
+}
+
+template <int NI>
+__global__ __launch_bounds__(kRhsThreads) void k_condense_rhs_t(Geo g, DevTab<double> tab,
+                                                                const double* __restrict__ f, int64_t N,
+                                                                double* __restrict__ fhat, int k) {
+    constexpr int n = NI + 2, p = NI + 1, NI2 = NI * NI;
+    constexpr int nslot = 6 * NI2 + 12 * NI + 8;
+    __shared__ RhsSmem<NI> sm;
+    const Layout& L = g.L;
+    const int64_t e = blockIdx.x;
+    int e1, e2, e3;
+    elem_index(L, e, &e1, &e2, &e3);
+    double d[4];
+    elem_metric(g, e, e1, e2, e3, d);
+    const double J = elem_jacobian(g, e1, e2, e3);
+    rhs_tables<NI>(sm, tab, tab.St);
+#define C(kk, jj, ii) sm.C[((kk) * n + (jj)) * n + (ii)]
+    for (int r = 0; r < k; ++r) {
+        __syncthreads();  // tables stored / the previous RHS's cube read
+        rhs_cube<NI>(sm, g, f, N, r, e1, e2, e3, J);
+        // interior: V = D^-1 F~_I
+        for (int idx = threadIdx.x; idx < NI2 * NI; idx += blockDim.x) {
+            const int i = idx % NI, j = (idx / NI) % NI, kk = idx / NI2;
+            C(1 + kk, 1 + j, 1 + i) /= d[0] + d[1] * sm.lam[i] + d[2] * sm.lam[j] + d[3] * sm.lam[kk];
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
+            int ent, loc;
+            double val;
+            if (s < 6 * NI2) {
+                const int fc = s / NI2;
+                loc = s - fc * NI2;
+                ent = fc;
+                const int s1 = loc / NI, s2 = loc - (loc / NI) * NI;
+                const double* c = (fc & 1) ? sm.b : sm.a;
+                const int side = (fc & 1) ? p : 0;
+                double acc = 0.0;
+                if (fc < 2) {  // (k, j), sum over i
+#pragma unroll
+                    for (int m = 0; m < NI; ++m) acc += c[m] * C(1 + s1, 1 + s2, 1 + m);
+                    val = C(1 + s1, 1 + s2, side) - d[1] * acc;
+                } else if (fc < 4) {  // (k, i), sum over j
+#pragma unroll
+                    for (int m = 0; m < NI; ++m) acc += c[m] * C(1 + s1, 1 + m, 1 + s2);
+                    val = C(1 + s1, side, 1 + s2) - d[2] * acc;
+                } else {  // (j, i), sum over k
+#pragma unroll
+                    for (int m = 0; m < NI; ++m) acc += c[m] * C(1 + m, 1 + s1, 1 + s2);
+                    val = C(side, 1 + s1, 1 + s2) - d[3] * acc;
+                }
+            } else if (s < 6 * NI2 + 12 * NI) {
+                const int q = (s - 6 * NI2) / NI;
+                loc = s - 6 * NI2 - q * NI;
+                ent = 6 + q;
+                if (q < 4) {
+                    const int jb = q & 1, kb = q >> 1;
+                    val = C(kb * p, jb * p, 1 + loc);
+                } else if (q < 8) {
+                    const int ib = (q - 4) & 1, kb = (q - 4) >> 1;
+                    val = C(kb * p, 1 + loc, ib * p);
+                } else {
+                    const int ib = (q - 8) & 1, jb = (q - 8) >> 1;
+                    val = C(1 + loc, jb * p, ib * p);
+                }
+            } else {
+                const int q = s - 6 * NI2 - 12 * NI;
+                ent = 18 + q;
+                loc = 0;
+                val = C((q >> 2) * p, ((q >> 1) & 1) * p, (q & 1) * p);
+            }
+            int64_t base;
+            bool con;
+            element_entity(L, e1, e2, e3, ent, &base, &con);
+            if (!con) atomic_add(&fhat[(base + loc) * k + r], val);
+        }
+    }
+#undef C
+}
+
+template <int NI>
+__global__ __launch_bounds__(kRhsThreads) void k_recover_interior_t(Geo g, DevTab<double> tab,
+                                                                    const double* __restrict__ f, int64_t N,
+                                                                    const double* __restrict__ xs,
+                                                                    double* __restrict__ u, int k, int keep_con) {
+    constexpr int n = NI + 2, p = NI + 1, NI2 = NI * NI;
+    __shared__ RhsSmem<NI> sm;
+    __shared__ int64_t fb[6];
+    __shared__ int fcon[6];
+    const Layout& L = g.L;
+    const int64_t e = blockIdx.x;
+    const int64_t N1 = (int64_t)L.n1 * p + 1, N2 = (int64_t)L.n2 * p + 1;
+    int e1, e2, e3;
+    elem_index(L, e, &e1, &e2, &e3);
+    double d[4];
+    elem_metric(g, e, e1, e2, e3, d);
+    const double J = elem_jacobian(g, e1, e2, e3);
+    if (threadIdx.x < 6) {
+        bool c;
+        element_entity(L, e1, e2, e3, threadIdx.x, &fb[threadIdx.x], &c);
+        fcon[threadIdx.x] = c && !keep_con ? 1 : 0;
+    }
+    // forward transform by S^T first; S for the back transform afterwards
+#define C(kk, jj, ii) sm.C[((kk) * n + (jj)) * n + (ii)]
+#define UF(face, s1, s2) (fcon[face] ? 0.0 : xs[(fb[face] + (int64_t)(s1) * NI + (s2)) * k + r])
+    for (int r = 0; r < k; ++r) {
+        __syncthreads();  // the previous RHS's back transform and output done
+        rhs_tables<NI>(sm, tab, tab.St);
+        __syncthreads();
+        rhs_cube<NI>(sm, g, f, N, r, e1, e2, e3, J);
+        for (int idx = threadIdx.x; idx < NI2 * NI; idx += blockDim.x) {
+            const int i = idx % NI, j = (idx / NI) % NI, kk = idx / NI2;
+            const double uc = d[1] * (sm.a[i] * UF(0, kk, j) + sm.b[i] * UF(1, kk, j)) +
+                              d[2] * (sm.a[j] * UF(2, kk, i) + sm.b[j] * UF(3, kk, i)) +
+                              d[3] * (sm.a[kk] * UF(4, j, i) + sm.b[kk] * UF(5, j, i));
+            const double D = d[0] + d[1] * sm.lam[i] + d[2] * sm.lam[j] + d[3] * sm.lam[kk];
+            C(1 + kk, 1 + j, 1 + i) = (C(1 + kk, 1 + j, 1 + i) - uc) / D;
+        }
+        for (int t = threadIdx.x; t < NI * NI; t += blockDim.x) sm.A[t] = tab.S[t];  // read only after the barrier
+        __syncthreads();
+        rhs_lines<NI, 0>(sm.C, sm.A, 1);
+        __syncthreads();
+        rhs_lines<NI, 1>(sm.C, sm.A, 1);
+        __syncthreads();
+        rhs_lines<NI, 2>(sm.C, sm.A, 1);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < NI2 * NI; idx += blockDim.x) {
+            const int i = idx % NI, j = (idx / NI) % NI, kk = idx / NI2;
+            const int64_t node =
+                ((int64_t)e1 * p + 1 + i) + N1 * (((int64_t)e2 * p + 1 + j) + N2 * ((int64_t)e3 * p + 1 + kk));
+            u[(int64_t)r * N + node] = C(1 + kk, 1 + j, 1 + i);
+        }
+    }
+#undef UF
+#undef C
+}
+
 int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch) {
     const size_t bytes = (size_t)(p + 1) * (p + 1) * (p + 1) * sizeof(double);
     *needs_scratch = bytes > 64 * 1024;
@@ -333,8 +543,25 @@ int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch) {
     return (int)grid;
 }
 
+#define RHS_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+
 hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
                                double* fhat, int k, double* scratch, int grid, hipStream_t st) {
+    if (g.L.NI <= 15) {
+        const int64_t ne = (int64_t)g.L.n1 * g.L.n2 * g.L.n3;
+        if (ne <= 0) return hipSuccess;
+        if (ne > INT32_MAX) return hipErrorInvalidValue;
+        switch (g.L.NI) {
+#define X(NI)                                                                                                    \
+    case NI:                                                                                                     \
+        hipLaunchKernelGGL(k_condense_rhs_t<NI>, dim3((unsigned)ne), dim3(kRhsThreads), 0, st, g, tab, f, N, fhat, \
+                           k);                                                                                   \
+        break;
+            RHS_CASES(X)
+#undef X
+        }
+        return hipGetLastError();
+    }
     const int n = g.L.p + 1;
     const size_t shm = scratch ? 0 : (size_t)n * n * n * sizeof(double);
     hipLaunchKernelGGL(k_condense_rhs, dim3(grid), dim3(256), shm, st, g, tab, f, N, fhat, k, scratch);
@@ -405,6 +632,21 @@ __global__ __launch_bounds__(256) void k_recover_interior(Geo g, DevTab<double> 
 hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
                                    const double* xskel, double* u, int k, double* scratch, int grid,
                                    int keep_con, hipStream_t st) {
+    if (g.L.NI <= 15) {
+        const int64_t ne = (int64_t)g.L.n1 * g.L.n2 * g.L.n3;
+        if (ne <= 0) return hipSuccess;
+        if (ne > INT32_MAX) return hipErrorInvalidValue;
+        switch (g.L.NI) {
+#define X(NI)                                                                                                  \
+    case NI:                                                                                                   \
+        hipLaunchKernelGGL(k_recover_interior_t<NI>, dim3((unsigned)ne), dim3(kRhsThreads), 0, st, g, tab, f, N, \
+                           xskel, u, k, keep_con);                                                              \
+        break;
+            RHS_CASES(X)
+#undef X
+        }
+        return hipGetLastError();
+    }
     const int n = g.L.p + 1;
     const size_t shm = scratch ? 0 : (size_t)n * n * n * sizeof(double);
     hipLaunchKernelGGL(k_recover_interior, dim3(grid), dim3(256), shm, st, g, tab, f, N, xskel, u, k, scratch,
