@@ -269,8 +269,8 @@ def suite(args):
 # HBM traffic of the dominant kernel from rocprofv3 counters
 # ---------------------------------------------------------------------------
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_config2_p8.md")
-DOMINANT = "k_apply_tpt<double, 7, true>"
-KERNEL_SOURCES = ["apply.hip", "apply_element.h", "device_common.h", "kernels.h", "layout.h"]
+DOMINANT = "k_apply_tpt<double, 7, true, true>"
+KERNEL_SOURCES = ["apply.hip", "apply_element.h", "cg_device.h", "device_common.h", "kernels.h", "layout.h"]
 COPY_BYTES = 256 << 20
 
 
@@ -332,9 +332,13 @@ def pmc_summary(fetch_csv, write_csv, commands):
         return sum(big) / len(big)
 
     def dominant(rows):
+        # full applies only: launches queued after convergence exit at once and
+        # read a few KiB (below a tenth of the median)
         for name, lst in rows.items():
             if name.startswith("void semcond::" + DOMINANT):
-                return sum(v for _, v in lst) / len(lst), len(lst)
+                vals = sorted(v for _, v in lst)
+                full = [v for v in vals if v >= 0.1 * vals[len(vals) // 2]]
+                return sum(full) / len(full), len(full)
         raise KeyError(DOMINANT)
 
     ff = COPY_BYTES / (copy_value(fe) * 1024.0)
@@ -355,8 +359,8 @@ def pmc_summary(fetch_csv, write_csv, commands):
         "| calibration: FETCH_SIZE of a streaming kernel reading and writing %d MiB | %.0f KiB (factor %.4f) |" % (
             COPY_BYTES >> 20, copy_value(fe), ff),
         "| calibration: WRITE_SIZE of the same kernel | %.0f KiB (factor %.4f) |" % (copy_value(wr), fw),
-        "| dominant kernel FETCH_SIZE per dispatch (%d dispatches) | %.1f KiB |" % (nf, fk),
-        "| dominant kernel WRITE_SIZE per dispatch (%d dispatches) | %.1f KiB |" % (nw, wk),
+        "| dominant kernel FETCH_SIZE per full dispatch (%d dispatches) | %.1f KiB |" % (nf, fk),
+        "| dominant kernel WRITE_SIZE per full dispatch (%d dispatches) | %.1f KiB |" % (nw, wk),
         "| scaled HBM read bytes per launch | %.0f |" % fetch_b,
         "| scaled HBM write bytes per launch | %.0f |" % write_b,
         "",
@@ -493,7 +497,7 @@ def main():
         dom = {"kernel": "k_pcg_persistent<double,7,%d>" % tS, "ms": cg_ms, "launches": cg_launches,
                "bytes": 13 * 8 * Ns * cg_iters, "traffic": None}
     else:
-        dom = {"kernel": "k_apply_tpt<double,7,true>", "ms": ap_ms, "launches": ap_launches,
+        dom = {"kernel": "k_apply_tpt<double,7,true,true>", "ms": ap_ms, "launches": ap_launches,
                "bytes": 4 * 8 * Ns * ap_launches, "traffic": stored_traffic()}
     dom_achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
     apply_bytes = 2 * 8 * Ns
@@ -529,7 +533,7 @@ def main():
                      "bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
                      "kernel_us_per_launch": dom["ms"] * 1e3 / max(dom["launches"], 1)},
         "apply_roofline": {"bound": "hbm", "achieved": apply_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": apply_achieved / HBM_PEAK_GBS, "kernel": "k_apply_tpt<double,7,false>",
+                           "frac": apply_achieved / HBM_PEAK_GBS, "kernel": "k_apply_tpt<double,7,false,false>",
                            "kernel_us": kern_s * 1e6, "gdof_s": N / kern_s / 1e9,
                            "bytes_per_launch": apply_bytes},
     }

@@ -71,6 +71,8 @@ struct semcond_ctx {
     int* h_active = nullptr;  // pinned host copy of CG activity flags
     int h_active_cap = 0;
     hipEvent_t poll_ev[2] = {nullptr, nullptr};  // lagged convergence polls of the fused CG loop
+    int* h_flags = nullptr;                       // pinned, written by the fused CG kernels: [kMaxRhs]
+    int cg_epoch = 0;                             // numbers the fused CG loops (tags h_flags)
     // persistent CG launch configuration per (k, dtype): (S, G)
     std::map<std::pair<int, int>, std::pair<int, int>> tuned;
     // tracing: event pairs around kernel launches, with the kernel id
@@ -404,6 +406,8 @@ CgFuse fuse_view(const CgWork& w, int k, int ph, int64_t n_e) {
     f.tol2 = w.s.tol2;
     f.pq = w.s.pq;
     f.alpha = w.s.alpha;
+    f.host_act = nullptr;
+    f.epoch2 = 0;
     return f;
 }
 
@@ -431,9 +435,16 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     // them (two launches per iteration instead of four); the redundant reads
     // of the partial sums grow with n_e k.
     const bool fused = c->n_e * (int64_t)k <= kFusedMaxItems;
-    if (fused)
+    if (fused) {
         for (hipEvent_t& e : c->poll_ev)
             if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        if (!c->h_flags && hipHostMalloc((void**)&c->h_flags, kMaxRhs * sizeof(int), hipHostMallocCoherent) !=
+                               hipSuccess)
+            return fail(c, SEMCOND_ENOMEM, "pinned host allocation failed");
+        // a flag counts as "stopped" only when a kernel of this loop wrote it
+        c->cg_epoch = (c->cg_epoch + 1) & 0x3FFFFFFF;
+    }
+    const int epoch2 = 2 * c->cg_epoch;
     auto none_active = [&](const int* h) {
         for (int i = 0; i < k; ++i)
             if (h[i]) return false;
@@ -441,18 +452,21 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     };
     int n_it = 0, pending = -1;
     for (int it = 0; it < max_iter; ++it) {
-        if (it % check_every == 0) {
-            if (fused && it > 0) {
-                // Lagged poll: copy the latest flags with an event and look at
-                // the copy made one check interval earlier, so the queue never
-                // drains; iterations queued after convergence exit at once.
+        if (it % check_every == 0 && !(fused && it == 0)) {
+            // (the fused loop needs no check before its first iteration: a RHS
+            // that is converged from the start exits every kernel at once)
+            if (fused) {
+                // Lagged poll: the kernels write the flags to pinned host memory
+                // as they decide them; the host waits for the event recorded one
+                // check interval earlier (the queue never drains) and reads them.
+                // Iterations queued after convergence exit at once.
                 const int b = (it / check_every) & 1;
-                const int* act = ((it - 1) & 1) ? w.act1 : w.s.active;
-                HIPCHK(c, hipMemcpyAsync(c->h_active + b * k, act, k * sizeof(int), hipMemcpyDeviceToHost, st));
                 HIPCHK(c, hipEventRecord(c->poll_ev[b], st));
                 if (pending >= 0) {
                     HIPCHK(c, hipEventSynchronize(c->poll_ev[pending]));
-                    if (none_active(c->h_active + pending * k)) break;
+                    bool stopped = true;
+                    for (int i = 0; i < k; ++i) stopped &= __atomic_load_n(c->h_flags + i, __ATOMIC_ACQUIRE) == epoch2;
+                    if (stopped) break;
                 }
                 pending = b;
             } else {
@@ -465,7 +479,9 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
         // the direction p = beta p + z at its gather; the step stores it.
         if (fused) {
             // slot it & 1 is this iteration's rho / active, the other the previous one's
-            const CgFuse f = fuse_view(w, k, it & 1, c->n_e);
+            CgFuse f = fuse_view(w, k, it & 1, c->n_e);
+            f.host_act = c->h_flags;
+            f.epoch2 = epoch2;
             int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta, 0,
                                           it > 0 ? &f : nullptr);
             if (rc) return rc;
@@ -824,6 +840,7 @@ int semcond_destroy(semcond_ctx* c) {
     hipFree(c->ws_persist.ptr);
     hipFree(c->ws_lift.ptr);
     if (c->h_active) hipHostFree(c->h_active);
+    if (c->h_flags) hipHostFree(c->h_flags);
     for (hipEvent_t e : c->poll_ev)
         if (e) hipEventDestroy(e);
     for (hipEvent_t e : c->ev) hipEventDestroy(e);

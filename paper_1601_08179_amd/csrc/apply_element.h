@@ -565,6 +565,12 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
     __shared__ double s_fz[FZ ? 2 * (WG / 64) : 1];
 
     auto item = [&](const int64_t e, const bool live, const uint32_t r) __attribute__((always_inline)) {
+        if constexpr (DIR && ONE && FZ) {
+            if (!A.fz.act_prev[r]) {  // stopped before this iteration: nothing to gather
+                if (blockIdx.x == 0 && tid == 0) cg_carry_stopped(A.fz, (int)r);
+                return;
+            }
+        }
         Gathered<T, DIR> G;
         gather_issue<T, NI, DIR>(A, e, live, r, t, G);
         T bt = DIR ? (T)beta[r] : (T)0;

@@ -90,8 +90,18 @@ __device__ inline double cg_rz_complete(const CgFuse& f, int r, double rz, doubl
         f.rho[r] = rho_new;
         f.act[r] = act_new;
         f.beta[r] = beta;
+        if (f.host_act) f.host_act[r] = f.epoch2 + act_new;
     }
     return beta;
+}
+
+// The state of a RHS that had stopped before this iteration, carried into this
+// iteration's slot (what cg_rz_complete stores for it).
+__device__ inline void cg_carry_stopped(const CgFuse& f, int r) {
+    f.rho[r] = f.rho_prev[r];
+    f.act[r] = 0;
+    f.beta[r] = 0.0;
+    if (f.host_act) f.host_act[r] = f.epoch2;
 }
 
 // Completion of p.q for RHS r (RED_PQ) on this iteration's slot: alpha =
@@ -117,6 +127,7 @@ __device__ inline double cg_pq_complete(const CgFuse& f, int r, double pq, bool 
         if (status) {
             f.status[r] = status;
             f.act[r] = 0;
+            if (f.host_act) f.host_act[r] = f.epoch2;
         }
     }
     return alpha;

@@ -45,6 +45,8 @@ struct CgFuse {
     const double* tol2;
     double* pq;
     double* alpha;
+    int* host_act;  // nullable: pinned host copy of act as epoch2 + act, written with it
+    int epoch2;     // twice the number of the solve call (flags of earlier calls never match)
 };
 
 template <typename T>

@@ -1043,6 +1043,7 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
     constexpr int NT = kFusedStepThreads;
     __shared__ double s_red[2 * (NT / 64)];
     const int rhs = blockIdx.y;
+    if (!f.act[rhs]) return;  // stopped (its state is already carried by the apply)
     double pq[1];
     block_sums<NT, 1>(f.energy + rhs, 0, f.n_e, k, s_red, pq);
     bool act;
