@@ -497,8 +497,11 @@ def main():
         dom = {"kernel": "k_pcg_persistent<double,7,%d>" % tS, "ms": cg_ms, "launches": cg_launches,
                "bytes": 13 * 8 * Ns * cg_iters, "traffic": None}
     else:
-        dom = {"kernel": "k_apply_tpt<double,7,true,true>", "ms": ap_ms, "launches": ap_launches,
-               "bytes": 4 * 8 * Ns * ap_launches, "traffic": stored_traffic()}
+        # one full apply per CG iteration; the launches queued after convergence
+        # leave at once, their (small) time stays in the total
+        full = int(round(it_per_solve * side_steps))
+        dom = {"kernel": "k_apply_tpt<double,7,true,true>", "ms": ap_ms, "launches": full,
+               "bytes": 4 * 8 * Ns * full, "traffic": stored_traffic(), "early_exit_launches": ap_launches - full}
     dom_achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
     apply_bytes = 2 * 8 * Ns
     apply_achieved = apply_bytes / kern_s / 1e9
@@ -531,7 +534,8 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": dom["kernel"], "launches": dom["launches"],
                      "bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
-                     "kernel_us_per_launch": dom["ms"] * 1e3 / max(dom["launches"], 1)},
+                     "kernel_us_per_launch": dom["ms"] * 1e3 / max(dom["launches"], 1),
+                     "early_exit_launches": dom.get("early_exit_launches", 0)},
         "apply_roofline": {"bound": "hbm", "achieved": apply_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": apply_achieved / HBM_PEAK_GBS, "kernel": "k_apply_tpt<double,7,false,false>",
                            "kernel_us": kern_s * 1e6, "gdof_s": N / kern_s / 1e9,
