@@ -138,10 +138,10 @@ def suite(args):
         u = torch.zeros_like(ft)
         res = {"case": "k=16 RHS, 24^3 elements, p=12", "n_e": ctx.n_e, "N": ctx.N, "N_s": ctx.N_s, "k": k}
         for name, kw in [("f64_stepwise", dict(persistent=False)), ("f64_persistent", dict(persistent=True)),
-                         ("mixed_stepwise", dict(precision=semcond.PREC_MIXED_IR, inner_tol=1e-4,
-                                                 persistent=False)),
-                         ("mixed_persistent", dict(precision=semcond.PREC_MIXED_IR, inner_tol=1e-4,
-                                                   persistent=True))]:
+                         ("mixed_stepwise", dict(precision=semcond.PREC_MIXED_IR, persistent=False)),
+                         ("mixed_persistent", dict(precision=semcond.PREC_MIXED_IR, persistent=True)),
+                         ("mixed_restart_stepwise", dict(precision=semcond.PREC_MIXED_IR, inner_tol=1e-4,
+                                                         ir_restart=True, persistent=False))]:
             ctx.solve(ft, out=u, tol=1e-10, **kw)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -151,6 +151,7 @@ def suite(args):
             res[name] = {"ms_per_rhs": dt * 1e3 / k, "iters_max": max(i["iters"] for i in info),
                          "outer_max": max(i["outer"] for i in info),
                          "rel_res_max": max(i["rel_res"] for i in info)}
+        res["mixed_speedup_vs_f64"] = res["f64_stepwise"]["ms_per_rhs"] / res["mixed_stepwise"]["ms_per_rhs"]
         for dt_name, dt_t in (("f64", torch.float64), ("f32", torch.float32)):
             S, G = ctx.autotune(k=k, dtype=dt_t)
             res["tuned_" + dt_name] = "stepwise" if S == 0 else "persistent S=%d G=%d" % (S, G)

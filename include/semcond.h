@@ -113,7 +113,8 @@ typedef struct {
     int recover_interior;   /* 1: also write interior nodes of u_nodal (Alg. 4), def. 1   */
     const void* x0;         /* optional initial guess, TRANSFORMED skeleton [N_s][k] FP64 */
     void* skel_out;         /* optional out: TRANSFORMED skeleton solution [N_s][k] FP64  */
-    double inner_tol;       /* MIXED_IR: relative tolerance of each FP32 inner solve      */
+    double inner_tol;       /* MIXED_IR: relative tolerance of each FP32 inner solve,     */
+                            /*   default 3e-3 (see ir_restart)                            */
     int max_outer;          /* MIXED_IR: refinement steps, default 30                     */
     int rhs_dual;           /* 0: f are nodal values, F = M_G f (default); 1: f is the   */
                             /* assembled discrete right-hand side itself (R F_L), as in  */
@@ -133,6 +134,13 @@ typedef struct {
                             /* to the right-hand side (lifting; Sec. 8's solver test has */
                             /* inhomogeneous Dirichlet conditions).  x0 holds unknowns   */
                             /* only; skel_out returns the full skeleton values           */
+    int ir_restart;         /* MIXED_IR: 0 (default): the FP32 CG keeps its search        */
+                            /*   direction across refinement steps and only its residual */
+                            /*   is replaced by the FP64 one (a reliable update), unless */
+                            /*   a step failed to halve the worst residual; 1: every     */
+                            /*   inner solve restarts from p = 0.  Either way a step's   */
+                            /*   inner tolerance is inner_tol, or looser when a smaller  */
+                            /*   reduction (with a factor 4 margin) reaches tol          */
 } semcond_solve_opts;
 
 #define SEMCOND_CG_STEPWISE   0

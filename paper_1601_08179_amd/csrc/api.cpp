@@ -237,7 +237,7 @@ enum VecLayout { NODE_MAJOR = 0, RHS_MAJOR = 1 };
 template <typename T>
 int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, double* energy, hipStream_t st,
                       bool v_is_zero = false, const T* dir_r = nullptr, const double* dir_beta = nullptr,
-                      int read_con = 0, const CgFuse* fz = nullptr) {
+                      int read_con = 0, const CgFuse* fz = nullptr, const int* act = nullptr) {
     if (!v_is_zero) HIPCHK(c, launch_fill<T>(v, c->N_s * k, (T)0, st));
     ApplyArgs<T> a = apply_args<T>(c);
     a.u = u;
@@ -254,6 +254,7 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, do
         a.dir_beta = dir_beta;
         if (fz) a.fz = *fz;
     }
+    a.act = act;
     if (c->prof) {
         int rc = profile_begin(c, SEMCOND_KERNEL_APPLY, st);
         if (rc) return rc;
@@ -411,25 +412,39 @@ CgFuse fuse_view(const CgWork& w, int k, int ph, int64_t n_e) {
     return f;
 }
 
-// Preconditioned CG on the transformed condensed system, k RHS, type T.
-// b, x, r, p, q: [N_s][k] of T.  x holds the initial guess on entry (x0_given)
-// or is zeroed.  Returns per-RHS iterations/status through the state.
+// Start of a CG solve: tolerance, r = b - A x (x0_given) or x = 0, r = b; q = 0;
+// rho = r.z, b.b, activity.  keep_dir: the direction p of the previous solve on
+// these buffers is continued (first beta = r.z / the r.z that formed it), as a
+// refinement step that replaces the residual without restarting the Krylov
+// recurrence; otherwise p = 0.
 template <typename T>
-int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol, int max_iter,
-           int check_every, bool x0_given, CgWork& w, hipStream_t st) {
+int cg_start(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol, bool x0_given, bool keep_dir,
+             CgWork& w, hipStream_t st) {
     const int64_t Ns = c->N_s;
     const double tol2 = tol * tol;
     HIPCHK(c, hipMemcpyAsync(w.s.tol2, &tol2, sizeof(double), hipMemcpyHostToDevice, st));
     if (x0_given) {
         int rc = apply_transformed<T>(c, x, q, k, RHS_MAJOR, nullptr, st);
         if (rc) return rc;
-        HIPCHK(c, launch_cg_init<T>(b, q, pinv<T>(c), r, p, Ns, k, w.partials, st));
+        HIPCHK(c, launch_cg_init<T>(b, q, pinv<T>(c), r, p, Ns, k, w.partials, st, keep_dir));
     } else {
         HIPCHK(c, launch_fill<T>(x, Ns * k, (T)0, st));
         HIPCHK(c, launch_fill<T>(q, Ns * k, (T)0, st));
-        HIPCHK(c, launch_cg_init<T>(b, (T*)nullptr, pinv<T>(c), r, p, Ns, k, w.partials, st));
+        HIPCHK(c, launch_cg_init<T>(b, (T*)nullptr, pinv<T>(c), r, p, Ns, k, w.partials, st, keep_dir));
     }
-    HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 3, k, w.s, RED_INIT, st));
+    HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 3, k, w.s, keep_dir ? RED_INIT_KEEP : RED_INIT, st));
+    return SEMCOND_OK;
+}
+
+// Preconditioned CG on the transformed condensed system, k RHS, type T.
+// b, x, r, p, q: [N_s][k] of T.  x holds the initial guess on entry (x0_given)
+// or is zeroed.  Returns per-RHS iterations/status through the state.
+template <typename T>
+int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol, int max_iter,
+           int check_every, bool x0_given, CgWork& w, hipStream_t st, bool keep_dir = false) {
+    const int64_t Ns = c->N_s;
+    int rc0 = cg_start<T>(c, b, x, r, p, q, k, tol, x0_given, keep_dir, w, st);
+    if (rc0) return rc0;
     if (check_every < 1) check_every = 1;
     // Small problems complete both reductions inside the kernels that consume
     // them (two launches per iteration instead of four); the redundant reads
@@ -487,7 +502,8 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
             if (rc) return rc;
             HIPCHK(c, launch_cg_step_fused<T>(x, r, p, q, pinv<T>(c), Ns, k, f, w.partials, st));
         } else {
-            int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta);
+            int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta, 0, nullptr,
+                                          w.s.active);
             if (rc) return rc;
             HIPCHK(c, launch_cg_reduce(w.energy, c->n_e, 1, k, w.s, RED_PQ, st));
             HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, st));
@@ -681,7 +697,7 @@ int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, in
 // or default persistent grid where a persistent kernel exists.
 template <typename T>
 int run_cg_any(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol, int max_iter, int check_every,
-               bool x0_given, int mode, CgWork& w, hipStream_t st) {
+               bool x0_given, int mode, CgWork& w, hipStream_t st, bool keep_dir = false) {
     int S = 0, G = 0;
     bool use = false;
     if (mode != SEMCOND_CG_STEPWISE && persist_supported(c->L.NI, 1, k)) {
@@ -694,20 +710,9 @@ int run_cg_any(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double
             use = persist_default(c, k, dtype_of<T>(), &S, &G);
         }
     }
-    if (!use) return run_cg<T>(c, b, x, r, p, q, k, tol, max_iter, check_every, x0_given, w, st);
-    const int64_t Ns = c->N_s;
-    const double tol2 = tol * tol;
-    HIPCHK(c, hipMemcpyAsync(w.s.tol2, &tol2, sizeof(double), hipMemcpyHostToDevice, st));
-    if (x0_given) {
-        int rc = apply_transformed<T>(c, x, q, k, RHS_MAJOR, nullptr, st);
-        if (rc) return rc;
-        HIPCHK(c, launch_cg_init<T>(b, q, pinv<T>(c), r, p, Ns, k, w.partials, st));
-    } else {
-        HIPCHK(c, launch_fill<T>(x, Ns * k, (T)0, st));
-        HIPCHK(c, launch_fill<T>(q, Ns * k, (T)0, st));
-        HIPCHK(c, launch_cg_init<T>(b, (T*)nullptr, pinv<T>(c), r, p, Ns, k, w.partials, st));
-    }
-    HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 3, k, w.s, RED_INIT, st));
+    if (!use) return run_cg<T>(c, b, x, r, p, q, k, tol, max_iter, check_every, x0_given, w, st, keep_dir);
+    int rc = cg_start<T>(c, b, x, r, p, q, k, tol, x0_given, keep_dir, w, st);
+    if (rc) return rc;
     return run_persistent<T>(c, x, r, p, q, k, tol, max_iter, w, S, G, st);
 }
 
@@ -1174,11 +1179,12 @@ void semcond_solve_opts_default(semcond_solve_opts* o) {
     o->recover_interior = 1;
     o->x0 = nullptr;
     o->skel_out = nullptr;
-    o->inner_tol = 1e-5;
+    o->inner_tol = 3e-3;
     o->max_outer = 30;
     o->rhs_dual = 0;
     o->persistent = SEMCOND_CG_AUTO;
     o->g_dirichlet = nullptr;
+    o->ir_restart = 0;
 }
 
 int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_solve_opts* opts,
@@ -1311,6 +1317,8 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
         if (!o.x0) HIPCHK(c, launch_fill<double>(x, nv, 0.0, st));
         HIPCHK(c, launch_fill<double>(q, nv, 0.0, st));
         int step = 0;
+        double prev_worst = 0.0;
+        bool keep = false;  // continue the inner direction in this step
         for (;; ++step) {
             // r = b - A64 x (q holds A64 x; zeroed again by cg_init), convergence per RHS
             if (step > 0 || o.x0) {
@@ -1337,9 +1345,23 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
                     if (ho.active[i] && status[i] == 0) status[i] = SEMCOND_ENOTCONV;
                 break;
             }
+            // Inner tolerance: inner_tol, or a looser one when a smaller reduction
+            // (with a factor 4 margin) takes every active RHS to tol.
+            double worst = 0.0, need = 0.5;
+            for (int i = 0; i < k; ++i)
+                if (ho.active[i] && status[i] >= 0) {
+                    worst = std::max(worst, relres[i]);
+                    if (relres[i] > 0.0) need = std::min(need, 0.25 * o.tol / relres[i]);
+                }
+            const double run_tol = std::max(o.inner_tol, need);
+            // The FP32 CG continues its search direction across refinement steps
+            // (only the residual is replaced by the FP64 one) unless restarts are
+            // asked for, or the last step did not halve the worst residual.
+            keep = step > 0 && !o.ir_restart && worst < 0.5 * prev_worst;
+            prev_worst = worst;
             HIPCHK(c, launch_convert_masked(r, r32, nv, k, wo.s.active, st));
-            rc = run_cg_any<float>(c, r32, x32, b32, p32, q32, k, o.inner_tol, o.max_iter, o.check_every, false,
-                                   o.persistent, w, st);
+            rc = run_cg_any<float>(c, r32, x32, b32, p32, q32, k, run_tol, o.max_iter, o.check_every, false,
+                                   o.persistent, w, st, keep);
             if (rc) return rc;
             CgHost hi;
             rc = read_state(c, w, k, &hi, st);

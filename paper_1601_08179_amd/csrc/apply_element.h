@@ -139,6 +139,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
 #define UV(q) F[NFACE + NEDGE + (q)]
 
     for (int r = 0; r < k; ++r) {
+        if (A.act && !A.act[r]) continue;  // a stopped right-hand side
         // The products of the metric terms are formed anew for every right-hand
         // side instead of being kept live across the loop (register pressure).
         T d0 = d0e, d1 = d1e, d2 = d2e, d3 = d3e;
@@ -565,6 +566,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
     __shared__ double s_fz[FZ ? 2 * (WG / 64) : 1];
 
     auto item = [&](const int64_t e, const bool live, const uint32_t r) __attribute__((always_inline)) {
+        if (A.act && !A.act[r]) return;  // a stopped right-hand side (the same in the whole workgroup)
         if constexpr (DIR && ONE && FZ) {
             if (!A.fz.act_prev[r]) {  // stopped before this iteration: nothing to gather
                 if (blockIdx.x == 0 && tid == 0) cg_carry_stopped(A.fz, (int)r);

@@ -59,8 +59,9 @@ __device__ inline void block_sums(const double* v, int64_t qstride, int64_t n, i
 }
 
 // Completion of the r.z / r.r reduction of a step for RHS r (RED_RZ):
-// iteration count, convergence on r.r <= tol^2 b.b, else beta = r.z / rho and
-// rho = r.z.  Reads the state of the previous iteration's slot (rho_prev,
+// iteration count, convergence on r.r <= tol^2 b.b (rho kept: the r.z that
+// formed the last direction, which a continued solve divides by), else beta =
+// r.z / rho and rho = r.z.  Reads the state of the previous iteration's slot (rho_prev,
 // act_prev) and, when `store`, writes this iteration's slot and the per-RHS
 // counters.  Returns beta (0 for a converged or stopped RHS); *still receives
 // whether the RHS keeps iterating.

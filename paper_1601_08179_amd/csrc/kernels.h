@@ -72,6 +72,9 @@ struct ApplyArgs {
     // workgroup completes the previous step's r.z reduction itself (RED_RZ),
     // and the workgroups of x = 0 store the new state.
     CgFuse fz = {};
+    // Nullable, [k]: right-hand sides r with act[r] == 0 are skipped (stopped CG
+    // right-hand sides in the loop with separate reductions).
+    const int* act = nullptr;
 };
 
 constexpr int kMaxRhs = 256;  // right-hand sides per call
@@ -154,18 +157,21 @@ template <typename T>
 hipError_t launch_transpose(const T* in, T* out, int64_t R, int64_t C, hipStream_t st);
 
 // r = b - q0 (q0 nullable: then r = b; else q0 is zeroed after use), p = 0
-// (the previous direction of the first step, whose beta is 0),
+// (the previous direction of the first step, whose beta is 0) unless keep_p,
 // partials[0]: r.z, [1]: r.r, [2]: b.b  ([3][vec_blocks(k)][k] doubles).
 template <typename T>
 hipError_t launch_cg_init(const T* b, T* q0, const T* pinv, T* r, T* p, int64_t Ns, int k,
-                          double* partials, hipStream_t st);
+                          double* partials, hipStream_t st, bool keep_p = false);
 // Reduce [nparts][k] partials of `nq` quantities; mode selects the CG step logic.
-enum ReduceMode { RED_INIT = 0, RED_PQ = 1, RED_RZ = 2 };
+// RED_INIT_KEEP is RED_INIT for a CG that continues the direction p left by a
+// previous solve (cg_init with keep_p): beta = r.z / rho of that solve.
+enum ReduceMode { RED_INIT = 0, RED_PQ = 1, RED_RZ = 2, RED_INIT_KEEP = 3 };
 hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int k, CgState s, int mode,
                             hipStream_t st);
 // One CG step on active right-hand sides, with q = H~^ p already formed:
 // p = fmadd(beta, p, pinv r) (the direction the apply used), x += alpha p,
-// r -= alpha q; then q = 0 and partials[0] r.z (z = pinv r), [1] r.r.
+// r -= alpha q; then q = 0 and partials[0] r.z (z = pinv r), [1] r.r.  Blocks
+// of stopped right-hand sides return at once.
 template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s,
                           double* partials, hipStream_t st);
@@ -174,6 +180,8 @@ hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int
 // breakdown); partials [2][fused_step_blocks(k)][k] of r.z and r.r for the next
 // apply's fused completion.
 constexpr int kFusedStepThreads = 1024;
+// Nodes per thread of the fused step whose loads are issued before p.q is reduced.
+constexpr int kFusedStepPrefetch = 4;
 int fused_step_blocks(int k);
 template <typename T>
 hipError_t launch_cg_step_fused(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, const CgFuse& f,

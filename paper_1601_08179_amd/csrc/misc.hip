@@ -822,7 +822,7 @@ __device__ inline void block_partials(double (&acc)[NQ], int k, double* __restri
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_init(const T* __restrict__ b, T* __restrict__ q0,
                                                  const T* __restrict__ pinv, T* __restrict__ r, T* __restrict__ p,
-                                                 int64_t Ns, int k, double* __restrict__ partials) {
+                                                 int64_t Ns, int k, double* __restrict__ partials, int keep_p) {
     const int64_t off = (int64_t)blockIdx.y * Ns, stride = (int64_t)gridDim.x * blockDim.x;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < Ns; s += stride) {
@@ -835,7 +835,7 @@ __global__ __launch_bounds__(256) void k_cg_init(const T* __restrict__ b, T* __r
         }
         const T z = pinv[s] * rv;
         r[idx] = rv;
-        p[idx] = (T)0;
+        if (!keep_p) p[idx] = (T)0;
         acc[0] += (double)rv * (double)z;
         acc[1] += (double)rv * (double)rv;
         acc[2] += (double)bv * (double)bv;
@@ -845,14 +845,15 @@ __global__ __launch_bounds__(256) void k_cg_init(const T* __restrict__ b, T* __r
 
 template <typename T>
 hipError_t launch_cg_init(const T* b, T* q0, const T* pinv, T* r, T* p, int64_t Ns, int k, double* partials,
-                          hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_init<T>, dim3(vec_blocks(k), k), dim3(256), 0, st, b, q0, pinv, r, p, Ns, k, partials);
+                          hipStream_t st, bool keep_p) {
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(vec_blocks(k), k), dim3(256), 0, st, b, q0, pinv, r, p, Ns, k, partials,
+                       keep_p ? 1 : 0);
     return hipGetLastError();
 }
 template hipError_t launch_cg_init<double>(const double*, double*, const double*, double*, double*, int64_t, int,
-                                           double*, hipStream_t);
+                                           double*, hipStream_t, bool);
 template hipError_t launch_cg_init<float>(const float*, float*, const float*, float*, float*, int64_t, int, double*,
-                                          hipStream_t);
+                                          hipStream_t, bool);
 
 // One block of B = k * floor(256/k) threads: thread t sums RHS t mod k over
 // the parts t/k, t/k + B/k, ... (all loads of a thread issued together).  For
@@ -932,14 +933,18 @@ __global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __re
     }
     if (t < k) {
         const double t0 = acc[0], t1 = acc[1], t2 = acc[2];
-        if (mode == RED_INIT) {
+        if (mode == RED_INIT || mode == RED_INIT_KEEP) {
             const double rz = t0, rr = t1, b2 = t2;
             s.rho[r] = rz;
             s.rr[r] = rr;
             s.bb[r] = b2;
             s.iters[r] = 0;
             s.alpha[r] = 0.0;
-            s.beta[r] = 0.0;
+            // continued direction: the first step takes p = z + (r.z / rho_old) p_old,
+            // rho_old the r.z that formed p_old (kept at convergence); a fresh
+            // start has p = 0
+            const bool cont = mode == RED_INIT_KEEP && rho > 0.0 && isfinite(rho) && isfinite(rz);
+            s.beta[r] = cont ? rz / rho : 0.0;
             const bool bad = !isfinite(rr) || !isfinite(rz);
             s.status[r] = bad ? -5 : 0;
             s.active[r] = bad ? 0 : ((rr > tol2 * b2) ? 1 : 0);
@@ -996,7 +1001,9 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
     const int64_t off = (int64_t)rhs * Ns, stride = (int64_t)gridDim.x * blockDim.x;
     const T alpha = (T)s.alpha[rhs];
     const T beta = (T)s.beta[rhs];
-    const bool act = s.active[rhs] != 0;
+    // A stopped right-hand side keeps x, r and p; its q is not read again (the
+    // apply skips it) and its partial sums are ignored.
+    if (s.active[rhs] == 0) return;
     double acc[2] = {0.0, 0.0};
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < Ns; n += stride) {
         const int64_t idx = off + n;
@@ -1004,13 +1011,11 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
         const T qv = q[idx];
         const T pn = pinv[n];
         q[idx] = (T)0;  // q is accumulated from zero by the next operator application
-        if (act) {
-            const T pv = fmadd(beta, p[idx], pn * rv);  // the direction the apply used
-            p[idx] = pv;
-            x[idx] += alpha * pv;
-            rv -= alpha * qv;
-            r[idx] = rv;
-        }
+        const T pv = fmadd(beta, p[idx], pn * rv);  // the direction the apply used
+        p[idx] = pv;
+        x[idx] += alpha * pv;
+        rv -= alpha * qv;
+        r[idx] = rv;
         const T z = pn * rv;
         acc[0] += (double)rv * (double)z;
         acc[1] += (double)rv * (double)rv;
@@ -1044,6 +1049,25 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
     __shared__ double s_red[2 * (NT / 64)];
     const int rhs = blockIdx.y;
     if (!f.act[rhs]) return;  // stopped (its state is already carried by the apply)
+    // The thread's first SU nodes are loaded before p.q is reduced, so that the
+    // vector loads and the energy loads are in flight together; the nodes are
+    // then processed in the same order as the rest (n0, n0 + stride, ...).
+    constexpr int SU = kFusedStepPrefetch;
+    const int64_t off = (int64_t)rhs * Ns, stride = (int64_t)gridDim.x * NT;
+    const int64_t n0 = (int64_t)blockIdx.x * NT + threadIdx.x;
+    T rv0[SU], qv0[SU], pn0[SU], pp0[SU], xv0[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        const int64_t n = n0 + u * stride;
+        rv0[u] = qv0[u] = pn0[u] = pp0[u] = xv0[u] = (T)0;
+        if (n < Ns) {
+            rv0[u] = r[off + n];
+            qv0[u] = q[off + n];
+            pn0[u] = pinv[n];
+            pp0[u] = p[off + n];
+            xv0[u] = x[off + n];
+        }
+    }
     double pq[1];
     block_sums<NT, 1>(f.energy + rhs, 0, f.n_e, k, s_red, pq);
     bool act;
@@ -1051,22 +1075,27 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
     // a stopped RHS keeps x, r and p; its q and partial sums are not read again
     if (!act) return;
     const T beta = (T)f.beta[rhs];
-    const int64_t off = (int64_t)rhs * Ns, stride = (int64_t)gridDim.x * NT;
     double acc[2] = {0.0, 0.0};
-    for (int64_t n = (int64_t)blockIdx.x * NT + threadIdx.x; n < Ns; n += stride) {
+    auto node = [&](int64_t n, T rv, T qv, T pn, T pold, T xv) __attribute__((always_inline)) {
         const int64_t idx = off + n;
-        T rv = r[idx];
-        const T qv = q[idx];
-        const T pn = pinv[n];
         q[idx] = (T)0;  // q is accumulated from zero by the next operator application
-        const T pv = fmadd(beta, p[idx], pn * rv);  // the direction the apply used
+        const T pv = fmadd(beta, pold, pn * rv);  // the direction the apply used
         p[idx] = pv;
-        x[idx] += alpha * pv;
+        x[idx] = xv + alpha * pv;
         rv -= alpha * qv;
         r[idx] = rv;
         const T z = pn * rv;
         acc[0] += (double)rv * (double)z;
         acc[1] += (double)rv * (double)rv;
+    };
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        const int64_t n = n0 + u * stride;
+        if (n < Ns) node(n, rv0[u], qv0[u], pn0[u], pp0[u], xv0[u]);
+    }
+    for (int64_t n = n0 + SU * stride; n < Ns; n += stride) {
+        const int64_t idx = off + n;
+        node(n, r[idx], q[idx], pinv[n], p[idx], x[idx]);
     }
 #pragma unroll
     for (int qq = 0; qq < 2; ++qq) acc[qq] = wave_sum(acc[qq]);

@@ -21,12 +21,15 @@ def _direct(op, f):
     return np.stack([op.recover_interior(f[r], op.solve_condensed(f[r])) for r in range(f.shape[0])])
 
 
+@pytest.mark.parametrize("restart", [False, True])
 @pytest.mark.parametrize("name", ["config1", "stretched3_p5", "lam_e_p3", "neumann_p6", "stretched3_p8", "p17_planes"])
-def test_mixed_ir_matches_direct(lib, name):
-    print("case", name, flush=True)
+def test_mixed_ir_matches_direct(lib, name, restart):
+    """Refinement with the inner direction continued across steps (default)
+    and with every inner CG restarted."""
+    print("case", name, "restart", restart, flush=True)
     ctx, op, g, free = both(MESHES[name]())
     f = W.random_skeleton_input(op.sizes["N"], k=3, seed=11)
-    u, info = ctx.solve(_t(f), tol=1e-12, precision=lib.PREC_MIXED_IR, inner_tol=1e-4)
+    u, info = ctx.solve(_t(f), tol=1e-12, precision=lib.PREC_MIXED_IR, inner_tol=1e-4, ir_restart=restart)
     ref = _direct(op, f)
     u = u.cpu().numpy()
     for r in range(3):
