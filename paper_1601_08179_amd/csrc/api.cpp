@@ -68,6 +68,7 @@ struct semcond_ctx {
     Buffer ws_nodal;    // nodal right-hand sides of dual solves
     Buffer ws_persist;  // partials and barrier words of the persistent CG
     Buffer ws_lift;     // prescribed Dirichlet values (transformed) and a temporary
+    Buffer ws_slots;    // per-side output slots of the CG applies (layout.h)
     int* h_active = nullptr;  // pinned host copy of CG activity flags
     int h_active_cap = 0;
     hipEvent_t poll_ev[2] = {nullptr, nullptr};  // lagged convergence polls of the fused CG loop
@@ -237,7 +238,8 @@ enum VecLayout { NODE_MAJOR = 0, RHS_MAJOR = 1 };
 template <typename T>
 int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, double* energy, hipStream_t st,
                       bool v_is_zero = false, const T* dir_r = nullptr, const double* dir_beta = nullptr,
-                      int read_con = 0, const CgFuse* fz = nullptr, const int* act = nullptr) {
+                      int read_con = 0, const CgFuse* fz = nullptr, const int* act = nullptr,
+                      T* slots = nullptr) {
     if (!v_is_zero) HIPCHK(c, launch_fill<T>(v, c->N_s * k, (T)0, st));
     ApplyArgs<T> a = apply_args<T>(c);
     a.u = u;
@@ -255,6 +257,11 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, do
         if (fz) a.fz = *fz;
     }
     a.act = act;
+    if (slots) {
+        if (lay != RHS_MAJOR || !v_is_zero) return fail(c, SEMCOND_EINVAL, "slot output needs RHS-major vectors");
+        a.slots = slots;
+        a.qlen = slot_len(c->L);
+    }
     if (c->prof) {
         int rc = profile_begin(c, SEMCOND_KERNEL_APPLY, st);
         if (rc) return rc;
@@ -446,6 +453,17 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     int rc0 = cg_start<T>(c, b, x, r, p, q, k, tol, x0_given, keep_dir, w, st);
     if (rc0) return rc0;
     if (check_every < 1) check_every = 1;
+    // The loop's applies store per-side slots (plain stores, no atomics) that
+    // the step sums in a fixed order; cleared here, so that slots no element
+    // writes read 0.
+    T* Q = nullptr;
+    const int64_t qlen = slot_len(c->L);
+    if (qlen * (int64_t)k < (int64_t(1) << 31)) {
+        rc0 = grow(c, c->ws_slots, (size_t)qlen * k * sizeof(T));
+        if (rc0) return rc0;
+        Q = (T*)c->ws_slots.ptr;
+        HIPCHK(c, launch_fill<T>(Q, qlen * k, (T)0, st));
+    }
     // Small problems complete both reductions inside the kernels that consume
     // them (two launches per iteration instead of four); the redundant reads
     // of the partial sums grow with n_e k.
@@ -490,23 +508,24 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
                 if (none_active(c->h_active)) break;
             }
         }
-        // q is zero here: zeroed at start and by every step.  The apply forms
-        // the direction p = beta p + z at its gather; the step stores it.
+        // The apply writes the slots Q (else adds into q, which is zero here:
+        // zeroed at start and by every step).  It forms the direction
+        // p = beta p + z at its gather; the step stores it.
         if (fused) {
             // slot it & 1 is this iteration's rho / active, the other the previous one's
             CgFuse f = fuse_view(w, k, it & 1, c->n_e);
             f.host_act = c->h_flags;
             f.epoch2 = epoch2;
             int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta, 0,
-                                          it > 0 ? &f : nullptr);
+                                          it > 0 ? &f : nullptr, nullptr, Q);
             if (rc) return rc;
-            HIPCHK(c, launch_cg_step_fused<T>(x, r, p, q, pinv<T>(c), Ns, k, f, w.partials, st));
+            HIPCHK(c, launch_cg_step_fused<T>(x, r, p, q, pinv<T>(c), Ns, k, f, w.partials, Q, qlen, c->L, st));
         } else {
             int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta, 0, nullptr,
-                                          w.s.active);
+                                          w.s.active, Q);
             if (rc) return rc;
             HIPCHK(c, launch_cg_reduce(w.energy, c->n_e, 1, k, w.s, RED_PQ, st));
-            HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, st));
+            HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, Q, qlen, c->L, st));
             HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 2, k, w.s, RED_RZ, st));
         }
         n_it = it + 1;
@@ -844,6 +863,7 @@ int semcond_destroy(semcond_ctx* c) {
     hipFree(c->ws_nodal.ptr);
     hipFree(c->ws_persist.ptr);
     hipFree(c->ws_lift.ptr);
+    hipFree(c->ws_slots.ptr);
     if (c->h_active) hipHostFree(c->h_active);
     if (c->h_flags) hipHostFree(c->h_flags);
     for (hipEvent_t e : c->poll_ev)

@@ -54,6 +54,16 @@ constexpr int apply_lanes(int NI) {
 }
 constexpr int apply_pack(int NI) { return apply_threads(NI) / apply_lanes(NI); }
 
+// R: the element's row value of a skeleton node, stored into the element's slot
+// of the node (qr, the right-hand side's slots, when set) or added into vr.
+template <typename T>
+__device__ inline void out_store(const ApplyArgs<T>& A, T* vr, T* qr, uint32_t node, int slot, T val) {
+    if (qr)
+        qr[slot_addr(A.g.L, node, slot)] = val;
+    else
+        atomic_add(vr + node * A.ns, val);
+}
+
 // Shared memory of one element.
 template <typename T, int NI>
 struct ApplySmem {
@@ -267,6 +277,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
 
         double en = 0.0;
         T* const vr = A.v + (size_t)r * A.rs;
+        T* const qr = A.slots ? A.slots + (size_t)r * A.qlen : nullptr;
         // ---- faces, one algebraic form for all six (Sec. 6 primary part, Table 2
         // condensed part), one face per round so that every face-dependent
         // quantity is wave-uniform.  Face f = w,e,s,n,b,t has slot (s1,s2) =
@@ -305,7 +316,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                               dfast * m0 * (ca[s2] * UE(efl, s1) + cb[s2] * UE(efh, s1)) +
                               dslow * m0 * (ca[s1] * UE(esl, s2) + cb[s1] * UE(esh, s2)) + cond;
                 if (!con && live) {
-                    atomic_add(vr + (fbase + (uint32_t)loc) * (uint32_t)A.ns, out);
+                    out_store(A, vr, qr, fbase + (uint32_t)loc, 1 - (f & 1), out);
                     en += (double)uf * (double)out;
                 }
             }
@@ -346,7 +357,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                 const T out = (dg0 + dpar * m02 * lam[m]) * ue + m0 * K0p * (do1 * UE(q ^ 1, m) + do2 * UE(q ^ 2, m)) +
                               dpar * m02 * (ca[m] * UV(vlo) + cb[m] * UV(vhi)) + m0 * (do1 * l1 + do2 * l2);
                 if (!econ[6 + q] && live) {
-                    atomic_add(vr + ((uint32_t)ebase[6 + q] + (uint32_t)m) * (uint32_t)A.ns, out);
+                    out_store(A, vr, qr, (uint32_t)ebase[6 + q] + (uint32_t)m, (1 - b0) + 2 * (1 - b1), out);
                     en += (double)ue * (double)out;
                 }
             }
@@ -371,7 +382,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                           m02 * K0p * (d1 * UV(q ^ 1) + d2 * UV(q ^ 2) + d3 * UV(q ^ 4)) +
                           m02 * (d1 * sx + d2 * sy + d3 * sz);
             if (!econ[18 + q] && live) {
-                atomic_add(vr + (uint32_t)ebase[18 + q] * (uint32_t)A.ns, out);
+                out_store(A, vr, qr, (uint32_t)ebase[18 + q], (1 - ib) + 2 * (1 - jb) + 4 * (1 - kb), out);
                 en += (double)UV(q) * (double)out;
             }
         }
@@ -635,6 +646,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
 
         double en = 0.0;
         T* const vr = A.v + (size_t)r * A.rs;
+        T* const qr = A.slots ? A.slots + (size_t)r * A.qlen : nullptr;
         // ---- faces: primary part (Sec. 6) + condensed part (Table 2), pairs w/e, s/n, b/t.
         // Face f has slots (k,j), (k,j), (k,i), (k,i), (j,i), (j,i); bordering edges (UE index)
         // fast-lo, fast-hi, slow-lo, slow-hi: w {8,10,4,6} e {9,11,5,7} s {8,9,0,2}
@@ -673,7 +685,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                               dfast * m0 * (ta2 * UE(efl_t[f], s1) + tb2 * UE(efh_t[f], s1)) +
                               dslow * m0 * (ta1 * UE(esl_t[f], s2) + tb1 * UE(esh_t[f], s2)) + cnd[f];
                 if (!fcon[f] && live) {
-                    atomic_add(vr + (E.fb[f] + (uint32_t)t) * A.ns, out);
+                    out_store(A, vr, qr, E.fb[f] + (uint32_t)t, 1 - (f & 1), out);
                     en += (double)uf * (double)out;
                 }
             }
@@ -717,7 +729,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                 bool con;
                 edge_node<NI>(L, E, par, eb0, eb1, em, &node, &con);
                 if (!con && live) {
-                    atomic_add(vr + node * A.ns, out);
+                    out_store(A, vr, qr, node, (1 - eb0) + 2 * (1 - eb1), out);
                     en += (double)ue * (double)out;
                 }
             }
@@ -745,7 +757,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
             bool con;
             vertex_node(L, E, vib, vjb, vkb, &node, &con);
             if (!con && live) {
-                atomic_add(vr + node * A.ns, out);
+                out_store(A, vr, qr, node, (1 - vib) + 2 * (1 - vjb) + 4 * (1 - vkb), out);
                 en += (double)UV(q) * (double)out;
             }
         }

@@ -75,6 +75,11 @@ struct ApplyArgs {
     // Nullable, [k]: right-hand sides r with act[r] == 0 are skipped (stopped CG
     // right-hand sides in the loop with separate reductions).
     const int* act = nullptr;
+    // Nullable: the element rows are stored into per-side slots (layout.h)
+    // slots[r * qlen + slot_addr(node, slot)] instead of being added into v
+    // (RHS-major only, ns = 1).
+    T* slots = nullptr;
+    int64_t qlen = 0;
 };
 
 constexpr int kMaxRhs = 256;  // right-hand sides per call
@@ -171,10 +176,12 @@ hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int 
 // One CG step on active right-hand sides, with q = H~^ p already formed:
 // p = fmadd(beta, p, pinv r) (the direction the apply used), x += alpha p,
 // r -= alpha q; then q = 0 and partials[0] r.z (z = pinv r), [1] r.r.  Blocks
-// of stopped right-hand sides return at once.
+// of stopped right-hand sides return at once.  With qs (nullable) q is the
+// slot sum of the apply's per-side slots (qs + rhs * qlen, layout.h) and is
+// not cleared.
 template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s,
-                          double* partials, hipStream_t st);
+                          double* partials, const T* qs, int64_t qlen, const Layout& L, hipStream_t st);
 // The same step with p.q completed by every block from the element energies
 // f.energy (RED_PQ on slot f.rho / f.act; blocks x = 0 store pq, alpha and a
 // breakdown); partials [2][fused_step_blocks(k)][k] of r.z and r.r for the next
@@ -185,6 +192,6 @@ constexpr int kFusedStepPrefetch = 4;
 int fused_step_blocks(int k);
 template <typename T>
 hipError_t launch_cg_step_fused(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, const CgFuse& f,
-                                double* partials, hipStream_t st);
+                                double* partials, const T* qs, int64_t qlen, const Layout& L, hipStream_t st);
 
 }  // namespace semcond

@@ -73,6 +73,45 @@ __host__ __device__ inline int64_t v_base(const Layout& L, int vz, int vy, int v
     return L.oV + ((int64_t)vz * (L.n2 + 1) + vy) * (L.n1 + 1) + vx;
 }
 
+// Per-side output slots of the condensed operator inside the conjugate
+// gradients: every element stores its rows of a shared entity into a slot of
+// its own (plain stores), and the assembly R becomes a fixed-order sum of the
+// slots of a node.  A face node has 2 slots (slot 1 - side of the element's
+// face: w, s, b -> 1; e, n, t -> 0), an edge node 4 ((1 - b0) + 2 (1 - b1) for
+// the element's boundary bits of the edge), a vertex 8 ((1 - ib) + 2 (1 - jb) +
+// 4 (1 - kb)).  Per right-hand side: [2][N_s] (slots 0 and 1 of every node),
+// [2][edge nodes] (slots 2, 3 of edges), [6][vertices] (slots 2..7).  Slots
+// that no element writes (domain boundary sides, Dirichlet entities) hold 0.
+__host__ __device__ inline int64_t slot_len(const Layout& L) {
+    return 2 * L.Ns + 2 * (L.oV - L.oEx) + 6 * (L.Ns - L.oV);
+}
+// Offset of (node, slot) within one right-hand side (slot_len < 2^31).
+__host__ __device__ inline uint32_t slot_addr(const Layout& L, uint32_t node, int slot) {
+    const uint32_t Ns = (uint32_t)L.Ns, oEx = (uint32_t)L.oEx, oV = (uint32_t)L.oV;
+    if (slot < 2) return (uint32_t)slot * Ns + node;
+    const uint32_t nE = oV - oEx;
+    if (node < oV) return 2 * Ns + (uint32_t)(slot - 2) * nE + (node - oEx);
+    return 2 * Ns + 2 * nE + (uint32_t)(slot - 2) * (Ns - oV) + (node - oV);
+}
+// Assembled value of a node: its slots summed in slot order.
+template <typename T>
+__host__ __device__ inline T slot_sum(const Layout& L, const T* Q, uint32_t node) {
+    const uint32_t Ns = (uint32_t)L.Ns, oEx = (uint32_t)L.oEx, oV = (uint32_t)L.oV;
+    T v = Q[node] + Q[Ns + node];
+    if (node >= oEx) {
+        const uint32_t nE = oV - oEx;
+        if (node < oV) {
+            const uint32_t b = 2 * Ns + (node - oEx);
+            v += Q[b];
+            v += Q[b + nE];
+        } else {
+            const uint32_t nV = Ns - oV, b = 2 * Ns + 2 * nE + (node - oV);
+            for (int s = 0; s < 6; ++s) v += Q[b + (uint32_t)s * nV];
+        }
+    }
+    return v;
+}
+
 // Is a grid plane on a Dirichlet domain face?
 __host__ __device__ inline bool xcon(const Layout& L, int x) {
     return (x == 0 && (L.mask & 1u)) || (x == L.n1 && (L.mask & 2u));

@@ -993,10 +993,23 @@ hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int 
     return hipGetLastError();
 }
 
-template <typename T>
+// q of node n of RHS rhs: the slot sum when slots are given (nothing to clear),
+// else q itself, cleared for the next operator application.
+template <typename T, bool SLOTS>
+__device__ inline T cg_q(T* __restrict__ q, const T* __restrict__ qs, int64_t qlen, const Layout& L, int rhs,
+                         int64_t idx, int64_t n) {
+    if constexpr (SLOTS) {
+        return slot_sum(L, qs + (size_t)rhs * qlen, (uint32_t)n);
+    } else {
+        return q[idx];
+    }
+}
+
+template <typename T, bool SLOTS>
 __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
                                                  T* __restrict__ q, const T* __restrict__ pinv, int64_t Ns, int k,
-                                                 CgState s, double* __restrict__ partials) {
+                                                 CgState s, double* __restrict__ partials, const T* __restrict__ qs,
+                                                 int64_t qlen, Layout L) {
     const int rhs = blockIdx.y;
     const int64_t off = (int64_t)rhs * Ns, stride = (int64_t)gridDim.x * blockDim.x;
     const T alpha = (T)s.alpha[rhs];
@@ -1008,9 +1021,9 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < Ns; n += stride) {
         const int64_t idx = off + n;
         T rv = r[idx];
-        const T qv = q[idx];
+        const T qv = cg_q<T, SLOTS>(q, qs, qlen, L, rhs, idx, n);
         const T pn = pinv[n];
-        q[idx] = (T)0;  // q is accumulated from zero by the next operator application
+        if constexpr (!SLOTS) q[idx] = (T)0;  // q is accumulated from zero by the next operator application
         const T pv = fmadd(beta, p[idx], pn * rv);  // the direction the apply used
         p[idx] = pv;
         x[idx] += alpha * pv;
@@ -1025,14 +1038,19 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
 
 template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s, double* partials,
-                          hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_step<T>, dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q, pinv, Ns, k, s, partials);
+                          const T* qs, int64_t qlen, const Layout& L, hipStream_t st) {
+    if (qs)
+        hipLaunchKernelGGL((k_cg_step<T, true>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q, pinv, Ns, k, s,
+                           partials, qs, qlen, L);
+    else
+        hipLaunchKernelGGL((k_cg_step<T, false>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q, pinv, Ns, k,
+                           s, partials, qs, qlen, L);
     return hipGetLastError();
 }
 template hipError_t launch_cg_step<double>(double*, double*, double*, double*, const double*, int64_t, int, CgState,
-                                           double*, hipStream_t);
+                                           double*, const double*, int64_t, const Layout&, hipStream_t);
 template hipError_t launch_cg_step<float>(float*, float*, float*, float*, const float*, int64_t, int, CgState, double*,
-                                          hipStream_t);
+                                          const float*, int64_t, const Layout&, hipStream_t);
 
 int fused_step_blocks(int k) { return std::max(1, 256 / k); }
 
@@ -1040,11 +1058,12 @@ int fused_step_blocks(int k) { return std::max(1, 256 / k); }
 // (blocks of kFusedStepThreads threads, fused_step_blocks(k) per RHS: few
 // blocks, so that each apply workgroup's later reduction of their partials
 // stays small).
-template <typename T>
+template <typename T, bool SLOTS>
 __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restrict__ x, T* __restrict__ r,
                                                                      T* __restrict__ p, T* __restrict__ q,
                                                                      const T* __restrict__ pinv, int64_t Ns, int k,
-                                                                     CgFuse f, double* __restrict__ partials) {
+                                                                     CgFuse f, double* __restrict__ partials,
+                                                                     const T* __restrict__ qs, int64_t qlen, Layout L) {
     constexpr int NT = kFusedStepThreads;
     __shared__ double s_red[2 * (NT / 64)];
     const int rhs = blockIdx.y;
@@ -1062,7 +1081,7 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
         rv0[u] = qv0[u] = pn0[u] = pp0[u] = xv0[u] = (T)0;
         if (n < Ns) {
             rv0[u] = r[off + n];
-            qv0[u] = q[off + n];
+            qv0[u] = cg_q<T, SLOTS>(q, qs, qlen, L, rhs, off + n, n);
             pn0[u] = pinv[n];
             pp0[u] = p[off + n];
             xv0[u] = x[off + n];
@@ -1078,7 +1097,7 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
     double acc[2] = {0.0, 0.0};
     auto node = [&](int64_t n, T rv, T qv, T pn, T pold, T xv) __attribute__((always_inline)) {
         const int64_t idx = off + n;
-        q[idx] = (T)0;  // q is accumulated from zero by the next operator application
+        if constexpr (!SLOTS) q[idx] = (T)0;  // q is accumulated from zero by the next operator application
         const T pv = fmadd(beta, pold, pn * rv);  // the direction the apply used
         p[idx] = pv;
         x[idx] = xv + alpha * pv;
@@ -1095,7 +1114,7 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
     }
     for (int64_t n = n0 + SU * stride; n < Ns; n += stride) {
         const int64_t idx = off + n;
-        node(n, r[idx], q[idx], pinv[n], p[idx], x[idx]);
+        node(n, r[idx], cg_q<T, SLOTS>(q, qs, qlen, L, rhs, idx, n), pinv[n], p[idx], x[idx]);
     }
 #pragma unroll
     for (int qq = 0; qq < 2; ++qq) acc[qq] = wave_sum(acc[qq]);
@@ -1114,15 +1133,21 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
 
 template <typename T>
 hipError_t launch_cg_step_fused(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, const CgFuse& f,
-                                double* partials, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_step_fused<T>, dim3(fused_step_blocks(k), k), dim3(kFusedStepThreads), 0, st, x, r, p, q,
-                       pinv, Ns, k, f, partials);
+                                double* partials, const T* qs, int64_t qlen, const Layout& L, hipStream_t st) {
+    if (qs)
+        hipLaunchKernelGGL((k_cg_step_fused<T, true>), dim3(fused_step_blocks(k), k), dim3(kFusedStepThreads), 0, st,
+                           x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L);
+    else
+        hipLaunchKernelGGL((k_cg_step_fused<T, false>), dim3(fused_step_blocks(k), k), dim3(kFusedStepThreads), 0, st,
+                           x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L);
     return hipGetLastError();
 }
 template hipError_t launch_cg_step_fused<double>(double*, double*, double*, double*, const double*, int64_t, int,
-                                                 const CgFuse&, double*, hipStream_t);
+                                                 const CgFuse&, double*, const double*, int64_t, const Layout&,
+                                                 hipStream_t);
 template hipError_t launch_cg_step_fused<float>(float*, float*, float*, float*, const float*, int64_t, int,
-                                                const CgFuse&, double*, hipStream_t);
+                                                const CgFuse&, double*, const float*, int64_t, const Layout&,
+                                                hipStream_t);
 
 // out[c][r] = in[r][c] for an R x C row-major array, 32 x 32 tiles through LDS;
 // a one-dimensional grid of tiles (tile t: rows (t / tc) * 32, columns
