@@ -491,9 +491,10 @@ def main():
     kern_s = pa_ms / 1e3 / max(pa_launches, 1)
 
     # Roofline of the dominant kernel of the timed solves.  Algorithmic FP64 bytes
-    # (k = 1): the CG apply gathers p, r and P^-1 (it forms the direction) and adds
-    # into q: 4 N_s; the persistent CG per iteration moves 13 N_s (apply 4; step:
-    # reads r, q, P^-1, p, x and writes q, p, x, r).
+    # (k = 1): the CG apply gathers p, r and P^-1 (it forms the direction) and
+    # produces q: 4 N_s (its per-side slot stores are an implementation choice and
+    # show in the counter traffic, not here); the persistent CG per iteration
+    # moves 13 N_s (apply 4; step: reads r, q, P^-1, p, x and writes q, p, x, r).
     if cg_ms >= ap_ms:
         dom = {"kernel": "k_pcg_persistent<double,7,%d>" % tS, "ms": cg_ms, "launches": cg_launches,
                "bytes": 13 * 8 * Ns * cg_iters, "traffic": None}

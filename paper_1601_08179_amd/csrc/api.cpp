@@ -235,6 +235,13 @@ hipError_t launch_apply(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t st) {
 // [k][N_s] (RHS-major, inside the conjugate gradients).
 enum VecLayout { NODE_MAJOR = 0, RHS_MAJOR = 1 };
 
+// Whether the CG applies store face rows into slots as well (else faces are
+// added into q; edges and vertices always use slots).  Measured on MI355X:
+// the FP32 loop is faster with face slots, the FP64 loop with face additions
+// (fewer bytes for the step to read).
+template <typename T>
+constexpr int cg_face_slots() { return sizeof(T) == 4 ? 1 : 0; }
+
 template <typename T>
 int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, double* energy, hipStream_t st,
                       bool v_is_zero = false, const T* dir_r = nullptr, const double* dir_beta = nullptr,
@@ -261,6 +268,7 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, do
         if (lay != RHS_MAJOR || !v_is_zero) return fail(c, SEMCOND_EINVAL, "slot output needs RHS-major vectors");
         a.slots = slots;
         a.qlen = slot_len(c->L);
+        a.face_slots = cg_face_slots<T>();
     }
     if (c->prof) {
         int rc = profile_begin(c, SEMCOND_KERNEL_APPLY, st);
@@ -453,9 +461,9 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     int rc0 = cg_start<T>(c, b, x, r, p, q, k, tol, x0_given, keep_dir, w, st);
     if (rc0) return rc0;
     if (check_every < 1) check_every = 1;
-    // The loop's applies store per-side slots (plain stores, no atomics) that
-    // the step sums in a fixed order; cleared here, so that slots no element
-    // writes read 0.
+    // The loop's applies store per-side slots of edges and vertices (faces too
+    // in FP32; plain stores, no atomics) that the step sums in a fixed order;
+    // cleared here, so that slots no element writes read 0.
     T* Q = nullptr;
     const int64_t qlen = slot_len(c->L);
     if (qlen * (int64_t)k < (int64_t(1) << 31)) {
@@ -508,9 +516,9 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
                 if (none_active(c->h_active)) break;
             }
         }
-        // The apply writes the slots Q (else adds into q, which is zero here:
-        // zeroed at start and by every step).  It forms the direction
-        // p = beta p + z at its gather; the step stores it.
+        // The apply writes the slots Q and adds face rows (all rows without Q)
+        // into q, which is zero here: zeroed at start and by every step.  It
+        // forms the direction p = beta p + z at its gather; the step stores it.
         if (fused) {
             // slot it & 1 is this iteration's rho / active, the other the previous one's
             CgFuse f = fuse_view(w, k, it & 1, c->n_e);
@@ -519,13 +527,15 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
             int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta, 0,
                                           it > 0 ? &f : nullptr, nullptr, Q);
             if (rc) return rc;
-            HIPCHK(c, launch_cg_step_fused<T>(x, r, p, q, pinv<T>(c), Ns, k, f, w.partials, Q, qlen, c->L, st));
+            HIPCHK(c, launch_cg_step_fused<T>(x, r, p, q, pinv<T>(c), Ns, k, f, w.partials, Q, qlen, c->L,
+                                              cg_face_slots<T>(), st));
         } else {
             int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta, 0, nullptr,
                                           w.s.active, Q);
             if (rc) return rc;
             HIPCHK(c, launch_cg_reduce(w.energy, c->n_e, 1, k, w.s, RED_PQ, st));
-            HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, Q, qlen, c->L, st));
+            HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, Q, qlen, c->L,
+                                        cg_face_slots<T>(), st));
             HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 2, k, w.s, RED_RZ, st));
         }
         n_it = it + 1;

@@ -55,10 +55,12 @@ constexpr int apply_lanes(int NI) {
 constexpr int apply_pack(int NI) { return apply_threads(NI) / apply_lanes(NI); }
 
 // R: the element's row value of a skeleton node, stored into the element's slot
-// of the node (qr, the right-hand side's slots, when set) or added into vr.
+// of the node (qr, the right-hand side's slots, when set; faces only with
+// face_slots) or added into vr.
 template <typename T>
-__device__ inline void out_store(const ApplyArgs<T>& A, T* vr, T* qr, uint32_t node, int slot, T val) {
-    if (qr)
+__device__ inline void out_store(const ApplyArgs<T>& A, T* vr, T* qr, uint32_t node, int slot, T val,
+                                 bool face = false) {
+    if (qr && (!face || A.face_slots))
         qr[slot_addr(A.g.L, node, slot)] = val;
     else
         atomic_add(vr + node * A.ns, val);
@@ -316,7 +318,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                               dfast * m0 * (ca[s2] * UE(efl, s1) + cb[s2] * UE(efh, s1)) +
                               dslow * m0 * (ca[s1] * UE(esl, s2) + cb[s1] * UE(esh, s2)) + cond;
                 if (!con && live) {
-                    out_store(A, vr, qr, fbase + (uint32_t)loc, 1 - (f & 1), out);
+                    out_store(A, vr, qr, fbase + (uint32_t)loc, 1 - (f & 1), out, true);
                     en += (double)uf * (double)out;
                 }
             }
@@ -685,7 +687,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                               dfast * m0 * (ta2 * UE(efl_t[f], s1) + tb2 * UE(efh_t[f], s1)) +
                               dslow * m0 * (ta1 * UE(esl_t[f], s2) + tb1 * UE(esh_t[f], s2)) + cnd[f];
                 if (!fcon[f] && live) {
-                    out_store(A, vr, qr, E.fb[f] + (uint32_t)t, 1 - (f & 1), out);
+                    out_store(A, vr, qr, E.fb[f] + (uint32_t)t, 1 - (f & 1), out, true);
                     en += (double)uf * (double)out;
                 }
             }

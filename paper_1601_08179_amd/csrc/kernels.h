@@ -75,11 +75,14 @@ struct ApplyArgs {
     // Nullable, [k]: right-hand sides r with act[r] == 0 are skipped (stopped CG
     // right-hand sides in the loop with separate reductions).
     const int* act = nullptr;
-    // Nullable: the element rows are stored into per-side slots (layout.h)
+    // Nullable: the element rows of edges and vertices (and of faces when
+    // face_slots) are stored into per-side slots (layout.h)
     // slots[r * qlen + slot_addr(node, slot)] instead of being added into v
-    // (RHS-major only, ns = 1).
+    // (RHS-major only, ns = 1).  Face rows otherwise go into v: two additions
+    // into zero, whose result does not depend on their order.
     T* slots = nullptr;
     int64_t qlen = 0;
+    int face_slots = 0;
 };
 
 constexpr int kMaxRhs = 256;  // right-hand sides per call
@@ -176,12 +179,14 @@ hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int 
 // One CG step on active right-hand sides, with q = H~^ p already formed:
 // p = fmadd(beta, p, pinv r) (the direction the apply used), x += alpha p,
 // r -= alpha q; then q = 0 and partials[0] r.z (z = pinv r), [1] r.r.  Blocks
-// of stopped right-hand sides return at once.  With qs (nullable) q is the
-// slot sum of the apply's per-side slots (qs + rhs * qlen, layout.h) and is
-// not cleared.
+// of stopped right-hand sides return at once.  With qs (nullable) q of edge and
+// vertex nodes (of all nodes with face_slots) is the slot sum of the apply's
+// per-side slots (qs + rhs * qlen, layout.h) and only the q entries that the
+// apply added into are cleared.
 template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s,
-                          double* partials, const T* qs, int64_t qlen, const Layout& L, hipStream_t st);
+                          double* partials, const T* qs, int64_t qlen, const Layout& L, int face_slots,
+                          hipStream_t st);
 // The same step with p.q completed by every block from the element energies
 // f.energy (RED_PQ on slot f.rho / f.act; blocks x = 0 store pq, alpha and a
 // breakdown); partials [2][fused_step_blocks(k)][k] of r.z and r.r for the next
@@ -192,6 +197,7 @@ constexpr int kFusedStepPrefetch = 4;
 int fused_step_blocks(int k);
 template <typename T>
 hipError_t launch_cg_step_fused(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, const CgFuse& f,
-                                double* partials, const T* qs, int64_t qlen, const Layout& L, hipStream_t st);
+                                double* partials, const T* qs, int64_t qlen, const Layout& L, int face_slots,
+                          hipStream_t st);
 
 }  // namespace semcond

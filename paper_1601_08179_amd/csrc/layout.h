@@ -93,7 +93,8 @@ __host__ __device__ inline uint32_t slot_addr(const Layout& L, uint32_t node, in
     if (node < oV) return 2 * Ns + (uint32_t)(slot - 2) * nE + (node - oEx);
     return 2 * Ns + 2 * nE + (uint32_t)(slot - 2) * (Ns - oV) + (node - oV);
 }
-// Assembled value of a node: its slots summed in slot order.
+// Assembled value of a node: its slots summed in slot order (faces: only with
+// face slots; otherwise a face node's value is the atomic sum in q).
 template <typename T>
 __host__ __device__ inline T slot_sum(const Layout& L, const T* Q, uint32_t node) {
     const uint32_t Ns = (uint32_t)L.Ns, oEx = (uint32_t)L.oEx, oV = (uint32_t)L.oV;

@@ -993,23 +993,27 @@ hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int 
     return hipGetLastError();
 }
 
-// q of node n of RHS rhs: the slot sum when slots are given (nothing to clear),
-// else q itself, cleared for the next operator application.
+// q of node n of RHS rhs: the slot sum for nodes whose rows went into slots
+// (edges and vertices, faces too with face_slots), else q itself, which the
+// caller clears for the next operator application (cg_q_clear).
 template <typename T, bool SLOTS>
-__device__ inline T cg_q(T* __restrict__ q, const T* __restrict__ qs, int64_t qlen, const Layout& L, int rhs,
-                         int64_t idx, int64_t n) {
+__device__ inline T cg_q(const T* __restrict__ q, const T* __restrict__ qs, int64_t qlen, const Layout& L, int rhs,
+                         int64_t idx, int64_t n, int face_slots) {
     if constexpr (SLOTS) {
-        return slot_sum(L, qs + (size_t)rhs * qlen, (uint32_t)n);
-    } else {
-        return q[idx];
+        if (face_slots || n >= L.oEx) return slot_sum(L, qs + (size_t)rhs * qlen, (uint32_t)n);
     }
+    return q[idx];
+}
+template <bool SLOTS>
+__device__ inline bool cg_q_clear(const Layout& L, int64_t n, int face_slots) {
+    return !SLOTS || (!face_slots && n < L.oEx);
 }
 
 template <typename T, bool SLOTS>
 __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
                                                  T* __restrict__ q, const T* __restrict__ pinv, int64_t Ns, int k,
                                                  CgState s, double* __restrict__ partials, const T* __restrict__ qs,
-                                                 int64_t qlen, Layout L) {
+                                                 int64_t qlen, Layout L, int fsl) {
     const int rhs = blockIdx.y;
     const int64_t off = (int64_t)rhs * Ns, stride = (int64_t)gridDim.x * blockDim.x;
     const T alpha = (T)s.alpha[rhs];
@@ -1021,9 +1025,9 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < Ns; n += stride) {
         const int64_t idx = off + n;
         T rv = r[idx];
-        const T qv = cg_q<T, SLOTS>(q, qs, qlen, L, rhs, idx, n);
+        const T qv = cg_q<T, SLOTS>(q, qs, qlen, L, rhs, idx, n, fsl);
         const T pn = pinv[n];
-        if constexpr (!SLOTS) q[idx] = (T)0;  // q is accumulated from zero by the next operator application
+        if (cg_q_clear<SLOTS>(L, n, fsl)) q[idx] = (T)0;  // q is accumulated from zero by the next apply
         const T pv = fmadd(beta, p[idx], pn * rv);  // the direction the apply used
         p[idx] = pv;
         x[idx] += alpha * pv;
@@ -1038,19 +1042,19 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
 
 template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s, double* partials,
-                          const T* qs, int64_t qlen, const Layout& L, hipStream_t st) {
+                          const T* qs, int64_t qlen, const Layout& L, int face_slots, hipStream_t st) {
     if (qs)
         hipLaunchKernelGGL((k_cg_step<T, true>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q, pinv, Ns, k, s,
-                           partials, qs, qlen, L);
+                           partials, qs, qlen, L, face_slots);
     else
         hipLaunchKernelGGL((k_cg_step<T, false>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q, pinv, Ns, k,
-                           s, partials, qs, qlen, L);
+                           s, partials, qs, qlen, L, face_slots);
     return hipGetLastError();
 }
 template hipError_t launch_cg_step<double>(double*, double*, double*, double*, const double*, int64_t, int, CgState,
-                                           double*, const double*, int64_t, const Layout&, hipStream_t);
+                                           double*, const double*, int64_t, const Layout&, int, hipStream_t);
 template hipError_t launch_cg_step<float>(float*, float*, float*, float*, const float*, int64_t, int, CgState, double*,
-                                          const float*, int64_t, const Layout&, hipStream_t);
+                                          const float*, int64_t, const Layout&, int, hipStream_t);
 
 int fused_step_blocks(int k) { return std::max(1, 256 / k); }
 
@@ -1063,7 +1067,8 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
                                                                      T* __restrict__ p, T* __restrict__ q,
                                                                      const T* __restrict__ pinv, int64_t Ns, int k,
                                                                      CgFuse f, double* __restrict__ partials,
-                                                                     const T* __restrict__ qs, int64_t qlen, Layout L) {
+                                                                     const T* __restrict__ qs, int64_t qlen, Layout L,
+                                                                     int fsl) {
     constexpr int NT = kFusedStepThreads;
     __shared__ double s_red[2 * (NT / 64)];
     const int rhs = blockIdx.y;
@@ -1081,7 +1086,7 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
         rv0[u] = qv0[u] = pn0[u] = pp0[u] = xv0[u] = (T)0;
         if (n < Ns) {
             rv0[u] = r[off + n];
-            qv0[u] = cg_q<T, SLOTS>(q, qs, qlen, L, rhs, off + n, n);
+            qv0[u] = cg_q<T, SLOTS>(q, qs, qlen, L, rhs, off + n, n, fsl);
             pn0[u] = pinv[n];
             pp0[u] = p[off + n];
             xv0[u] = x[off + n];
@@ -1097,7 +1102,7 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
     double acc[2] = {0.0, 0.0};
     auto node = [&](int64_t n, T rv, T qv, T pn, T pold, T xv) __attribute__((always_inline)) {
         const int64_t idx = off + n;
-        if constexpr (!SLOTS) q[idx] = (T)0;  // q is accumulated from zero by the next operator application
+        if (cg_q_clear<SLOTS>(L, n, fsl)) q[idx] = (T)0;  // q is accumulated from zero by the next apply
         const T pv = fmadd(beta, pold, pn * rv);  // the direction the apply used
         p[idx] = pv;
         x[idx] = xv + alpha * pv;
@@ -1114,7 +1119,7 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
     }
     for (int64_t n = n0 + SU * stride; n < Ns; n += stride) {
         const int64_t idx = off + n;
-        node(n, r[idx], cg_q<T, SLOTS>(q, qs, qlen, L, rhs, idx, n), pinv[n], p[idx], x[idx]);
+        node(n, r[idx], cg_q<T, SLOTS>(q, qs, qlen, L, rhs, idx, n, fsl), pinv[n], p[idx], x[idx]);
     }
 #pragma unroll
     for (int qq = 0; qq < 2; ++qq) acc[qq] = wave_sum(acc[qq]);
@@ -1133,20 +1138,21 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
 
 template <typename T>
 hipError_t launch_cg_step_fused(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, const CgFuse& f,
-                                double* partials, const T* qs, int64_t qlen, const Layout& L, hipStream_t st) {
+                                double* partials, const T* qs, int64_t qlen, const Layout& L, int face_slots,
+                                hipStream_t st) {
     if (qs)
         hipLaunchKernelGGL((k_cg_step_fused<T, true>), dim3(fused_step_blocks(k), k), dim3(kFusedStepThreads), 0, st,
-                           x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L);
+                           x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L, face_slots);
     else
         hipLaunchKernelGGL((k_cg_step_fused<T, false>), dim3(fused_step_blocks(k), k), dim3(kFusedStepThreads), 0, st,
-                           x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L);
+                           x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L, face_slots);
     return hipGetLastError();
 }
 template hipError_t launch_cg_step_fused<double>(double*, double*, double*, double*, const double*, int64_t, int,
-                                                 const CgFuse&, double*, const double*, int64_t, const Layout&,
+                                                 const CgFuse&, double*, const double*, int64_t, const Layout&, int,
                                                  hipStream_t);
 template hipError_t launch_cg_step_fused<float>(float*, float*, float*, float*, const float*, int64_t, int,
-                                                const CgFuse&, double*, const float*, int64_t, const Layout&,
+                                                const CgFuse&, double*, const float*, int64_t, const Layout&, int,
                                                 hipStream_t);
 
 // out[c][r] = in[r][c] for an R x C row-major array, 32 x 32 tiles through LDS;
