@@ -235,10 +235,10 @@ hipError_t launch_apply(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t st) {
 // [k][N_s] (RHS-major, inside the conjugate gradients).
 enum VecLayout { NODE_MAJOR = 0, RHS_MAJOR = 1 };
 
-// Whether the CG applies store face rows into slots as well (else faces are
-// added into q; edges and vertices always use slots).  Measured on MI355X:
-// the FP32 loop is faster with face slots, the FP64 loop with face additions
-// (fewer bytes for the step to read).
+// Whether the CG applies that use slots store face rows into slots as well
+// (else faces are added into q; edges and vertices use slots).  Measured on
+// MI355X: the FP32 loop is faster with face slots, the FP64 loop with face
+// additions (fewer bytes for the step to read).
 template <typename T>
 constexpr int cg_face_slots() { return sizeof(T) == 4 ? 1 : 0; }
 
@@ -461,21 +461,23 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     int rc0 = cg_start<T>(c, b, x, r, p, q, k, tol, x0_given, keep_dir, w, st);
     if (rc0) return rc0;
     if (check_every < 1) check_every = 1;
-    // The loop's applies store per-side slots of edges and vertices (faces too
-    // in FP32; plain stores, no atomics) that the step sums in a fixed order;
-    // cleared here, so that slots no element writes read 0.
+    // Small problems complete both reductions inside the kernels that consume
+    // them (two launches per iteration instead of four); the redundant reads
+    // of the partial sums grow with n_e k.
+    const bool fused = c->n_e * (int64_t)k <= kFusedMaxItems;
+    // In the loop with separate reductions the applies store per-side slots of
+    // edges and vertices (faces too in FP32; plain stores, no atomics) that the
+    // step sums in a fixed order; cleared here, so that slots no element writes
+    // read 0.  The small fused loop adds every row into q (measured faster
+    // there: its step is latency-bound and reads fewer values).
     T* Q = nullptr;
     const int64_t qlen = slot_len(c->L);
-    if (qlen * (int64_t)k < (int64_t(1) << 31)) {
+    if (!fused && qlen * (int64_t)k < (int64_t(1) << 31)) {
         rc0 = grow(c, c->ws_slots, (size_t)qlen * k * sizeof(T));
         if (rc0) return rc0;
         Q = (T*)c->ws_slots.ptr;
         HIPCHK(c, launch_fill<T>(Q, qlen * k, (T)0, st));
     }
-    // Small problems complete both reductions inside the kernels that consume
-    // them (two launches per iteration instead of four); the redundant reads
-    // of the partial sums grow with n_e k.
-    const bool fused = c->n_e * (int64_t)k <= kFusedMaxItems;
     if (fused) {
         for (hipEvent_t& e : c->poll_ev)
             if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));

@@ -57,10 +57,10 @@ constexpr int apply_pack(int NI) { return apply_threads(NI) / apply_lanes(NI); }
 // R: the element's row value of a skeleton node, stored into the element's slot
 // of the node (qr, the right-hand side's slots, when set; faces only with
 // face_slots) or added into vr.
-template <typename T>
+template <bool SL = true, typename T>
 __device__ inline void out_store(const ApplyArgs<T>& A, T* vr, T* qr, uint32_t node, int slot, T val,
                                  bool face = false) {
-    if (qr && (!face || A.face_slots))
+    if (SL && qr && (!face || A.face_slots))
         qr[slot_addr(A.g.L, node, slot)] = val;
     else
         atomic_add(vr + node * A.ns, val);
@@ -579,7 +579,12 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
     __shared__ double s_fz[FZ ? 2 * (WG / 64) : 1];
 
     auto item = [&](const int64_t e, const bool live, const uint32_t r) __attribute__((always_inline)) {
-        if (A.act && !A.act[r]) return;  // a stopped right-hand side (the same in the whole workgroup)
+        // a stopped right-hand side (the same in the whole workgroup); only the CG
+        // loop with separate reductions passes activity flags and slots
+        constexpr bool SL = DIR && !FZ;
+        if constexpr (SL) {
+            if (A.act && !A.act[r]) return;
+        }
         if constexpr (DIR && ONE && FZ) {
             if (!A.fz.act_prev[r]) {  // stopped before this iteration: nothing to gather
                 if (blockIdx.x == 0 && tid == 0) cg_carry_stopped(A.fz, (int)r);
@@ -648,7 +653,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
 
         double en = 0.0;
         T* const vr = A.v + (size_t)r * A.rs;
-        T* const qr = A.slots ? A.slots + (size_t)r * A.qlen : nullptr;
+        T* const qr = SL && A.slots ? A.slots + (size_t)r * A.qlen : nullptr;
         // ---- faces: primary part (Sec. 6) + condensed part (Table 2), pairs w/e, s/n, b/t.
         // Face f has slots (k,j), (k,j), (k,i), (k,i), (j,i), (j,i); bordering edges (UE index)
         // fast-lo, fast-hi, slow-lo, slow-hi: w {8,10,4,6} e {9,11,5,7} s {8,9,0,2}
@@ -687,7 +692,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                               dfast * m0 * (ta2 * UE(efl_t[f], s1) + tb2 * UE(efh_t[f], s1)) +
                               dslow * m0 * (ta1 * UE(esl_t[f], s2) + tb1 * UE(esh_t[f], s2)) + cnd[f];
                 if (!fcon[f] && live) {
-                    out_store(A, vr, qr, E.fb[f] + (uint32_t)t, 1 - (f & 1), out, true);
+                    out_store<SL>(A, vr, qr, E.fb[f] + (uint32_t)t, 1 - (f & 1), out, true);
                     en += (double)uf * (double)out;
                 }
             }
@@ -731,7 +736,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                 bool con;
                 edge_node<NI>(L, E, par, eb0, eb1, em, &node, &con);
                 if (!con && live) {
-                    out_store(A, vr, qr, node, (1 - eb0) + 2 * (1 - eb1), out);
+                    out_store<SL>(A, vr, qr, node, (1 - eb0) + 2 * (1 - eb1), out);
                     en += (double)ue * (double)out;
                 }
             }
@@ -759,7 +764,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
             bool con;
             vertex_node(L, E, vib, vjb, vkb, &node, &con);
             if (!con && live) {
-                out_store(A, vr, qr, node, (1 - vib) + 2 * (1 - vjb) + 4 * (1 - vkb), out);
+                out_store<SL>(A, vr, qr, node, (1 - vib) + 2 * (1 - vjb) + 4 * (1 - vkb), out);
                 en += (double)UV(q) * (double)out;
             }
         }

@@ -192,8 +192,6 @@ hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int
 // breakdown); partials [2][fused_step_blocks(k)][k] of r.z and r.r for the next
 // apply's fused completion.
 constexpr int kFusedStepThreads = 1024;
-// Nodes per thread of the fused step whose loads are issued before p.q is reduced.
-constexpr int kFusedStepPrefetch = 4;
 int fused_step_blocks(int k);
 template <typename T>
 hipError_t launch_cg_step_fused(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, const CgFuse& f,

@@ -1073,25 +1073,7 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
     __shared__ double s_red[2 * (NT / 64)];
     const int rhs = blockIdx.y;
     if (!f.act[rhs]) return;  // stopped (its state is already carried by the apply)
-    // The thread's first SU nodes are loaded before p.q is reduced, so that the
-    // vector loads and the energy loads are in flight together; the nodes are
-    // then processed in the same order as the rest (n0, n0 + stride, ...).
-    constexpr int SU = kFusedStepPrefetch;
     const int64_t off = (int64_t)rhs * Ns, stride = (int64_t)gridDim.x * NT;
-    const int64_t n0 = (int64_t)blockIdx.x * NT + threadIdx.x;
-    T rv0[SU], qv0[SU], pn0[SU], pp0[SU], xv0[SU];
-#pragma unroll
-    for (int u = 0; u < SU; ++u) {
-        const int64_t n = n0 + u * stride;
-        rv0[u] = qv0[u] = pn0[u] = pp0[u] = xv0[u] = (T)0;
-        if (n < Ns) {
-            rv0[u] = r[off + n];
-            qv0[u] = cg_q<T, SLOTS>(q, qs, qlen, L, rhs, off + n, n, fsl);
-            pn0[u] = pinv[n];
-            pp0[u] = p[off + n];
-            xv0[u] = x[off + n];
-        }
-    }
     double pq[1];
     block_sums<NT, 1>(f.energy + rhs, 0, f.n_e, k, s_red, pq);
     bool act;
@@ -1112,12 +1094,7 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
         acc[0] += (double)rv * (double)z;
         acc[1] += (double)rv * (double)rv;
     };
-#pragma unroll
-    for (int u = 0; u < SU; ++u) {
-        const int64_t n = n0 + u * stride;
-        if (n < Ns) node(n, rv0[u], qv0[u], pn0[u], pp0[u], xv0[u]);
-    }
-    for (int64_t n = n0 + SU * stride; n < Ns; n += stride) {
+    for (int64_t n = (int64_t)blockIdx.x * NT + threadIdx.x; n < Ns; n += stride) {
         const int64_t idx = off + n;
         node(n, r[idx], cg_q<T, SLOTS>(q, qs, qlen, L, rhs, idx, n, fsl), pinv[n], p[idx], x[idx]);
     }
