@@ -468,12 +468,14 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     // In the loop with separate reductions the applies store per-side slots of
     // edges and vertices (faces too in FP32; plain stores, no atomics) that the
     // step sums in a fixed order; cleared here, so that slots no element writes
-    // read 0.  The small fused loop adds every row into q (measured faster
-    // there: its step is latency-bound and reads fewer values), and so does
-    // p = 2 (one node per entity: slots measured 5 % slower).
+    // read 0.  Where they measured faster on MI355X: not in the small fused
+    // loop (its step is latency-bound and reads fewer values with additions),
+    // not at p = 2 (one node per entity: 5 % slower), and in FP64 only while one
+    // wave holds an element (n_I <= 8; at p = 12 with 16 RHS 5 % slower).
     T* Q = nullptr;
     const int64_t qlen = slot_len(c->L);
-    if (!fused && c->L.NI >= 3 && qlen * (int64_t)k < (int64_t(1) << 31)) {
+    const bool slots = !fused && c->L.NI >= 3 && (sizeof(T) == 4 || c->L.NI <= 8);
+    if (slots && qlen * (int64_t)k < (int64_t(1) << 31)) {
         rc0 = grow(c, c->ws_slots, (size_t)qlen * k * sizeof(T));
         if (rc0) return rc0;
         Q = (T*)c->ws_slots.ptr;
