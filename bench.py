@@ -489,6 +489,28 @@ def main():
     pa_ms, pa_launches, _ = ctx.profile_read(semcond.KERNEL_APPLY)
     ctx.profile_enable(False)
     kern_s = pa_ms / 1e3 / max(pa_launches, 1)
+    # the same apply with a cold last-level cache: 512 MiB written between launches
+    flush = torch.empty((512 << 20) // 8, dtype=torch.float64, device="cuda")
+    ctx.profile_enable(True)
+    for rep in range(20):
+        flush.fill_(float(rep))
+        ctx.apply(xs, out=ys)
+    pc_ms, pc_launches, _ = ctx.profile_read(semcond.KERNEL_APPLY)
+    ctx.profile_enable(False)
+    cold_s = pc_ms / 1e3 / max(pc_launches, 1)
+    # STREAM-style copy on this GPU (1 GiB read + 1 GiB written), next to the nominal peak
+    ca = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        cb.copy_(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * ca.numel() * 8 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del flush, ca, cb
 
     # Roofline of the dominant kernel of the timed solves.  Algorithmic FP64 bytes
     # (k = 1): the CG apply gathers p, r and P^-1 (it forms the direction) and
@@ -537,11 +559,13 @@ def main():
                      "kernel": dom["kernel"], "launches": dom["launches"],
                      "bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
                      "kernel_us_per_launch": dom["ms"] * 1e3 / max(dom["launches"], 1),
-                     "early_exit_launches": dom.get("early_exit_launches", 0)},
+                     "early_exit_launches": dom.get("early_exit_launches", 0),
+                     "copy_gbs_measured": copy_gbs, "frac_of_measured_copy": dom_achieved / copy_gbs},
         "apply_roofline": {"bound": "hbm", "achieved": apply_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": apply_achieved / HBM_PEAK_GBS, "kernel": "k_apply_tpt<double,7,false,false>",
                            "kernel_us": kern_s * 1e6, "gdof_s": N / kern_s / 1e9,
-                           "bytes_per_launch": apply_bytes},
+                           "bytes_per_launch": apply_bytes, "cold_cache_kernel_us": cold_s * 1e6,
+                           "cold_cache_frac": apply_bytes / cold_s / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wmesh, args.cpu_seconds)
