@@ -258,6 +258,33 @@ int semcond_solve(semcond_ctx* ctx, const void* f_nodal, void* u_nodal, int k,
                   const semcond_solve_opts* opts, semcond_solve_info* info, void* stream);
 
 /*
+ * Interior recovery (Algorithm 4, second loop) from a skeleton solution:
+ * skeleton nodes u = T u~ (Sec. 6 basis change), interior nodes
+ * u_I = (S(x)S(x)S) D^-1 (F~_I - H~_IB u~_B) per element (Sec. 4, Sec. 5).
+ *   f_nodal  device [k][N] FP64, the nodal right-hand sides of the solve
+ *   u_skel   device [N_s][k] FP64, TRANSFORMED skeleton values including those
+ *            of the Dirichlet entities (zero for homogeneous conditions), e.g.
+ *            the skel_out of semcond_solve
+ *   u_nodal  device [k][N] FP64, every node written
+ *   dtype    SEMCOND_F64 (only)
+ * Stream-ordered.  Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int semcond_recover_interior(semcond_ctx* ctx, const void* f_nodal, const void* u_skel, void* u_nodal,
+                             int k, int dtype, void* stream);
+
+/*
+ * Pre-size the context's device workspace and the host side of its
+ * convergence polls for applies, transforms, solves (any launch kind, with
+ * prescribed Dirichlet values or dual right-hand sides) and interior recovery
+ * of up to k_max right-hand sides; dtype SEMCOND_F64 covers FP64 solves,
+ * SEMCOND_F32 also FP32 and MIXED_IR ones.  Later calls with k <= k_max then
+ * allocate nothing (profiling, autotuning and semcond_update_coefficients
+ * adding per-element tables excepted).  Synchronises the device.
+ * Errors: EINVAL (k_max, dtype), ENOMEM, EDEVICE.
+ */
+int semcond_reserve(semcond_ctx* ctx, int k_max, int dtype);
+
+/*
  * Replace the Helmholtz parameter / metric coefficients of an existing context
  * (Sec. 3: d_e = (h1 h2 h3/8)(lambda, 4/h1^2, 4/h2^2, 4/h3^2); Sec. 8 notes that
  * lambda changes between time steps) and rebuild the preconditioner.  Same

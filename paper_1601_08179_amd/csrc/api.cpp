@@ -1222,6 +1222,80 @@ void semcond_solve_opts_default(semcond_solve_opts* o) {
     o->ir_restart = 0;
 }
 
+int semcond_recover_interior(semcond_ctx* c, const void* f, const void* u_skel, void* u, int k, int dtype,
+                             void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!f || !u_skel || !u) return fail(c, SEMCOND_EINVAL, "f, u_skel and u must be device pointers");
+    if (dtype != SEMCOND_F64) return fail(c, SEMCOND_EINVAL, "interior recovery is FP64 only");
+    int rc = check_k(c, k);
+    if (rc) return rc;
+    hipStream_t st = S(stream);
+    const size_t nv = (size_t)c->N_s * k;
+    rc = grow(c, c->ws_vec, nv * sizeof(double));
+    if (rc) return rc;
+    double* phys = (double*)c->ws_vec.ptr;
+    int grid;
+    double* scratch;
+    rc = scratch_for_cubes(c, &grid, &scratch);
+    if (rc) return rc;
+    // skeleton nodes: u = T u~ (Dirichlet entities keep the values given in u_skel);
+    // interior nodes: u_I = (S(x)S(x)S) D^-1 (F~_I - H~_IB u~_B) (Algorithm 4, second loop)
+    HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.S, (const double*)u_skel, phys, k, st));
+    HIPCHK(c, launch_skel_to_nodal(c->L, phys, (double*)u, c->N, k, 1, st));
+    HIPCHK(c, launch_recover_interior(c->geo, c->t64.tab, (const double*)f, c->N, (const double*)u_skel, (double*)u,
+                                      k, scratch, grid, 1, st));
+    return SEMCOND_OK;
+}
+
+int semcond_reserve(semcond_ctx* c, int k_max, int dtype) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (dtype != SEMCOND_F64 && dtype != SEMCOND_F32) return fail(c, SEMCOND_EINVAL, "dtype must be F64 or F32");
+    int rc = check_k(c, k_max);
+    if (rc) return rc;
+    const int k = k_max;
+    const size_t nv = (size_t)c->N_s * k;
+    // solve vectors (FP64 b x r p q, FP32 ones for F32 / MIXED_IR), which also
+    // cover the applies' and transforms' temporaries (at most 2 N_s k values)
+    rc = grow(c, c->ws_vec, 5 * nv * sizeof(double) + (dtype == SEMCOND_F32 ? 5 * nv * sizeof(float) : 0));
+    if (rc) return rc;
+    CgWork w;
+    rc = cg_state(c, k, 0, &w);  // both state slots, pinned activity copy
+    if (rc) return rc;
+    const int64_t qlen = slot_len(c->L);
+    if (qlen * (int64_t)k < (int64_t(1) << 31)) {
+        rc = grow(c, c->ws_slots, (size_t)qlen * k * sizeof(double));
+        if (rc) return rc;
+    }
+    int grid;
+    double* scratch;
+    rc = scratch_for_cubes(c, &grid, &scratch);
+    if (rc) return rc;
+    rc = grow(c, c->ws_lift, 2 * nv * sizeof(double));  // prescribed Dirichlet values
+    if (rc) return rc;
+    rc = grow(c, c->ws_nodal, (size_t)c->N * k * sizeof(double));  // assembled (dual) right-hand sides
+    if (rc) return rc;
+    // persistent CG: partial sums for the largest co-resident grid, barrier words
+    size_t pb = 0;
+    for (int S0 : {1, 2, 4}) {
+        if (!persist_supported(c->L.NI, S0, k)) continue;
+        const int mg = dtype == SEMCOND_F64 ? persist_max_grid<double>(c->L.NI, S0)
+                                            : std::max(persist_max_grid<double>(c->L.NI, S0),
+                                                       persist_max_grid<float>(c->L.NI, S0));
+        pb = std::max(pb, (3 * (size_t)std::max(mg, 0) * k * sizeof(double) + 255) / 256 * 256);
+    }
+    if (pb) {
+        rc = grow(c, c->ws_persist, pb + kBarWords * sizeof(unsigned));
+        if (rc) return rc;
+    }
+    // host side of the fused CG loop's convergence polls
+    for (hipEvent_t& e : c->poll_ev)
+        if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (!c->h_flags && hipHostMalloc((void**)&c->h_flags, kMaxRhs * sizeof(int), hipHostMallocCoherent) != hipSuccess)
+        return fail(c, SEMCOND_ENOMEM, "pinned host allocation failed");
+    HIPCHK(c, hipDeviceSynchronize());
+    return SEMCOND_OK;
+}
+
 int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_solve_opts* opts,
                   semcond_solve_info* info, void* stream) {
     if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");

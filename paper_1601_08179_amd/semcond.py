@@ -66,6 +66,9 @@ _SIGS = {
     "semcond_nodal_to_skeleton": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_int, ctypes.c_void_p]),
     "semcond_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
+    "semcond_recover_interior": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "semcond_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "semcond_update_coefficients": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, _c_double_p, _c_double_p,
                                                    ctypes.c_void_p]),
     "semcond_nodal_mass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -292,6 +295,29 @@ class Context:
         _check(_lib.semcond_condense_rhs(self._h, _dev(f, "f"), _dev(out, "out"), k, _dtype_code(out),
                                          _stream(stream)), self._h)
         return out
+
+    def recover_interior(self, f, u_skel, out=None, stream=None):
+        """Nodal solution from nodal right-hand sides f ((k, N) or (N,)) and the
+        TRANSFORMED skeleton solution u_skel ((N_s, k) or (N_s,)), e.g. a solve's
+        skel_out: skeleton nodes u = T u~, interior nodes recovered per element."""
+        import torch
+        k = self._k_nodal(f, "f")
+        if self._k_skel(u_skel, "u_skel") != k:
+            raise ValueError("u_skel must hold as many right-hand sides as f")
+        if f.dtype != torch.float64 or u_skel.dtype != torch.float64:
+            raise TypeError("f and u_skel must be float64")
+        if out is None:
+            out = torch.empty_like(f)
+        _check(_lib.semcond_recover_interior(self._h, _dev(f, "f"), _dev(u_skel, "u_skel"), _dev(out, "out"), k, F64,
+                                             _stream(stream)), self._h)
+        return out
+
+    def reserve(self, k_max, dtype=None):
+        """Pre-size the workspace for calls with up to k_max right-hand sides
+        (dtype torch.float32: FP32 and mixed-precision solves too)."""
+        import torch
+        code = F32 if dtype == torch.float32 else F64
+        _check(_lib.semcond_reserve(self._h, int(k_max), code), self._h)
 
     def skeleton_to_nodal(self, skel, nodal=None, stream=None):
         import torch

@@ -177,3 +177,57 @@ def test_separate_reduction_loop_residual_p10(lib, precision):
         res = fh - op.apply(u[r])
         fs = op.free_skel
         assert np.linalg.norm(res[fs]) <= 1e-9 * np.linalg.norm(fh[fs]), (r, info[r])
+
+
+@pytest.mark.parametrize("prescribed", [False, True])
+def test_recover_interior_entry_point(lib, prescribed):
+    """semcond_recover_interior on a solve's transformed skeleton output
+    reproduces the solve's nodal solution (the same kernels: bitwise), which
+    matches the oracle's direct solve with interior recovery; with prescribed
+    Dirichlet values the skeleton output carries them."""
+    import torch
+    print("case recover_interior prescribed", prescribed, flush=True)
+    ctx, op, g, free = both(MESHES["stretched3_p5"]())
+    f = W.random_skeleton_input(op.sizes["N"], k=3, seed=31)
+    skel = torch.empty((ctx.N_s, 3), dtype=torch.float64, device="cuda")
+    kw = {}
+    if prescribed:
+        kw["g"] = _t(W.random_skeleton_input(op.sizes["N"], k=3, seed=32))
+    u, info = ctx.solve(_t(f), tol=1e-13, skel_out=skel, **kw)
+    v = ctx.recover_interior(_t(f), skel)
+    assert torch.equal(u, v)
+    if not prescribed:
+        ref = _direct(op, f)
+        v = v.cpu().numpy()
+        for r in range(3):
+            assert np.abs(v[r] - ref[r]).max() <= 1e-10 * np.abs(ref[r]).max(), (r, info[r])
+
+
+def test_reserve_then_solve(lib):
+    """After semcond_reserve(k_max = 4, FP32) solves and applies with k <= 4
+    give what they give on a context without the reservation; invalid
+    arguments are rejected."""
+    import torch
+    print("case reserve", flush=True)
+    wm = MESHES["stretched3_p5"]()
+    from paper_1601_08179_amd import semcond
+    a, b = semcond.Context(wm), semcond.Context(wm)
+    a.reserve(4, torch.float32)
+    f = _t(W.random_skeleton_input(a.N, k=4, seed=33))
+    for kw in (dict(), dict(precision=lib.PREC_MIXED_IR), dict(persistent=True)):
+        ua, ia = a.solve(f, tol=1e-12, **kw)
+        ub, ib = b.solve(f, tol=1e-12, **kw)
+        # the right-hand side condensation adds edge and vertex rows with atomics:
+        # rounding may differ between the two contexts' runs
+        assert all(abs(x["iters"] - y["iters"]) <= 1 for x, y in zip(ia, ib)), kw
+        d = (ua - ub).abs().max().item() / ub.abs().max().item()
+        assert d <= 1e-10, (kw, d)
+    x = torch.randn((a.N_s, 4), dtype=torch.float64, device="cuda")
+    va, vb = a.apply(x), b.apply(x)
+    assert (va - vb).abs().max().item() <= 1e-13 * vb.abs().max().item()
+    with pytest.raises(lib.SemcondError):
+        a.reserve(0)
+    with pytest.raises(lib.SemcondError):
+        lib._check(lib._lib.semcond_reserve(a._h, 4, 7), a._h)
+    a.close()
+    b.close()
