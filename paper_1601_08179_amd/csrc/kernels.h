@@ -172,7 +172,8 @@ hipError_t launch_cg_init(const T* b, T* q0, const T* pinv, T* r, T* p, int64_t 
                           double* partials, hipStream_t st, bool keep_p = false);
 // Reduce [nparts][k] partials of `nq` quantities; mode selects the CG step logic.
 // RED_INIT_KEEP is RED_INIT for a CG that continues the direction p left by a
-// previous solve (cg_init with keep_p): beta = r.z / rho of that solve.
+// previous solve (cg_init with keep_p): beta = r.z / rho, rho being the r.z that
+// formed that solve's last direction (kept when it converged).
 enum ReduceMode { RED_INIT = 0, RED_PQ = 1, RED_RZ = 2, RED_INIT_KEEP = 3 };
 hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int k, CgState s, int mode,
                             hipStream_t st);
@@ -196,6 +197,6 @@ int fused_step_blocks(int k);
 template <typename T>
 hipError_t launch_cg_step_fused(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, const CgFuse& f,
                                 double* partials, const T* qs, int64_t qlen, const Layout& L, int face_slots,
-                          hipStream_t st);
+                                hipStream_t st);
 
 }  // namespace semcond
