@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void k_condense_rhs(Geo g, DevTab<double> tab,
 // cube and the 1D tables in LDS (the tables read at wave-uniform indices, as
 // broadcasts), lines transformed with their values in registers, and D^-1
 // applied once per interior node so that the face sums are plain products.
-// One workgroup of kRhsThreads threads per element.
+// One workgroup of kRhsThreads threads per (element, right-hand side).
 // ---------------------------------------------------------------------------
 
 constexpr int kRhsThreads = 256;
@@ -415,8 +415,9 @@ __global__ __launch_bounds__(kRhsThreads) void k_condense_rhs_t(Geo g, DevTab<do
     const double J = elem_jacobian(g, e1, e2, e3);
     rhs_tables<NI>(sm, tab, tab.St);
 #define C(kk, jj, ii) sm.C[((kk) * n + (jj)) * n + (ii)]
-    for (int r = 0; r < k; ++r) {
-        __syncthreads();  // tables stored / the previous RHS's cube read
+    {
+        const int r = blockIdx.y;  // one workgroup per (element, right-hand side)
+        __syncthreads();  // tables stored
         rhs_cube<NI>(sm, g, f, N, r, e1, e2, e3, J);
         // interior: V = D^-1 F~_I
         for (int idx = threadIdx.x; idx < NI2 * NI; idx += blockDim.x) {
@@ -502,8 +503,9 @@ __global__ __launch_bounds__(kRhsThreads) void k_recover_interior_t(Geo g, DevTa
     // forward transform by S^T first; S for the back transform afterwards
 #define C(kk, jj, ii) sm.C[((kk) * n + (jj)) * n + (ii)]
 #define UF(face, s1, s2) (fcon[face] ? 0.0 : xs[(fb[face] + (int64_t)(s1) * NI + (s2)) * k + r])
-    for (int r = 0; r < k; ++r) {
-        __syncthreads();  // the previous RHS's back transform and output done
+    {
+        const int r = blockIdx.y;  // one workgroup per (element, right-hand side)
+        __syncthreads();  // face bases and flags stored
         rhs_tables<NI>(sm, tab, tab.St);
         __syncthreads();
         rhs_cube<NI>(sm, g, f, N, r, e1, e2, e3, J);
@@ -554,8 +556,8 @@ hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const do
         switch (g.L.NI) {
 #define X(NI)                                                                                                    \
     case NI:                                                                                                     \
-        hipLaunchKernelGGL(k_condense_rhs_t<NI>, dim3((unsigned)ne), dim3(kRhsThreads), 0, st, g, tab, f, N, fhat, \
-                           k);                                                                                   \
+        hipLaunchKernelGGL(k_condense_rhs_t<NI>, dim3((unsigned)ne, (unsigned)k), dim3(kRhsThreads), 0, st, g, tab, \
+                           f, N, fhat, k);                                                                       \
         break;
             RHS_CASES(X)
 #undef X
@@ -639,8 +641,8 @@ hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, cons
         switch (g.L.NI) {
 #define X(NI)                                                                                                  \
     case NI:                                                                                                   \
-        hipLaunchKernelGGL(k_recover_interior_t<NI>, dim3((unsigned)ne), dim3(kRhsThreads), 0, st, g, tab, f, N, \
-                           xskel, u, k, keep_con);                                                              \
+        hipLaunchKernelGGL(k_recover_interior_t<NI>, dim3((unsigned)ne, (unsigned)k), dim3(kRhsThreads), 0, st, g,  \
+                           tab, f, N, xskel, u, k, keep_con);                                                   \
         break;
             RHS_CASES(X)
 #undef X
