@@ -475,7 +475,7 @@ def main():
     step_s, _ = timed(persistent=False)
     pers_s, _ = timed(persistent=True)
     # FP32 inner CG + FP64 iterative refinement
-    mixed_s, minfo = timed(precision=semcond.PREC_MIXED_IR, inner_tol=1e-5)
+    mixed_s, minfo = timed(precision=semcond.PREC_MIXED_IR)
 
     # ---- apply alone (transformed basis, back-to-back), kernel time from events ------
     xs = torch.randn(Ns, dtype=torch.float64, device="cuda")

@@ -140,7 +140,19 @@ typedef struct {
                             /*   a step failed to halve the worst residual; 1: every     */
                             /*   inner solve restarts from p = 0.  Either way a step's   */
                             /*   inner tolerance is inner_tol, or looser when a smaller  */
-                            /*   reduction (with a factor 4 margin) reaches tol          */
+                            /*   reduction (with a factor 4 margin) reaches tol, and     */
+                            /*   never below the FP32 operator's rounding level          */
+                            /*   (16 K_00 2^-24, K_00 the 1D stiffness corner entry);    */
+                            /*   an inner solve whose residual norm has not halved for   */
+                            /*   64 iterations ends its refinement step                  */
+    int deterministic;      /* 1: bit-reproducible solve (Sec. 3 assembly R in a fixed    */
+                            /*   order): the element rows of edges and vertices (and in  */
+                            /*   the applies outside the CG also of faces) go to per-side */
+                            /*   slots summed in slot order, never through atomics; the  */
+                            /*   CG runs with separate reduction launches and one launch */
+                            /*   per step.  Two solves of the same input on one device   */
+                            /*   then return the same bits.  Default 0 (atomics: results */
+                            /*   may differ in the last bits between runs)               */
 } semcond_solve_opts;
 
 #define SEMCOND_CG_STEPWISE   0
@@ -186,6 +198,19 @@ int semcond_create(const semcond_mesh* mesh, void* stream, semcond_ctx** out);
 
 /* Release a context and its device memory (synchronises the device). */
 int semcond_destroy(semcond_ctx* ctx);
+
+/*
+ * Deterministic assembly for every later semcond_apply, semcond_condense_rhs
+ * and semcond_solve on ctx (on != 0), or atomics where they measured faster
+ * (on = 0, the default).  The assembly R of Sec. 3 sums each shared skeleton
+ * node's element rows (two per face node, four per edge node, eight per
+ * vertex); deterministic mode stores every row into a per-side slot and sums
+ * the slots in a fixed order, so that results do not depend on scheduling.
+ * The slot workspace holds about 3 N_s k values; calls whose slot workspace
+ * would reach 2^31 values fail with EINVAL.  A solve is deterministic when
+ * this flag or its opts->deterministic is set.
+ */
+int semcond_set_deterministic(semcond_ctx* ctx, int on);
 
 /* Sizes: total nodes N, skeleton nodes N_s (layout length), free (unconstrained)
  * skeleton nodes, elements.  Any pointer may be NULL. */
@@ -316,6 +341,19 @@ int semcond_mass_apply(semcond_ctx* ctx, const void* in, void* out, int k, int i
  */
 int semcond_element_grads(semcond_ctx* ctx, const void* u_nodal, const void* a_nodal, void* grad,
                           int k, void* stream);
+
+/*
+ * The same element terms per right-hand side: grad[e][m][r] = -a_{e,r}^T A_m
+ * u_{e,r} (Sec. 3, eq. helmholtz_operator), m = 0..3, for the adjoint pairs
+ * (u_r, a_r) of k right-hand sides, i.e. dL_r/dd_{e,m} of per-RHS losses
+ * L_r (their sum over r is semcond_element_grads' columns 0..3; dL_r/dlambda_e
+ * = J_e grad[e][0][r]).
+ *   u_nodal, a_nodal  device [k][N] FP64
+ *   grad              device [n_e][4][k] FP64, every entry written
+ * Stream-ordered.  Errors: EINVAL.
+ */
+int semcond_element_grads_rhs(semcond_ctx* ctx, const void* u_nodal, const void* a_nodal, void* grad,
+                              int k, void* stream);
 
 /*
  * Autotuner of the CG launch (k right-hand sides of scalar type dtype): times

@@ -8,6 +8,9 @@ backward: one adjoint solve with the same operator (H_G is symmetric), a =
           interior recovered), then dL/df = M_G a, dL/dlambda_e and dL/dd_{e,1..3}
           from the library's per-element kernel (-a_e^T A_m u_e).
 All arithmetic runs in the HIP library; this module only moves tensors.
+
+The forward sets the context's coefficients to (lambda_e, d) and leaves them
+there; the backward puts them back when anything changed them in between.
 """
 
 import torch
@@ -20,13 +23,19 @@ class _Solve(torch.autograd.Function):
     def forward(fctx, f, lam_e, dmetric, ctx, tol, precision):
         dcoef = torch.zeros((ctx.n_e, 4), dtype=torch.float64)
         dcoef[:, 1:] = dmetric.detach().to("cpu", torch.float64)
-        ctx.update_coefficients(lam_e=lam_e.detach().to("cpu", torch.float64).numpy(), dcoef=dcoef.numpy())
+        lam_h = lam_e.detach().to("cpu", torch.float64).numpy().copy()
+        dcoef_h = dcoef.numpy().copy()
+        ctx.update_coefficients(lam_e=lam_h, dcoef=dcoef_h)
         u, info = ctx.solve(f.detach().contiguous(), tol=tol, precision=precision)
         fctx.ctx = ctx
         fctx.tol = tol
         fctx.precision = precision
         fctx.info = info
         fctx.devices = (lam_e.device, dmetric.device)
+        # the operator this solution belongs to: host copies of its coefficients
+        # and the context's coefficient version right after they were set
+        fctx.coef = (lam_h, dcoef_h)
+        fctx.coef_version = ctx.coef_version
         fctx.save_for_backward(u)
         return u
 
@@ -34,6 +43,11 @@ class _Solve(torch.autograd.Function):
     def backward(fctx, grad_u):
         (u,) = fctx.saved_tensors
         ctx = fctx.ctx
+        if ctx.coef_version != fctx.coef_version:
+            # another forward or a coefficient update came in between: the
+            # adjoint must use the operator of this forward
+            ctx.update_coefficients(lam_e=fctx.coef[0], dcoef=fctx.coef[1])
+            fctx.coef_version = ctx.coef_version
         a, _ = ctx.solve(grad_u.contiguous(), tol=fctx.tol, precision=fctx.precision, rhs_dual=True)
         g = ctx.element_grads(u, a)
         grad_f = ctx.mass_apply(a)

@@ -84,9 +84,21 @@ struct semcond_ctx {
     double prof_ms[2] = {0.0, 0.0};
     int64_t prof_launches[2] = {0, 0};
     int64_t prof_iters = 0;
+    // deterministic assembly: every apply, condensation and CG loop sums the
+    // element rows of shared nodes through per-side slots in a fixed order
+    bool det = false;         // set by semcond_set_deterministic (applies, condensation, solves)
+    bool det_active = false;  // in force for the current call
 };
 
 namespace {
+
+// Deterministic assembly in force for the duration of one library call.
+struct DetScope {
+    semcond_ctx* c;
+    bool old;
+    DetScope(semcond_ctx* ctx, bool on);
+    ~DetScope();
+};
 
 int fail(semcond_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg;
@@ -154,6 +166,9 @@ int upload_tables(semcond_ctx* c, DevTables<T>& d) {
     d.tab.K0p = (T)t.K0p;
     return SEMCOND_OK;
 }
+
+DetScope::DetScope(semcond_ctx* ctx, bool on) : c(ctx), old(ctx->det_active) { c->det_active = on; }
+DetScope::~DetScope() { c->det_active = old; }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -246,7 +261,24 @@ template <typename T>
 int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, double* energy, hipStream_t st,
                       bool v_is_zero = false, const T* dir_r = nullptr, const double* dir_beta = nullptr,
                       int read_con = 0, const CgFuse* fz = nullptr, const int* act = nullptr,
-                      T* slots = nullptr) {
+                      T* slots = nullptr, int face_slots = cg_face_slots<T>()) {
+    if (c->det_active && !slots && !dir_r) {
+        // deterministic plain apply: every row into its per-side slot, then the
+        // fixed-order slot sums written into v (all entries)
+        const int64_t qlen = slot_len(c->L);
+        if (qlen * (int64_t)k >= (int64_t(1) << 31))
+            return fail(c, SEMCOND_EINVAL, "deterministic apply: slot workspace beyond 2^31 entries");
+        int rc = grow(c, c->ws_slots, (size_t)qlen * k * sizeof(T));
+        if (rc) return rc;
+        T* Q = (T*)c->ws_slots.ptr;
+        HIPCHK(c, launch_fill<T>(Q, qlen * k, (T)0, st));
+        rc = apply_transformed<T>(c, u, v, k, lay, energy, st, true, nullptr, nullptr, read_con, nullptr, nullptr,
+                                  Q, 1);
+        if (rc) return rc;
+        HIPCHK(c, launch_slot_sum<T>(c->L, Q, qlen, v, k, lay == RHS_MAJOR ? 1u : (uint32_t)k,
+                                     lay == RHS_MAJOR ? (uint32_t)c->N_s : 1u, st));
+        return SEMCOND_OK;
+    }
     if (!v_is_zero) HIPCHK(c, launch_fill<T>(v, c->N_s * k, (T)0, st));
     ApplyArgs<T> a = apply_args<T>(c);
     a.u = u;
@@ -265,10 +297,10 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, do
     }
     a.act = act;
     if (slots) {
-        if (lay != RHS_MAJOR || !v_is_zero) return fail(c, SEMCOND_EINVAL, "slot output needs RHS-major vectors");
+        if (!v_is_zero) return fail(c, SEMCOND_EINVAL, "slot output needs a zeroed v");
         a.slots = slots;
         a.qlen = slot_len(c->L);
-        a.face_slots = cg_face_slots<T>();
+        a.face_slots = face_slots;
     }
     if (c->prof) {
         int rc = profile_begin(c, SEMCOND_KERNEL_APPLY, st);
@@ -325,8 +357,20 @@ int condense_rhs64(semcond_ctx* c, const double* f, double* fhat, int k, hipStre
     double* scratch;
     int rc = scratch_for_cubes(c, &grid, &scratch);
     if (rc) return rc;
-    HIPCHK(c, launch_fill<double>(fhat, c->N_s * k, 0.0, st));
-    HIPCHK(c, launch_condense_rhs(c->geo, c->t64.tab, f, c->N, fhat, k, scratch, grid, st));
+    double* slots = nullptr;
+    if (c->det_active) {
+        // deterministic: rows into per-side slots, summed in a fixed order
+        const int64_t qlen = slot_len(c->L);
+        if (qlen * (int64_t)k >= (int64_t(1) << 31))
+            return fail(c, SEMCOND_EINVAL, "deterministic condensation: slot workspace beyond 2^31 entries");
+        rc = grow(c, c->ws_slots, (size_t)qlen * k * sizeof(double));
+        if (rc) return rc;
+        slots = (double*)c->ws_slots.ptr;
+        HIPCHK(c, launch_fill<double>(slots, qlen * k, 0.0, st));
+    } else {
+        HIPCHK(c, launch_fill<double>(fhat, c->N_s * k, 0.0, st));
+    }
+    HIPCHK(c, launch_condense_rhs(c->geo, c->t64.tab, f, c->N, fhat, k, scratch, grid, slots, st));
     return SEMCOND_OK;
 }
 
@@ -334,15 +378,17 @@ struct CgWork {
     CgState s;
     double* partials;  // [3][vec_blocks(k)][k] (room for [3][kVecBlocks][k])
     double* energy;    // [n_e][k]
-    double* rho1;      // second slots of rho and active (fused loop, odd iterations)
-    int* act1;
+    double* rho1;      // second slots of rho, active and the stagnation state
+    int* act1;         // (fused loop, odd iterations)
+    double* rrb1;
+    int* stall1;
 };
 
 // Device state layout inside ws_state: two independent CG states (slot 0 for
 // the CG iteration, slot 1 for the outer refinement loop of MIXED_IR).
 int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
-    const size_t nd = 7 * (size_t)k + 1;               // rho pq alpha beta rr bb (6k) + rho slot 1 + tol2
-    const size_t ni = 4 * (size_t)k;                    // active iters status + active slot 1
+    const size_t nd = 9 * (size_t)k + 1;  // rho pq alpha beta rr bb (6k), rho slot 1, rrb (2 slots), tol2
+    const size_t ni = 6 * (size_t)k;      // active iters status, active slot 1, stall (2 slots)
     const size_t np = 3 * (size_t)kVecBlocks * k;
     const size_t ne = (size_t)c->n_e * k;
     const size_t one = ((nd + np + ne) * sizeof(double) + ni * sizeof(int) + 255) / 256 * 256;
@@ -355,8 +401,11 @@ int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
     w->s.beta = d + 3 * k;
     w->s.rr = d + 4 * k;
     w->s.bb = d + 5 * k;
-    w->s.tol2 = d + 7 * k;
     w->rho1 = d + 6 * k;
+    w->s.rrb = d + 7 * k;
+    w->rrb1 = d + 8 * k;
+    w->s.tol2 = d + 9 * k;
+    w->s.window = 0;
     w->partials = d + nd;
     w->energy = w->partials + np;
     int* ip = (int*)(w->energy + ne);
@@ -364,6 +413,8 @@ int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
     w->s.iters = ip + k;
     w->s.status = ip + 2 * k;
     w->act1 = ip + 3 * k;
+    w->s.stall = ip + 4 * k;
+    w->stall1 = ip + 5 * k;
     if (c->h_active_cap < 3 * k) {
         if (c->h_active) hipHostFree(c->h_active);
         c->h_active = nullptr;
@@ -399,6 +450,11 @@ int read_state(semcond_ctx* c, const CgWork& w, int k, CgHost* h, hipStream_t st
 // consuming kernels.
 constexpr int64_t kFusedMaxItems = 16384;
 
+// Iterations without the residual norm halving after which an inner FP32
+// solve of the iterative refinement stops (its outer step then recomputes
+// the FP64 residual).
+constexpr int kInnerStallWindow = 64;
+
 // Views of the CG state for iteration parity ph (slot ph: this iteration's
 // rho / active; slot 1 - ph: the previous iteration's); the apply's partial
 // sums are set by the caller from the second iteration on.
@@ -406,6 +462,8 @@ CgFuse fuse_view(const CgWork& w, int k, int ph, int64_t n_e) {
     CgFuse f = {};
     double* rho[2] = {w.s.rho, w.rho1};
     int* act[2] = {w.s.active, w.act1};
+    double* rrb[2] = {w.s.rrb, w.rrb1};
+    int* stall[2] = {w.s.stall, w.stall1};
     f.part = w.partials;
     f.nsb = fused_step_blocks(k);
     f.energy = w.energy;
@@ -422,6 +480,11 @@ CgFuse fuse_view(const CgWork& w, int k, int ph, int64_t n_e) {
     f.tol2 = w.s.tol2;
     f.pq = w.s.pq;
     f.alpha = w.s.alpha;
+    f.rrb_prev = rrb[1 - ph];
+    f.rrb = rrb[ph];
+    f.stall_prev = stall[1 - ph];
+    f.stall = stall[ph];
+    f.window = w.s.window;
     f.host_act = nullptr;
     f.epoch2 = 0;
     return f;
@@ -464,7 +527,7 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     // Small problems complete both reductions inside the kernels that consume
     // them (two launches per iteration instead of four); the redundant reads
     // of the partial sums grow with n_e k.
-    const bool fused = c->n_e * (int64_t)k <= kFusedMaxItems;
+    const bool fused = !c->det_active && c->n_e * (int64_t)k <= kFusedMaxItems;
     // In the loop with separate reductions the applies store per-side slots of
     // edges and vertices (faces too in FP32; plain stores, no atomics) that the
     // step sums in a fixed order; cleared here, so that slots no element writes
@@ -474,7 +537,10 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     // wave holds an element (n_I <= 8; at p = 12 with 16 RHS 5 % slower).
     T* Q = nullptr;
     const int64_t qlen = slot_len(c->L);
-    const bool slots = !fused && c->L.NI >= 3 && (sizeof(T) == 4 || c->L.NI <= 8);
+    // (deterministic mode: always, so that no edge or vertex row is added by atomics)
+    const bool slots = c->det_active || (!fused && c->L.NI >= 3 && (sizeof(T) == 4 || c->L.NI <= 8));
+    if (c->det_active && qlen * (int64_t)k >= (int64_t(1) << 31))
+        return fail(c, SEMCOND_EINVAL, "deterministic solve: slot workspace beyond 2^31 entries");
     if (slots && qlen * (int64_t)k < (int64_t(1) << 31)) {
         rc0 = grow(c, c->ws_slots, (size_t)qlen * k * sizeof(T));
         if (rc0) return rc0;
@@ -552,11 +618,15 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
         if (odd) {
             v.rho = w.rho1;
             v.active = w.act1;
+            v.rrb = w.rrb1;
+            v.stall = w.stall1;
         }
         HIPCHK(c, launch_cg_reduce(w.partials, fused_step_blocks(k), 2, k, v, RED_RZ, st));
         if (odd) {
             HIPCHK(c, hipMemcpyAsync(w.s.rho, w.rho1, k * sizeof(double), hipMemcpyDeviceToDevice, st));
             HIPCHK(c, hipMemcpyAsync(w.s.active, w.act1, k * sizeof(int), hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipMemcpyAsync(w.s.rrb, w.rrb1, k * sizeof(double), hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, hipMemcpyAsync(w.s.stall, w.stall1, k * sizeof(int), hipMemcpyDeviceToDevice, st));
         }
     }
     return SEMCOND_OK;
@@ -577,8 +647,13 @@ int set_coefficients(semcond_ctx* c, double lambda, const double* lambda_e, cons
     c->geo.lam = lambda;
     c->geo.lam_e = lambda_e ? c->d_lam_e : nullptr;
     c->geo.dcoef = dcoef_e ? c->d_dcoef : nullptr;
-    HIPCHK(c, launch_fill<double>(c->d_diag, c->N_s, 0.0, st));
-    HIPCHK(c, launch_precond_diag(c->geo, c->t64.tab, c->d_diag, st));
+    // the diagonal's rows of shared nodes are summed through per-side slots in
+    // a fixed order, so every context of a mesh has bitwise the same diagonal
+    const int64_t qlen = slot_len(c->L);
+    int rc = grow(c, c->ws_slots, (size_t)qlen * sizeof(double));
+    if (rc) return rc;
+    HIPCHK(c, launch_fill<double>((double*)c->ws_slots.ptr, qlen, 0.0, st));
+    HIPCHK(c, launch_precond_diag(c->geo, c->t64.tab, c->d_diag, (double*)c->ws_slots.ptr, st));
     HIPCHK(c, launch_precond_invert<double>(c->L, c->d_diag, c->d_pinv64, st));
     HIPCHK(c, launch_precond_invert<float>(c->L, c->d_diag, c->d_pinv32, st));
     return SEMCOND_OK;
@@ -671,6 +746,9 @@ int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, in
     P.active = w.s.active;
     P.iters = w.s.iters;
     P.status = w.s.status;
+    P.rrb = w.s.rrb;
+    P.stall = w.s.stall;
+    P.window = w.s.window;
     P.tol2 = tol * tol;
     P.max_iter = max_iter;
     P.bar = bar;
@@ -734,7 +812,8 @@ int run_cg_any(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double
                bool x0_given, int mode, CgWork& w, hipStream_t st, bool keep_dir = false) {
     int S = 0, G = 0;
     bool use = false;
-    if (mode != SEMCOND_CG_STEPWISE && persist_supported(c->L.NI, 1, k)) {
+    // (the persistent kernel scatters with atomics: never in deterministic mode)
+    if (mode != SEMCOND_CG_STEPWISE && !c->det_active && persist_supported(c->L.NI, 1, k)) {
         auto it = c->tuned.find({k, dtype_of<T>()});
         if (it != c->tuned.end() && it->second.first > 0) {
             S = it->second.first;
@@ -1031,6 +1110,7 @@ int semcond_apply(semcond_ctx* c, const void* u, void* v, int k, int dtype, int 
     if (rc) return rc;
     if (basis != SEMCOND_PHYSICAL && basis != SEMCOND_TRANSFORMED) return fail(c, SEMCOND_EINVAL, "bad basis");
     hipStream_t st = S(stream);
+    DetScope det(c, c->det);
     const size_t es = dtype == SEMCOND_F64 ? sizeof(double) : sizeof(float);
     if (basis == SEMCOND_TRANSFORMED && k == 1) {
         if (dtype == SEMCOND_F64) return apply_transformed<double>(c, (const double*)u, (double*)v, k, NODE_MAJOR, nullptr, st);
@@ -1079,6 +1159,7 @@ int semcond_condense_rhs(semcond_ctx* c, const void* f, void* fhat, int k, int d
     if (!rc) rc = check_k(c, k);
     if (rc) return rc;
     hipStream_t st = S(stream);
+    DetScope det(c, c->det);
     if (dtype == SEMCOND_F64) return condense_rhs64(c, (const double*)f, (double*)fhat, k, st);
     rc = grow(c, c->ws_vec, sizeof(double) * (size_t)c->N_s * k);
     if (rc) return rc;
@@ -1201,7 +1282,16 @@ int semcond_element_grads(semcond_ctx* c, const void* u, const void* a, void* gr
     if (!u || !a || !grad) return fail(c, SEMCOND_EINVAL, "NULL pointer");
     if (k < 1 || k > 256) return fail(c, SEMCOND_EINVAL, "k must be in [1, 256]");
     HIPCHK(c, launch_element_grads(c->geo, c->t64.tab.w, c->t64.K, (const double*)u, (const double*)a, c->N, k,
-                                   (double*)grad, S(stream)));
+                                   (double*)grad, false, S(stream)));
+    return SEMCOND_OK;
+}
+
+int semcond_element_grads_rhs(semcond_ctx* c, const void* u, const void* a, void* grad, int k, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!u || !a || !grad) return fail(c, SEMCOND_EINVAL, "NULL pointer");
+    if (k < 1 || k > 256) return fail(c, SEMCOND_EINVAL, "k must be in [1, 256]");
+    HIPCHK(c, launch_element_grads(c->geo, c->t64.tab.w, c->t64.K, (const double*)u, (const double*)a, c->N, k,
+                                   (double*)grad, true, S(stream)));
     return SEMCOND_OK;
 }
 
@@ -1220,6 +1310,13 @@ void semcond_solve_opts_default(semcond_solve_opts* o) {
     o->persistent = SEMCOND_CG_AUTO;
     o->g_dirichlet = nullptr;
     o->ir_restart = 0;
+    o->deterministic = 0;
+}
+
+int semcond_set_deterministic(semcond_ctx* c, int on) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    c->det = on != 0;
+    return SEMCOND_OK;
 }
 
 int semcond_recover_interior(semcond_ctx* c, const void* f, const void* u_skel, void* u, int k, int dtype,
@@ -1313,6 +1410,7 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
     if (o.precision == SEMCOND_PREC_MIXED_IR && (!(o.inner_tol > 0.0 && o.inner_tol < 1.0) || o.max_outer < 1))
         return fail(c, SEMCOND_EINVAL, "MIXED_IR needs 0 < inner_tol < 1 and max_outer >= 1");
     hipStream_t st = S(stream);
+    DetScope det(c, c->det || o.deterministic != 0);
     const int64_t Ns = c->N_s;
     const size_t nv = (size_t)Ns * k;
     if (o.rhs_dual) {
@@ -1462,15 +1560,22 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
                     worst = std::max(worst, relres[i]);
                     if (relres[i] > 0.0) need = std::min(need, 0.25 * o.tol / relres[i]);
                 }
-            const double run_tol = std::max(o.inner_tol, need);
+            // ... but never below what the FP32 operator can reach: its face rows
+            // cancel K_00 against the 1D Schur value 1/2 (Sec. 6 transformed
+            // primary part), so its rounding error relative to the residual is
+            // about 2 K_00 FP32 units; a margin of 8 on top.
+            const double fp32_floor = 8.0 * 0x1p-24 * 2.0 * c->t.K00;
+            const double run_tol = std::max(std::max(o.inner_tol, need), fp32_floor);
             // The FP32 CG continues its search direction across refinement steps
             // (only the residual is replaced by the FP64 one) unless restarts are
             // asked for, or the last step did not halve the worst residual.
             keep = step > 0 && !o.ir_restart && worst < 0.5 * prev_worst;
             prev_worst = worst;
             HIPCHK(c, launch_convert_masked(r, r32, nv, k, wo.s.active, st));
+            w.s.window = kInnerStallWindow;  // an inner solve that stops halving its residual ends
             rc = run_cg_any<float>(c, r32, x32, b32, p32, q32, k, run_tol, o.max_iter, o.check_every, false,
                                    o.persistent, w, st, keep);
+            w.s.window = 0;
             if (rc) return rc;
             CgHost hi;
             rc = read_state(c, w, k, &hi, st);

@@ -580,8 +580,9 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
 
     auto item = [&](const int64_t e, const bool live, const uint32_t r) __attribute__((always_inline)) {
         // a stopped right-hand side (the same in the whole workgroup); only the CG
-        // loop with separate reductions passes activity flags and slots
-        constexpr bool SL = DIR && !FZ;
+        // loop with separate reductions passes activity flags, and slots only it
+        // and the deterministic plain applies
+        constexpr bool SL = !FZ;
         if constexpr (SL) {
             if (A.act && !A.act[r]) return;
         }

@@ -65,16 +65,39 @@ __device__ inline void block_sums(const double* v, int64_t qstride, int64_t n, i
 // act_prev) and, when `store`, writes this iteration's slot and the per-RHS
 // counters.  Returns beta (0 for a converged or stopped RHS); *still receives
 // whether the RHS keeps iterating.
+// Stagnation test of an inner solve of the iterative refinement: progress means
+// r.r below a quarter of its value at the last progress (the residual norm
+// halved), which resets the count; a right-hand side whose residual has not
+// halved for `window` iterations stops (window <= 0: never).  FP32 recurrences
+// cannot reduce the residual much below the operator's own rounding level,
+// so without this test an inner tolerance below that level would keep the
+// inner solve running to its iteration limit.
+__device__ inline bool cg_stalled(double rr, double rrb_old, int stall_old, int window, double* rrb_new,
+                                  int* stall_new) {
+    if (rr < 0.25 * rrb_old) {
+        *rrb_new = rr;
+        *stall_new = 0;
+        return false;
+    }
+    *rrb_new = rrb_old;
+    *stall_new = stall_old + 1;
+    return window > 0 && *stall_new >= window;
+}
+
 __device__ inline double cg_rz_complete(const CgFuse& f, int r, double rz, double rr, bool store, bool* still) {
     const int act = f.act_prev[r];
     const double rho = f.rho_prev[r];
     double beta = 0.0, rho_new = rho;
     int act_new = act, status = 0;
+    double rrb = f.rrb_prev[r];
+    int stall = f.stall_prev[r];
     if (act) {
         if (!isfinite(rr) || !isfinite(rz)) {
             status = -5;
             act_new = 0;
         } else if (rr <= f.tol2[0] * f.bb[r]) {
+            act_new = 0;
+        } else if (cg_stalled(rr, f.rrb_prev[r], f.stall_prev[r], f.window, &rrb, &stall)) {
             act_new = 0;
         } else {
             beta = rz / rho;
@@ -91,6 +114,8 @@ __device__ inline double cg_rz_complete(const CgFuse& f, int r, double rz, doubl
         f.rho[r] = rho_new;
         f.act[r] = act_new;
         f.beta[r] = beta;
+        f.rrb[r] = rrb;
+        f.stall[r] = stall;
         if (f.host_act) f.host_act[r] = f.epoch2 + act_new;
     }
     return beta;
@@ -102,6 +127,8 @@ __device__ inline void cg_carry_stopped(const CgFuse& f, int r) {
     f.rho[r] = f.rho_prev[r];
     f.act[r] = 0;
     f.beta[r] = 0.0;
+    f.rrb[r] = f.rrb_prev[r];
+    f.stall[r] = f.stall_prev[r];
     if (f.host_act) f.host_act[r] = f.epoch2;
 }
 

@@ -20,6 +20,11 @@ struct CgState {
     int* active;     // 1 while iterating
     int* iters;
     int* status;
+    // Stagnation exit (window > 0, inner solves of the refinement): rrb holds
+    // r.r at the last time the residual norm halved, stall the iterations since.
+    double* rrb;
+    int* stall;
+    int window;
 };
 
 // Per-iteration view of the CG state for kernels that complete a reduction of
@@ -45,6 +50,12 @@ struct CgFuse {
     const double* tol2;
     double* pq;
     double* alpha;
+    // stagnation state with the same two slots as rho (see CgState)
+    const double* rrb_prev;
+    double* rrb;
+    const int* stall_prev;
+    int* stall;
+    int window;
     int* host_act;  // nullable: pinned host copy of act as epoch2 + act, written with it
     int epoch2;     // twice the number of the solve call (flags of earlier calls never match)
 };
@@ -95,8 +106,17 @@ hipError_t launch_apply_tpt(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t s
 template <typename T>
 hipError_t launch_transform(const Layout& L, const T* A, const T* in, T* out, int k, hipStream_t st);
 
-// diag(R H~^_L R^T) accumulated into diag (FP64, zeroed first).
-hipError_t launch_precond_diag(const Geo& g, const DevTab<double>& tab, double* diag, hipStream_t st);
+// Assembly R from per-side slots (layout.h), RHS-major [k][qlen]: out(node, r)
+// at node * ns + r * rs, every node written.
+template <typename T>
+hipError_t launch_slot_sum(const Layout& L, const T* slots, int64_t qlen, T* out, int k, uint32_t ns, uint32_t rs,
+                           hipStream_t st);
+
+// diag(R H~^_L R^T) into diag (FP64).  slots (nullable, slot_len doubles,
+// zeroed): element rows go to per-side slots summed in a fixed order, so the
+// result does not depend on scheduling; without, diag (zeroed first)
+// accumulates them with atomics.
+hipError_t launch_precond_diag(const Geo& g, const DevTab<double>& tab, double* diag, double* slots, hipStream_t st);
 // pinv[s] = 1/diag[s] on free slots, 0 on constrained ones (type T).
 template <typename T>
 hipError_t launch_precond_invert(const Layout& L, const double* diag, T* pinv, hipStream_t st);
@@ -104,8 +124,14 @@ hipError_t launch_precond_invert(const Layout& L, const double* diag, T* pinv, h
 // Condensed transformed RHS, accumulated into fhat (zeroed first).  The element
 // cube of (p+1)^3 values lives in LDS when it fits, else in `scratch`
 // (grid x (p+1)^3 doubles, grid = number of workgroups used).
+// slots (nullable, k * slot_len doubles, zeroed): rows stored per side and
+// summed in a fixed order into fhat (every entry written); else fhat (zeroed
+// first) accumulates them with atomics.
 hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
-                               double* fhat, int k, double* scratch, int grid, hipStream_t st);
+                               double* fhat, int k, double* scratch, int grid, double* slots, hipStream_t st);
+hipError_t launch_condense_rhs_body(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
+                                    double* fhat, int k, double* scratch, int grid, double* slots, int64_t qlen,
+                                    hipStream_t st);
 int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch);
 
 // Interior recovery (Algorithm 4, second loop): u_I = (S(x)S(x)S) D^-1 (F~_I - H~_IB u~_B),
@@ -134,9 +160,10 @@ hipError_t launch_nodal_mass(const Geo& g, const double* w, double* mass, int64_
 // out = in * M_G (or in / M_G when inverse), nodal [k][N].
 hipError_t launch_mass_apply(const Geo& g, const double* w, const double* in, double* out, int64_t N, int k,
                              int inverse, hipStream_t st);
-// grad[e][m] = -sum_r a_e^T A_m u_e (m = 0..3), grad[e][4] = J_e grad[e][0]  ([n_e][5]).
+// grad[e][m] = -sum_r a_e^T A_m u_e (m = 0..3), grad[e][4] = J_e grad[e][0]  ([n_e][5]);
+// per_rhs: grad[e][m][r] = -a_{e,r}^T A_m u_{e,r}  ([n_e][4][k]).
 hipError_t launch_element_grads(const Geo& g, const double* w, const double* K, const double* u, const double* a,
-                                int64_t N, int k, double* grad, hipStream_t st);
+                                int64_t N, int k, double* grad, bool per_rhs, hipStream_t st);
 
 template <typename T>
 hipError_t launch_fill(T* x, int64_t n, T val, hipStream_t st);

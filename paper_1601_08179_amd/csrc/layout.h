@@ -93,6 +93,17 @@ __host__ __device__ inline uint32_t slot_addr(const Layout& L, uint32_t node, in
     if (node < oV) return 2 * Ns + (uint32_t)(slot - 2) * nE + (node - oEx);
     return 2 * Ns + 2 * nE + (uint32_t)(slot - 2) * (Ns - oV) + (node - oV);
 }
+// Slot of element entity `id` (the numbering of element_entity below) for the
+// element's side of that entity.
+__host__ __device__ inline int entity_slot(int id) {
+    if (id < 6) return 1 - (id & 1);
+    if (id < 18) {
+        const int q = (id - 6) & 3;
+        return (1 - (q & 1)) + 2 * (1 - (q >> 1));
+    }
+    const int q = id - 18;
+    return (1 - (q & 1)) + 2 * (1 - ((q >> 1) & 1)) + 4 * (1 - (q >> 2));
+}
 // Assembled value of a node: its slots summed in slot order (faces: only with
 // face slots; otherwise a face node's value is the atomic sum in q).
 template <typename T>

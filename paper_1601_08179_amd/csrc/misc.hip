@@ -98,6 +98,37 @@ template hipError_t launch_transform<float>(const Layout&, const float*, const f
                                             hipStream_t);
 
 // ---------------------------------------------------------------------------
+// Assembly R from per-side slots (layout.h): out(node, r) = the node's slots of
+// right-hand side r summed in slot order, written at node * ns + r * rs.
+// Slots that no element wrote hold 0, so constrained nodes receive 0.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_slot_sum(Layout L, const T* __restrict__ qs, int64_t qlen, T* __restrict__ out, int k, uint32_t ns,
+                           uint32_t rs) {
+    const int64_t n_all = L.Ns * k;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_all; i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(i / L.Ns);
+        const uint32_t node = (uint32_t)(i - (int64_t)r * L.Ns);
+        out[(int64_t)node * ns + (int64_t)r * rs] = slot_sum(L, qs + (int64_t)r * qlen, node);
+    }
+}
+
+template <typename T>
+hipError_t launch_slot_sum(const Layout& L, const T* slots, int64_t qlen, T* out, int k, uint32_t ns, uint32_t rs,
+                           hipStream_t st) {
+    int64_t b = (L.Ns * k + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_slot_sum<T>, dim3((unsigned)b), dim3(256), 0, st, L, slots, qlen, out, k, ns, rs);
+    return hipGetLastError();
+}
+template hipError_t launch_slot_sum<double>(const Layout&, const double*, int64_t, double*, int, uint32_t, uint32_t,
+                                            hipStream_t);
+template hipError_t launch_slot_sum<float>(const Layout&, const float*, int64_t, float*, int, uint32_t, uint32_t,
+                                           hipStream_t);
+
+// ---------------------------------------------------------------------------
 // Preconditioner: diagonal of the transformed condensed operator (Sec. 8: the
 // block preconditioner is diagonal in the transformed system).  Per element:
 //   face w (k,j): d0 M00 + d1 K00 + d2 M00 L_j + d3 M00 L_k - d1^2 sum_i a_i^2 / D_kji
@@ -106,7 +137,8 @@ template hipError_t launch_transform<float>(const Layout&, const float*, const f
 //   vertex: d0 M00^3 + (d1+d2+d3) M00^2 K00
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_precond_diag(Geo g, DevTab<double> tab, double* __restrict__ diag) {
+__global__ __launch_bounds__(256) void k_precond_diag(Geo g, DevTab<double> tab, double* __restrict__ diag,
+                                                      double* __restrict__ slots) {
     const Layout& L = g.L;
     const int NI = L.NI, NI2 = NI * NI;
     const int64_t e = blockIdx.x;
@@ -158,13 +190,19 @@ __global__ __launch_bounds__(256) void k_precond_diag(Geo g, DevTab<double> tab,
         int64_t base;
         bool con;
         element_entity(L, e1, e2, e3, ent, &base, &con);
-        if (!con) atomic_add(&diag[base + loc], val);
+        if (con) continue;
+        if (slots)
+            slots[slot_addr(L, (uint32_t)(base + loc), entity_slot(ent))] = val;
+        else
+            atomic_add(&diag[base + loc], val);
     }
 }
 
-hipError_t launch_precond_diag(const Geo& g, const DevTab<double>& tab, double* diag, hipStream_t st) {
+hipError_t launch_precond_diag(const Geo& g, const DevTab<double>& tab, double* diag, double* slots,
+                               hipStream_t st) {
     const int64_t ne = (int64_t)g.L.n1 * g.L.n2 * g.L.n3;
-    hipLaunchKernelGGL(k_precond_diag, dim3((unsigned)ne), dim3(256), 0, st, g, tab, diag);
+    hipLaunchKernelGGL(k_precond_diag, dim3((unsigned)ne), dim3(256), 0, st, g, tab, diag, slots);
+    if (slots) return launch_slot_sum<double>(g.L, slots, slot_len(g.L), diag, 1, 1, 1, st);
     return hipGetLastError();
 }
 
@@ -250,8 +288,8 @@ __device__ void cube_transformed_rhs(double* cube, const Geo& g, const DevTab<do
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_condense_rhs(Geo g, DevTab<double> tab, const double* __restrict__ f,
-                                                      int64_t N,
-                                                      double* __restrict__ fhat, int k, double* scratch) {
+                                                      int64_t N, double* __restrict__ fhat, int k, double* scratch,
+                                                      double* __restrict__ slots, int64_t qlen) {
     extern __shared__ double cube_lds[];
     const Layout& L = g.L;
     const int p = L.p, n = p + 1, NI = L.NI, NI2 = NI * NI;
@@ -316,7 +354,11 @@ __global__ __launch_bounds__(256) void k_condense_rhs(Geo g, DevTab<double> tab,
                 int64_t base;
                 bool con;
                 element_entity(L, e1, e2, e3, ent, &base, &con);
-                if (!con) atomic_add(&fhat[(base + loc) * k + r], val);
+                if (con) continue;
+                if (slots)
+                    slots[(int64_t)r * qlen + slot_addr(L, (uint32_t)(base + loc), entity_slot(ent))] = val;
+                else
+                    atomic_add(&fhat[(base + loc) * k + r], val);
             }
             __syncthreads();
         }
@@ -402,7 +444,8 @@ __device__ void rhs_cube(RhsSmem<NI>& sm, const Geo& g, const double* __restrict
 template <int NI>
 __global__ __launch_bounds__(kRhsThreads) void k_condense_rhs_t(Geo g, DevTab<double> tab,
                                                                 const double* __restrict__ f, int64_t N,
-                                                                double* __restrict__ fhat, int k) {
+                                                                double* __restrict__ fhat, int k,
+                                                                double* __restrict__ slots, int64_t qlen) {
     constexpr int n = NI + 2, p = NI + 1, NI2 = NI * NI;
     constexpr int nslot = 6 * NI2 + 12 * NI + 8;
     __shared__ RhsSmem<NI> sm;
@@ -472,7 +515,11 @@ __global__ __launch_bounds__(kRhsThreads) void k_condense_rhs_t(Geo g, DevTab<do
             int64_t base;
             bool con;
             element_entity(L, e1, e2, e3, ent, &base, &con);
-            if (!con) atomic_add(&fhat[(base + loc) * k + r], val);
+            if (con) continue;
+            if (slots)
+                slots[(int64_t)r * qlen + slot_addr(L, (uint32_t)(base + loc), entity_slot(ent))] = val;
+            else
+                atomic_add(&fhat[(base + loc) * k + r], val);
         }
     }
 #undef C
@@ -548,7 +595,16 @@ int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch) {
 #define RHS_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
 
 hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
-                               double* fhat, int k, double* scratch, int grid, hipStream_t st) {
+                               double* fhat, int k, double* scratch, int grid, double* slots, hipStream_t st) {
+    const int64_t qlen = slot_len(g.L);
+    hipError_t e = launch_condense_rhs_body(g, tab, f, N, fhat, k, scratch, grid, slots, qlen, st);
+    if (e != hipSuccess || !slots) return e;
+    return launch_slot_sum<double>(g.L, slots, qlen, fhat, k, (uint32_t)k, 1, st);
+}
+
+hipError_t launch_condense_rhs_body(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
+                                    double* fhat, int k, double* scratch, int grid, double* slots, int64_t qlen,
+                                    hipStream_t st) {
     if (g.L.NI <= 15) {
         const int64_t ne = (int64_t)g.L.n1 * g.L.n2 * g.L.n3;
         if (ne <= 0) return hipSuccess;
@@ -557,7 +613,7 @@ hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const do
 #define X(NI)                                                                                                    \
     case NI:                                                                                                     \
         hipLaunchKernelGGL(k_condense_rhs_t<NI>, dim3((unsigned)ne, (unsigned)k), dim3(kRhsThreads), 0, st, g, tab, \
-                           f, N, fhat, k);                                                                       \
+                           f, N, fhat, k, slots, qlen);                                                          \
         break;
             RHS_CASES(X)
 #undef X
@@ -566,7 +622,7 @@ hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const do
     }
     const int n = g.L.p + 1;
     const size_t shm = scratch ? 0 : (size_t)n * n * n * sizeof(double);
-    hipLaunchKernelGGL(k_condense_rhs, dim3(grid), dim3(256), shm, st, g, tab, f, N, fhat, k, scratch);
+    hipLaunchKernelGGL(k_condense_rhs, dim3(grid), dim3(256), shm, st, g, tab, f, N, fhat, k, scratch, slots, qlen);
     return hipGetLastError();
 }
 
@@ -870,14 +926,18 @@ __global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __re
     const int t = threadIdx.x, r = t % k, j = t / k, npb = blockDim.x / k;
     constexpr int U = 16;
     // per-RHS state read before anything is written, so that no load waits on a store
-    int act = 0, its = 0;
-    double rho = 0.0, bb = 0.0, tol2 = 0.0;
+    int act = 0, its = 0, stall = 0;
+    double rho = 0.0, bb = 0.0, tol2 = 0.0, rrb = 0.0;
     if (t < k) {
         act = s.active[t];
         its = s.iters[t];
         rho = s.rho[t];
         bb = s.bb[t];
         tol2 = s.tol2[0];
+        if (mode == RED_RZ) {
+            rrb = s.rrb[t];
+            stall = s.stall[t];
+        }
     }
     double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t m0 = j; m0 < nparts; m0 += (int64_t)U * npb) {
@@ -950,6 +1010,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __re
             const bool bad = !isfinite(rr) || !isfinite(rz);
             s.status[r] = bad ? -5 : 0;
             s.active[r] = bad ? 0 : ((rr > tol2 * b2) ? 1 : 0);
+            s.rrb[r] = rr;
+            s.stall[r] = 0;
         } else if (mode == RED_PQ) {
             const double pq = t0;
             s.pq[r] = pq;
@@ -978,8 +1040,16 @@ __global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __re
                 } else if (rr <= tol2 * bb) {
                     s.active[r] = 0;
                 } else {
-                    beta = rz / rho;
-                    s.rho[r] = rz;
+                    double rrb_new;
+                    int stall_new;
+                    if (cg_stalled(rr, rrb, stall, s.window, &rrb_new, &stall_new)) {
+                        s.active[r] = 0;
+                    } else {
+                        beta = rz / rho;
+                        s.rho[r] = rz;
+                    }
+                    s.rrb[r] = rrb_new;
+                    s.stall[r] = stall_new;
                 }
             }
             s.beta[r] = beta;
@@ -1237,9 +1307,13 @@ hipError_t launch_mass_apply(const Geo& g, const double* w, const double* in, do
 //   handles whole 1D lines of the element.
 // ---------------------------------------------------------------------------
 
+// PER_RHS: grad[e][m][r] = -a_{e,r}^T A_m u_{e,r} for every right-hand side r
+// ([n_e][4][k]) instead of the sum over r with the lambda column.
+template <bool PER_RHS>
 __global__ __launch_bounds__(256) void k_element_grads(Geo g, const double* __restrict__ w, const double* __restrict__ K,
                                                        const double* __restrict__ u, const double* __restrict__ a,
                                                        int64_t N, int k, double* __restrict__ grad) {
+    __shared__ double red[4][256];
     const Layout& L = g.L;
     const int p = L.p, n = p + 1;
     const int64_t N1 = (int64_t)L.n1 * p + 1, N2 = (int64_t)L.n2 * p + 1;
@@ -1275,23 +1349,40 @@ __global__ __launch_bounds__(256) void k_element_grads(Geo g, const double* __re
             }
             acc[1 + ax] += wt * s;
         }
+        if constexpr (PER_RHS) {
+            // fixed-order block sum of this right-hand side's four terms
+            __syncthreads();  // red free from the previous right-hand side
+            for (int m = 0; m < 4; ++m) red[m][threadIdx.x] = acc[m];
+            __syncthreads();
+            for (int s = 128; s > 0; s >>= 1) {
+                if ((int)threadIdx.x < s)
+                    for (int m = 0; m < 4; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + s];
+                __syncthreads();
+            }
+            if (threadIdx.x < 4) grad[(e * 4 + threadIdx.x) * k + r] = -red[threadIdx.x][0];
+            for (int m = 0; m < 4; ++m) acc[m] = 0.0;
+        }
     }
-    __shared__ double red[4][256];
-    for (int m = 0; m < 4; ++m) red[m][threadIdx.x] = acc[m];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int m = 0; m < 4; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + s];
+    if constexpr (!PER_RHS) {
+        for (int m = 0; m < 4; ++m) red[m][threadIdx.x] = acc[m];
         __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s)
+                for (int m = 0; m < 4; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x < 4) grad[e * 5 + threadIdx.x] = -red[threadIdx.x][0];
+        if (threadIdx.x == 4) grad[e * 5 + 4] = -red[0][0] * elem_jacobian(g, e1, e2, e3);  // d d0 / d lambda_e = J_e
     }
-    if (threadIdx.x < 4) grad[e * 5 + threadIdx.x] = -red[threadIdx.x][0];
-    if (threadIdx.x == 4) grad[e * 5 + 4] = -red[0][0] * elem_jacobian(g, e1, e2, e3);  // d d0 / d lambda_e = J_e
 }
 
 hipError_t launch_element_grads(const Geo& g, const double* w, const double* K, const double* u, const double* a,
-                                int64_t N, int k, double* grad, hipStream_t st) {
+                                int64_t N, int k, double* grad, bool per_rhs, hipStream_t st) {
     const int64_t ne = (int64_t)g.L.n1 * g.L.n2 * g.L.n3;
-    hipLaunchKernelGGL(k_element_grads, dim3((unsigned)ne), dim3(256), 0, st, g, w, K, u, a, N, k, grad);
+    if (per_rhs)
+        hipLaunchKernelGGL(k_element_grads<true>, dim3((unsigned)ne), dim3(256), 0, st, g, w, K, u, a, N, k, grad);
+    else
+        hipLaunchKernelGGL(k_element_grads<false>, dim3((unsigned)ne), dim3(256), 0, st, g, w, K, u, a, N, k, grad);
     return hipGetLastError();
 }
 

@@ -35,6 +35,9 @@ struct PcgArgs {
     int* active;
     int* iters;
     int* status;
+    double* rrb;     // stagnation state (see CgState), window <= 0: off
+    int* stall;
+    int window;
     double tol2;
     int max_iter;
     unsigned* bar;   // kBarWords grid barrier words, zero on first use

@@ -150,7 +150,8 @@ __global__ __launch_bounds__(S * apply_threads(NI), 2) void k_pcg_persistent(Pcg
     __shared__ ApplySmem<T, NI> sm[S];
     __shared__ double s_en[S][KM];
     __shared__ double s_rho[KM], s_alpha[KM], s_beta[KM], s_bb[KM], s_rr[KM], s_tot[2][KM];
-    __shared__ int s_act[KM], s_iters[KM], s_status[KM];
+    __shared__ int s_act[KM], s_iters[KM], s_status[KM], s_stall[KM];
+    __shared__ double s_rrb[KM];
     __shared__ double s_red[2][WG];
     __shared__ int s_flag, s_ok;
 
@@ -165,6 +166,8 @@ __global__ __launch_bounds__(S * apply_threads(NI), 2) void k_pcg_persistent(Pcg
         s_act[t] = P.active[t];
         s_iters[t] = P.iters[t];
         s_status[t] = P.status[t];
+        s_rrb[t] = P.rrb[t];
+        s_stall[t] = P.stall[t];
     }
     const double tol2 = P.tol2;
     __syncthreads();
@@ -291,6 +294,9 @@ __global__ __launch_bounds__(S * apply_threads(NI), 2) void k_pcg_persistent(Pcg
                 } else if (rr <= tol2 * s_bb[t]) {
                     s_act[t] = 0;
                     s_beta[t] = 0.0;
+                } else if (cg_stalled(rr, s_rrb[t], s_stall[t], P.window, &s_rrb[t], &s_stall[t])) {
+                    s_act[t] = 0;
+                    s_beta[t] = 0.0;
                 } else {
                     s_beta[t] = rz / s_rho[t];
                     s_rho[t] = rz;
@@ -308,6 +314,8 @@ __global__ __launch_bounds__(S * apply_threads(NI), 2) void k_pcg_persistent(Pcg
         P.active[t] = s_act[t];
         P.iters[t] = s_iters[t];
         P.status[t] = s_status[t];
+        P.rrb[t] = s_rrb[t];
+        P.stall[t] = s_stall[t];
     }
 }
 

@@ -6,8 +6,11 @@ stream, and turns status codes into exceptions.  There is no fallback: if the
 library is missing or fails to load, importing this module raises.
 """
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -36,7 +39,8 @@ class SolveOpts(ctypes.Structure):
                 ("check_every", ctypes.c_int), ("recover_interior", ctypes.c_int),
                 ("x0", ctypes.c_void_p), ("skel_out", ctypes.c_void_p),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("rhs_dual", ctypes.c_int),
-                ("persistent", ctypes.c_int), ("g_dirichlet", ctypes.c_void_p), ("ir_restart", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("g_dirichlet", ctypes.c_void_p), ("ir_restart", ctypes.c_int),
+                ("deterministic", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -51,6 +55,7 @@ _SIGS = {
     "semcond_host_tables": (ctypes.c_int, [ctypes.c_int] + [_c_double_p] * 5),
     "semcond_create": (ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "semcond_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "semcond_set_deterministic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "semcond_sizes": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 4),
     "semcond_skeleton_coords": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                                ctypes.POINTER(ctypes.c_uint8)]),
@@ -76,6 +81,8 @@ _SIGS = {
                                           ctypes.c_int, ctypes.c_void_p]),
     "semcond_element_grads": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int, ctypes.c_void_p]),
+    "semcond_element_grads_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "semcond_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_char_p,
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "semcond_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -154,6 +161,23 @@ def _dev(t, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
+# Contexts still open.  They are destroyed by an exit hook that runs while the
+# HIP runtime is still intact (Python's exit hooks run before the C runtime's
+# exit handlers tear HIP down); a context reached only by the garbage collector
+# during interpreter shutdown is left to the process exit instead of calling
+# into a runtime that may already be gone.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for c in list(_live):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A mesh + degree + lambda on the current device (semcond_create).
 
@@ -182,6 +206,8 @@ class Context:
         h = ctypes.c_void_p()
         _check(_lib.semcond_create(ctypes.byref(m), _stream(stream), ctypes.byref(h)))
         self._h = h
+        self.coef_version = 0  # bumped by update_coefficients
+        _live.add(self)
         self.p = p
         self.n = tuple(n)
         vals = [ctypes.c_int64() for _ in range(4)]
@@ -192,8 +218,11 @@ class Context:
         if getattr(self, "_h", None):
             _lib.semcond_destroy(self._h)
             self._h = None
+        _live.discard(self)
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -204,6 +233,11 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+    def set_deterministic(self, on=True):
+        """Fixed-order assembly (per-side slots, no atomics) for later applies,
+        condensations and solves on this context."""
+        _check(_lib.semcond_set_deterministic(self._h, 1 if on else 0), self._h)
 
     # -- introspection ---------------------------------------------------------
     def skeleton_coords(self):
@@ -346,6 +380,7 @@ class Context:
         dc = self._dcoef.ctypes.data_as(_c_double_p) if self._dcoef is not None else None
         _check(_lib.semcond_update_coefficients(self._h, 0.0 if lam is None else float(lam), le, dc,
                                                 _stream(stream)), self._h)
+        self.coef_version += 1
 
     def autotune(self, k=1, dtype=None, cache_path=None):
         """Pick the CG launch by timing; returns (S, G): the persistent grid, or (0, 0) for one
@@ -386,9 +421,21 @@ class Context:
                                           _stream(stream)), self._h)
         return out
 
+    def element_grads_rhs(self, u, a, stream=None):
+        """[n_e, 4, k]: -a_{e,r}^T A_m u_{e,r} per right-hand side r."""
+        import torch
+        k = self._k_nodal(u, "u")
+        if a.shape != u.shape:
+            raise ValueError("a must match u")
+        out = torch.empty((self.n_e, 4, k), dtype=torch.float64, device=u.device)
+        _check(_lib.semcond_element_grads_rhs(self._h, _dev(u, "u"), _dev(a, "a"), _dev(out, "out"), k,
+                                              _stream(stream)), self._h)
+        return out
+
     def solve(self, f, out=None, tol=1e-10, max_iter=20000, precision=PREC_F64, check_every=8,
               recover_interior=True, x0=None, skel_out=None, inner_tol=3e-3, max_outer=30,
-              rhs_dual=False, persistent=None, stream=None, raise_on_notconv=True, g=None, ir_restart=False):
+              rhs_dual=False, persistent=None, stream=None, raise_on_notconv=True, g=None, ir_restart=False,
+              deterministic=False):
         """Solve for nodal right-hand sides f (k, N) or (N,), FP64.  Returns (u, info).
         ir_restart (MIXED_IR): restart every FP32 inner CG from p = 0 instead of
         continuing its direction across refinement steps.
@@ -415,6 +462,7 @@ class Context:
         o.rhs_dual = 1 if rhs_dual else 0
         o.persistent = CG_AUTO if persistent is None else (CG_PERSISTENT if persistent else CG_STEPWISE)
         o.ir_restart = 1 if ir_restart else 0
+        o.deterministic = 1 if deterministic else 0
         if g is not None:
             if g.shape != f.shape or g.dtype != torch.float64:
                 raise ValueError("g must match f (shape, float64)")

@@ -133,3 +133,44 @@ def test_host_coefficient_inputs_get_host_gradients(lib):
         ctx.close()
     for a, b in zip(*grads):   # the scatter's atomic order may differ between runs
         np.testing.assert_allclose(a, b, rtol=1e-10, atol=1e-10 * np.abs(b).max())
+
+
+def test_backward_after_second_forward_uses_first_operator(lib):
+    """Two forwards with different lambda_e on one context, then the backward
+    of the first: its gradients are those of the first operator (oracle)."""
+    import torch
+    from oracle import grads as OG
+    from oracle import mesh as M
+    from paper_1601_08179_amd import autograd
+    rng = np.random.default_rng(23)
+    lam_a = np.exp(rng.uniform(np.log(0.1), np.log(100), 8))
+    lam_b = np.exp(rng.uniform(np.log(0.1), np.log(100), 8))
+    wmesh = W.mesh(3, (2, 2, 2), lam=None, lam_e=lam_a)
+    N = W.num_nodes(3, (2, 2, 2))
+    f = rng.standard_normal((1, N))
+    t = rng.standard_normal((1, N))
+    d, J = _metric(wmesh)
+    ctx, idx, ft, tt = _setup(wmesh, f, t)
+    la = torch.tensor(lam_a, device="cuda", requires_grad=True)
+    lb = torch.tensor(lam_b, device="cuda", requires_grad=True)
+    da = torch.tensor(d[:, 1:], device="cuda", requires_grad=True)
+    db = torch.tensor(d[:, 1:], device="cuda", requires_grad=True)
+    loss_a = _loss(autograd.solve(ctx, ft, la, da, tol=1e-14), tt, idx)
+    loss_b = _loss(autograd.solve(ctx, ft.detach(), lb, db, tol=1e-14), tt, idx)
+    loss_a.backward()
+    om = M.make_mesh(**dict(wmesh, lam_e=lam_a, dcoef=d))
+    ref = OG.loss_and_grads(om, f.T, t.T)
+    assert abs(loss_a.item() - ref["loss"]) <= 1e-10 * abs(ref["loss"])
+    np.testing.assert_allclose(la.grad.cpu().numpy(), ref["g_lam"], rtol=1e-9,
+                               atol=1e-9 * np.abs(ref["g_lam"]).max())
+    np.testing.assert_allclose(da.grad.cpu().numpy(), ref["g_d"][:, 1:], rtol=1e-9,
+                               atol=1e-9 * np.abs(ref["g_d"]).max())
+    np.testing.assert_allclose(ft.grad.cpu().numpy(), ref["g_f"].T, rtol=1e-9,
+                               atol=1e-9 * np.abs(ref["g_f"]).max())
+    # the second forward's backward still sees its own operator
+    loss_b.backward()
+    d_b, _ = _metric(W.mesh(3, (2, 2, 2), lam=None, lam_e=lam_b))
+    omb = M.make_mesh(**dict(wmesh, lam_e=lam_b, dcoef=d_b))
+    refb = OG.loss_and_grads(omb, f.T, t.T)
+    np.testing.assert_allclose(lb.grad.cpu().numpy(), refb["g_lam"], rtol=1e-9,
+                               atol=1e-9 * np.abs(refb["g_lam"]).max())

@@ -231,3 +231,24 @@ def test_reserve_then_solve(lib):
         lib._check(lib._lib.semcond_reserve(a._h, 4, 7), a._h)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("name", ["stretched3_p8", "p16_cube_limit"])
+def test_mixed_ir_unreachable_inner_tol(lib, name):
+    """An inner tolerance far below what the FP32 operator can reach (1e-9):
+    the inner tolerance is raised to the FP32 rounding level and an inner
+    solve that stops halving its residual ends its step, so the refinement
+    converges to 1e-10 in a bounded number of steps and inner iterations."""
+    print("case", name, flush=True)
+    ctx, op, g, free = both(MESHES[name]())
+    f = W.random_skeleton_input(op.sizes["N"], k=2, seed=18)
+    _, ref_info = ctx.solve(_t(f), tol=1e-10)
+    u, info = ctx.solve(_t(f), tol=1e-10, precision=lib.PREC_MIXED_IR, inner_tol=1e-9)
+    ref = _direct(op, f)
+    u = u.cpu().numpy()
+    for r in range(2):
+        print("FP64 iterations", ref_info[r]["iters"], "mixed", info[r], flush=True)
+        assert info[r]["status"] == 0 and info[r]["rel_res"] <= 1e-10, info[r]
+        assert info[r]["outer"] <= 12
+        assert info[r]["iters"] <= 6 * ref_info[r]["iters"] + 200
+        assert np.abs(u[r] - ref[r]).max() <= 1e-8 * np.abs(ref[r]).max()
