@@ -236,6 +236,26 @@ int semcond_skeleton_coords(const semcond_ctx* ctx, int32_t* ijk, uint8_t* free_
 int semcond_apply(semcond_ctx* ctx, const void* u, void* v, int k, int dtype, int basis,
                   void* stream);
 
+/*
+ * semcond_apply without any allocation at call time, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, layouts and results as
+ * semcond_apply; its workspace (the basis change and RHS-major copies of the
+ * physical-basis and k > 1 forms) is a fixed 32 MiB device array of the
+ * library, one per GPU, held until the process ends.
+ *   Limit: 2 N_s k values of scalar type dtype must fit 32 MiB (FP64: N_s k
+ *          <= 2 Mi; FP32: 4 Mi); larger calls fail with EINVAL, as does a
+ *          context in deterministic mode (its slot workspace would need an
+ *          allocation).  Launches are not recorded by semcond_profile_enable.
+ *   Every call on one GPU shares that GPU's array: calls that overlap in time
+ *   on one GPU (other streams, other contexts, other threads) race and must
+ *   be ordered by the caller.  The array keeps the last call's contents; the
+ *   call overwrites every part of it that it reads.
+ * Stream-ordered.  Errors: EINVAL, EDEVICE.
+ */
+int semcond_apply_noalloc(semcond_ctx* ctx, const void* u, void* v, int k, int dtype, int basis,
+                          void* stream);
+
 /* Basis change of skeleton arrays (direction: SEMCOND_COEF_TO_TRANSFORMED, ...).
  * in, out: device [N_s][k] of dtype, must not overlap. */
 int semcond_transform(semcond_ctx* ctx, const void* in, void* out, int k, int dtype,

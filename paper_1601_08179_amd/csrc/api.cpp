@@ -15,6 +15,7 @@
 #include "../../include/semcond.h"
 #include "kernels.h"
 #include "layout.h"
+#include "noalloc.h"
 #include "pcg_persistent.h"
 #include "tables.h"
 
@@ -88,6 +89,9 @@ struct semcond_ctx {
     // element rows of shared nodes through per-side slots in a fixed order
     bool det = false;         // set by semcond_set_deterministic (applies, condensation, solves)
     bool det_active = false;  // in force for the current call
+    // device address of the library's fixed apply workspace on this context's
+    // device (semcond_apply_noalloc), looked up at create
+    void* noalloc_ws = nullptr;
 };
 
 namespace {
@@ -887,9 +891,10 @@ int autotune_persistent(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int 
 // the physical basis adds S^-1 before and S^-T after (Sec. 6).  Temporaries:
 // ws_vec, 2 N_s k values.
 template <typename T>
-int apply_public(semcond_ctx* c, const T* u, T* v, int k, int basis, hipStream_t st) {
+int apply_public(semcond_ctx* c, const T* u, T* v, int k, int basis, T* ws, hipStream_t st) {
+    // ws: 2 N_s k values
     const int64_t Ns = c->N_s;
-    T* t1 = (T*)c->ws_vec.ptr;
+    T* t1 = ws;
     T* t2 = t1 + Ns * k;
     const DevTab<T>& tb = tabs<T>(c);
     const T* in = u;
@@ -1048,6 +1053,17 @@ int semcond_create(const semcond_mesh* m, void* stream, semcond_ctx** out) {
             return bail(SEMCOND_EDEVICE);                                                  \
         }                                                                                  \
     } while (0)
+    {
+        // the fixed workspace of semcond_apply_noalloc on this device
+        int dev = 0;
+        CHK(hipGetDevice(&dev));
+        CHK(noalloc_scratch_init());
+        c->noalloc_ws = noalloc_scratch(dev);
+        if (!c->noalloc_ws) {
+            fail(c, SEMCOND_EDEVICE, "fixed apply workspace: no device address");
+            return bail(SEMCOND_EDEVICE);
+        }
+    }
     CHK(hipMalloc(&c->d_widths, nw * sizeof(double)));
     CHK(hipMemcpy(c->d_widths, hw.data(), nw * sizeof(double), hipMemcpyHostToDevice));
     c->geo.L = c->L;
@@ -1118,8 +1134,39 @@ int semcond_apply(semcond_ctx* c, const void* u, void* v, int k, int dtype, int 
     }
     rc = grow(c, c->ws_vec, 2 * es * (size_t)c->N_s * k);
     if (rc) return rc;
-    if (dtype == SEMCOND_F64) return apply_public<double>(c, (const double*)u, (double*)v, k, basis, st);
-    return apply_public<float>(c, (const float*)u, (float*)v, k, basis, st);
+    if (dtype == SEMCOND_F64) return apply_public<double>(c, (const double*)u, (double*)v, k, basis, (double*)c->ws_vec.ptr, st);
+    return apply_public<float>(c, (const float*)u, (float*)v, k, basis, (float*)c->ws_vec.ptr, st);
+}
+
+int semcond_apply_noalloc(semcond_ctx* c, const void* u, void* v, int k, int dtype, int basis, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!u || !v) return fail(c, SEMCOND_EINVAL, "u and v must be device pointers");
+    if (u == v) return fail(c, SEMCOND_EINVAL, "u and v must not overlap");
+    int rc = check_dtype(c, dtype);
+    if (!rc) rc = check_k(c, k);
+    if (rc) return rc;
+    if (basis != SEMCOND_PHYSICAL && basis != SEMCOND_TRANSFORMED) return fail(c, SEMCOND_EINVAL, "bad basis");
+    if (c->det) return fail(c, SEMCOND_EINVAL, "semcond_apply_noalloc: deterministic mode needs the slot workspace");
+    if (!c->noalloc_ws) return fail(c, SEMCOND_EDEVICE, "semcond_apply_noalloc: fixed workspace not set up");
+    const size_t es = dtype == SEMCOND_F64 ? sizeof(double) : sizeof(float);
+    if (2 * es * (size_t)c->N_s * (size_t)k > kNoAllocScratchBytes)
+        return fail(c, SEMCOND_EINVAL, "semcond_apply_noalloc: 2 N_s k values exceed the fixed workspace (32 MiB)");
+    hipStream_t st = S(stream);
+    DetScope det(c, false);
+    // no profiling events either (their creation may allocate)
+    const bool prof = c->prof;
+    c->prof = false;
+    if (basis == SEMCOND_TRANSFORMED && k == 1) {
+        rc = dtype == SEMCOND_F64
+                 ? apply_transformed<double>(c, (const double*)u, (double*)v, k, NODE_MAJOR, nullptr, st)
+                 : apply_transformed<float>(c, (const float*)u, (float*)v, k, NODE_MAJOR, nullptr, st);
+    } else if (dtype == SEMCOND_F64) {
+        rc = apply_public<double>(c, (const double*)u, (double*)v, k, basis, (double*)c->noalloc_ws, st);
+    } else {
+        rc = apply_public<float>(c, (const float*)u, (float*)v, k, basis, (float*)c->noalloc_ws, st);
+    }
+    c->prof = prof;
+    return rc;
 }
 
 int semcond_transform(semcond_ctx* c, const void* in, void* out, int k, int dtype, int direction, void* stream) {
