@@ -57,12 +57,12 @@ class CondensedOperator:
         self.d, self.cls, self.uniq = element_classes(mesh)
         if len(self.uniq) > max_classes:
             raise MemoryError("%d element classes exceed the oracle limit" % len(self.uniq))
-        self.H = []
-        self.Hhat = []
-        for dc in self.uniq:
-            H = element.element_operator(self.p, dc, self.tab)
-            self.H.append(H)
-            self.Hhat.append(element.condense(H, self.B, self.I))
+        # per class: the element operator's blocks (dense Cholesky route for
+        # p <= 16, sparse Kronecker blocks with the separable interior inverse
+        # above), and for the dense route the explicit Schur complement
+        self.blocks = [element.ElementBlocks(self.p, dc, self.tab) for dc in self.uniq]
+        self.H = [b.H for b in self.blocks]
+        self.Hhat = [b.schur_matrix() if b.route == "dense" else None for b in self.blocks]
         self.skel = meshmod.skeleton_mask(mesh)
         self.cons = meshmod.constrained_mask(mesh)
         self.free_skel = self.skel & ~self.cons
@@ -88,19 +88,44 @@ class CondensedOperator:
             idx = self.gB[els]                              # (ne_c, nB)
             k = Um.shape[1]
             UL = Um[idx].transpose(1, 0, 2).reshape(len(self.B), -1)   # (nB, ne_c*k)
-            VL = (Hh @ UL).reshape(len(self.B), len(els), k)          # one GEMM per class
+            if Hh is not None:
+                VL = (Hh @ UL).reshape(len(self.B), len(els), k)      # one GEMM per class
+            else:
+                VL = self._schur_apply_chunked(c, UL).reshape(len(self.B), len(els), k)
             for r in range(k):
                 V[:, r] += np.bincount(idx.T.ravel(), weights=VL[:, :, r].ravel(),
                                        minlength=len(V))
         V[~self.free_skel] = 0.0
         return V[:, 0] if squeeze else V
 
+    def _schur_apply_chunked(self, c, UL, chunk=512):
+        """Schur complement of class c applied to the columns of UL (large-p route)."""
+        out = np.empty_like(UL)
+        for c0 in range(0, UL.shape[1], chunk):
+            out[:, c0:c0 + chunk] = self.blocks[c].schur_apply(UL[:, c0:c0 + chunk])
+        return out
+
+    def schur(self, c):
+        """Explicit Schur complement of class c (formed on first use for p > 16)."""
+        if self.Hhat[c] is None:
+            self.Hhat[c] = self.blocks[c].schur_matrix()
+        return self.Hhat[c]
+
+    @staticmethod
+    def _local_coo(H):
+        """Local (row, col, value) triples of a dense or sparse element matrix."""
+        if sp.issparse(H):
+            h = H.tocoo()
+            return h.row, h.col, h.data
+        n = H.shape[0]
+        return np.repeat(np.arange(n), n), np.tile(np.arange(n), n), H.ravel()
+
     # -- sparse assembled matrices -------------------------------------------
     def assembled_condensed(self):
         """Sparse Hhat_G restricted to free skeleton nodes, with their numbers."""
         rows, cols, vals = [], [], []
         for e in range(len(self.gB)):
-            Hh = self.Hhat[self.cls[e]]
+            Hh = self.schur(self.cls[e])
             g = self.gB[e]
             rows.append(np.repeat(g, len(g)))
             cols.append(np.tile(g, len(g)))
@@ -115,11 +140,11 @@ class CondensedOperator:
         """Sparse full uncondensed H_G = R H_L R^T restricted to free nodes."""
         rows, cols, vals = [], [], []
         for e in range(len(self.gmap)):
-            H = self.H[self.cls[e]]
+            lr, lc, lv = self._local_coo(self.H[self.cls[e]])
             g = self.gmap[e]
-            rows.append(np.repeat(g, len(g)))
-            cols.append(np.tile(g, len(g)))
-            vals.append(H.ravel())
+            rows.append(g[lr])
+            cols.append(g[lc])
+            vals.append(lv)
         N = self.sizes["N"]
         A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                           shape=(N, N)).tocsr()
@@ -152,16 +177,13 @@ class CondensedOperator:
             F = F[:, :, None]
         N = self.sizes["N"]
         out = np.zeros((N, F.shape[2]))
-        for c, H in enumerate(self.H):
+        for c, blk in enumerate(self.blocks):
             els = np.nonzero(self.cls == c)[0]
             if len(els) == 0:
                 continue
-            HII = H[np.ix_(self.I, self.I)]
-            HBI = H[np.ix_(self.B, self.I)]
-            ch = sla.cho_factor(HII, lower=True)
             for r in range(F.shape[2]):
                 FI = F[els][:, self.I, r].T                  # (nI, ne_c)
-                corr = HBI @ sla.cho_solve(ch, FI)           # (nB, ne_c)
+                corr = blk.HBI @ blk.interior_solve(FI)      # (nB, ne_c)
                 FB = F[els][:, self.B, r].T - corr
                 out[:, r] += np.bincount(self.gB[els].ravel(), weights=FB.T.ravel(), minlength=N)
         out[~self.free_skel] = 0.0
@@ -195,11 +217,11 @@ class CondensedOperator:
         """
         rows, cols, vals = [], [], []
         for e in range(len(self.gmap)):
-            H = self.H[self.cls[e]]
+            lr, lc, lv = self._local_coo(self.H[self.cls[e]])
             gm = self.gmap[e]
-            rows.append(np.repeat(gm, len(gm)))
-            cols.append(np.tile(gm, len(gm)))
-            vals.append(H.ravel())
+            rows.append(gm[lr])
+            cols.append(gm[lc])
+            vals.append(lv)
         N = self.sizes["N"]
         A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                           shape=(N, N)).tocsr()
@@ -226,15 +248,12 @@ class CondensedOperator:
         F = self.element_rhs(f)
         u = np.array(u_skel, dtype=np.float64)
         um = np.where(self.free_skel, u, 0.0)
-        for c, H in enumerate(self.H):
+        for c, blk in enumerate(self.blocks):
             els = np.nonzero(self.cls == c)[0]
             if len(els) == 0:
                 continue
-            HII = H[np.ix_(self.I, self.I)]
-            HIB = H[np.ix_(self.I, self.B)]
-            ch = sla.cho_factor(HII, lower=True)
             uB = um[self.gB[els]].T                          # (nB, ne_c)
-            uI = sla.cho_solve(ch, F[els][:, self.I].T - HIB @ uB)
+            uI = blk.interior_solve(F[els][:, self.I].T - blk.HIB @ uB)
             u[self.gI[els]] = uI.T
         u[self.cons] = 0.0
         return u

@@ -47,6 +47,25 @@ MESHES = {
 }
 
 
+# Degrees above the oracle's dense route (separable interior inverse, Sec. 5):
+# the k-plane element path at n_I = 17..31, including the lane-group splits of
+# n_I = 30, 31, with lambda > 0 or per-element lambda, graded widths (aspect
+# ratios up to 100) and partial Dirichlet masks that leave vertices free.
+LARGE_P = {
+    "p18_lam_e": lambda: W.mesh(18, (2, 2, 1), widths=[[0.1, 0.9], [0.35, 0.65], [0.5]], lam=None,
+                                lam_e=[0.2, 5.0, 60.0, 1.0], dirichlet=0b010101),
+    "p20_stretched": lambda: W.mesh(20, (2, 1, 2), widths=[[0.8, 0.2], [0.3], [0.04, 0.96]], lam=1.0,
+                                    dirichlet=0b100010),
+    "p24_lam": lambda: W.mesh(24, (1, 2, 2), widths=[[1.0], [0.03, 0.97], [0.4, 0.6]], lam=2.5,
+                              dirichlet=0b001001),
+    "p28_lam_e": lambda: W.mesh(28, (2, 1, 1), widths=[[0.45, 0.55], [0.2], [0.7]], lam=None,
+                                lam_e=[0.1, 100.0], dirichlet=0b000100),
+    "p31_planes": lambda: W.mesh(31, (2, 1, 1), widths=[[0.7, 0.3], [0.25], [0.9]], lam=1.0, dirichlet=0b001000),
+    "p32_lam_e": lambda: W.mesh(32, (2, 1, 2), widths=[[0.01, 0.99], [1.0], [0.5, 0.5]], lam=None,
+                                lam_e=[0.1, 100.0, 3.0, 0.7], dirichlet=0b000100),
+}
+
+
 def oracle_transform(op):
     """Dense (A, fs, T) over free skeleton nodes fs: A the oracle's assembled
     condensed matrix, T the block transform with S along every interior axis of

@@ -2,15 +2,16 @@
 meshes too large for the oracle's assembled operator (test helper).
 
 For a global node, every incident element's condensed operator is formed from
-its definitions (explicit element matrix, Schur complement by Cholesky,
-Sec. 4), applied to that element's boundary values, and the node's rows are
-summed (the assembly R of Sec. 3).  Values on Dirichlet faces are read as 0.
+its definitions (explicit element matrix and the Schur complement of Sec. 4:
+dense Cholesky for p <= 16, sparse Kronecker blocks with the separable interior
+inverse above), applied to that element's boundary values, and the node's rows
+are summed (the assembly R of Sec. 3).  Values on Dirichlet faces are read as 0.
+Per-element lambda (``lam_e``, element order e1 fastest) is honoured.
 """
 
 import itertools
 
 import numpy as np
-import scipy.linalg as sla
 
 from oracle import element as OE
 from oracle import gll
@@ -50,26 +51,22 @@ class SampledOracle:
         """H^_e u_B for element e = (e1, e2, e3): full boundary vector (element order of B)."""
         e1, e2, e3 = e
         w = self.m["widths"]
-        lam = self.m["lam"]
+        lam_e = self.m.get("lam_e")
+        lam = self.m["lam"] if lam_e is None else lam_e[e1 + self.n[0] * (e2 + self.n[1] * e3)]
         d = OE.metric((w[0][e1], w[1][e2], w[2][e3]), lam)
         key = tuple(d)
         if key not in self.cache:
             if len(self.cache) >= 8:          # bounded host memory at large p
                 self.cache.pop(next(iter(self.cache)))
-            H = OE.element_operator(self.p, d, self.tab)
-            c = sla.cho_factor(H[np.ix_(self.I, self.I)], lower=True) if len(self.I) else None
-            self.cache[key] = (H, c)
-        H, c = self.cache[key]
+            self.cache[key] = OE.ElementBlocks(self.p, d, self.tab)
+        blk = self.cache[key]
         p1 = self.p + 1
         kk, rem = np.divmod(self.B, p1 * p1)
         jj, ii = np.divmod(rem, p1)
         I1, I2, I3 = e1 * self.p + ii, e2 * self.p + jj, e3 * self.p + kk
         uB = np.array([0.0 if self.constrained((a, b, cc)) else u_of_node(a, b, cc)
                        for a, b, cc in zip(I1, I2, I3)])
-        out = H[np.ix_(self.B, self.B)] @ uB
-        if c is not None:
-            out -= H[np.ix_(self.B, self.I)] @ sla.cho_solve(c, H[np.ix_(self.I, self.B)] @ uB)
-        return out, (I1, I2, I3)
+        return blk.schur_apply(uB), (I1, I2, I3)
 
     def row(self, I, u_of_node, memo):
         total = 0.0

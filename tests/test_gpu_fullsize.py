@@ -49,6 +49,7 @@ CASES = {
     "config3_p4_ar32": (lambda: W.config3(4, 32, k=1)[0], 1),
     "config3_p8_ar128": (lambda: W.config3(8, 128, k=1)[0], 1),
     "config3_p16_ar8": (lambda: W.config3(16, 8, k=1)[0], 1),
+    "config3_p32_ar128": (lambda: W.config3(32, 128, k=1)[0], 1),
     "config4_p12_k16": (lambda: W.config4(k=1)[0], 16),
 }
 
@@ -98,3 +99,61 @@ def test_apply_full_size_sampled(lib, name):
         print(name, "rhs", r, "samples", len(ref), "rel err", err, flush=True)
         assert err <= 1e-12
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# Whole-mesh oracle checks at full size
+# ---------------------------------------------------------------------------
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda", dtype=torch.float64)
+
+
+@pytest.mark.parametrize("cfg", ["config2", "config5"])
+def test_apply_full_size_whole_mesh(lib, cfg):
+    """The 16^3 p = 8 benchmark mesh (k = 2) and the 8^3 p = 8 differentiation
+    mesh with per-element lambda and graded widths (k = 8): the physical-basis
+    apply at every free skeleton node against the oracle's assembled operator
+    (one explicit Schur complement per element class)."""
+    from gpu_helpers import both, rel_err
+    print("case", cfg, flush=True)
+    wmesh, k = (W.config2()[0], 2) if cfg == "config2" else (W.config5()[0], 8)
+    ctx, op, g, free = both(wmesh)
+    u = W.random_skeleton_input(op.sizes["N"], k=k, seed=91)
+    ref = op.apply(u.T)[g]
+    out = ctx.apply(_t(u.T[g]), basis=lib.PHYSICAL).cpu().numpy()
+    for r in range(k):
+        e = rel_err(out[free, r], ref[free, r])
+        emax = np.abs(out[free, r] - ref[free, r]).max() / np.abs(ref[free, r]).max()
+        assert e <= 1e-12 and emax <= 1e-12, (cfg, r, e, emax)
+    print(cfg, "k", k, "max rel err", e, flush=True)
+    assert np.all(out[~free] == 0.0)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["PREC_F64", "PREC_MIXED_IR"])
+def test_config4_solution_oracle_residual(lib, precision):
+    """24^3 elements, p = 12, 16 N(0,1) right-hand sides solved together to
+    1e-10 (FP64 CG, or FP32 inner CG with FP64 refinement): for the first and
+    last right-hand side the oracle's residual ||F^ - H^ u_B|| / ||F^|| of the
+    returned skeleton values (free nodes, physical basis) is <= 1e-9."""
+    print("case config4", precision, flush=True)
+    from oracle import mesh as M
+    from oracle.operators import CondensedOperator
+    wmesh, f = W.config4(k=16)
+    ctx = lib.Context(wmesh)
+    u, info = ctx.solve(_t(f), tol=1e-10, precision=getattr(lib, precision))
+    pick = [0, 15]
+    u = u[pick].cpu().numpy()
+    ctx.close()
+    op = CondensedOperator(M.make_mesh(**wmesh))
+    fs = op.free_skel
+    Fh = op.condensed_rhs(f[pick].T)
+    V = op.apply(u.T)
+    for j, r in enumerate(pick):
+        assert info[r]["status"] == 0 and info[r]["rel_res"] <= 1e-10, info[r]
+        rr = np.linalg.norm(Fh[fs, j] - V[fs, j]) / np.linalg.norm(Fh[fs, j])
+        print("config4", precision, "rhs", r, "iters", info[r]["iters"], "outer", info[r]["outer"],
+              "oracle residual", rr, flush=True)
+        assert rr <= 1e-9, (precision, r, rr)

@@ -200,3 +200,96 @@ def test_transformed_factorisation_matches_schur(p):
     w_face = np.nonzero((ii[B] == 0) & isI(jj[B]) & isI(kk[B]))[0]
     blk = Ht[np.ix_(w_face, w_face)]
     assert np.abs(blk - np.diag(np.diag(blk))).max() < 1e-12 * np.abs(blk).max()
+
+
+# ---------------------------------------------------------------------------
+# Large-p route (sparse Kronecker blocks, separable interior inverse)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p", [8, 12, 16])
+def test_separable_route_matches_dense_cholesky(p):
+    """The separable route's Schur complement equals the dense Cholesky one
+    for general metrics (lambda > 0, anisotropic), at every p the dense route
+    reaches."""
+    t = gll.tables(p)
+    for d in (np.array([0.8, 1.7, 0.6, 2.3]), element.metric((0.01, 0.5, 1.28), 3.0)):
+        dense = element.ElementBlocks(p, d, t, route="dense")
+        sep = element.ElementBlocks(p, d, t, route="separable")
+        S_d = dense.schur_matrix()
+        S_s = sep.schur_matrix()
+        assert np.abs(S_s - S_d).max() <= 1e-12 * np.abs(S_d).max()
+        U = np.random.default_rng(p).standard_normal((len(dense.B), 3))
+        a, b = dense.schur_apply(U), sep.schur_apply(U)
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("p", [18, 24, 32])
+def test_separable_route_against_explicit_operator(p):
+    """At large p, against the explicit sparse element operator: the interior
+    values u_I = -H_II^-1 H_IB u_B make (H u)_I vanish (energy minimum over the
+    interior), and the Schur complement applied to u_B equals (H u)_B."""
+    t = gll.tables(p)
+    d = element.metric((0.02, 0.7, 2.56), 1.0)
+    blk = element.ElementBlocks(p, d, t)
+    assert blk.route == "separable"
+    H = element.element_operator_sparse(p, d, t)
+    B, I = blk.B, blk.I
+    uB = np.random.default_rng(100 + p).standard_normal((len(B), 2))
+    uI = -blk.interior_solve(blk.HIB @ uB)
+    u = np.zeros(((p + 1) ** 3, 2))
+    u[B] = uB
+    u[I] = uI
+    Hu = H @ u
+    scale = np.abs(H).max() * np.abs(u).max()
+    assert np.abs(Hu[I]).max() <= 1e-12 * scale
+    SuB = blk.schur_apply(uB)
+    assert np.linalg.norm(SuB - Hu[B]) <= 1e-12 * np.linalg.norm(Hu[B])
+    # the interior solve itself, on a general right-hand side
+    b = np.random.default_rng(200 + p).standard_normal(len(I))
+    x = blk.interior_solve(b)
+    assert np.linalg.norm(blk.HII @ x - b) <= 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("p", [24])
+def test_separable_route_trilinear_closed_form(p):
+    """lambda = 0 at p = 24 on the separable route: the Schur complement
+    reproduces the closed-form H u on B for the eight trilinear modes."""
+    t = gll.tables(p)
+    x, w = t["x"], t["w"]
+    d = np.array([0.0, 1.7, 0.6, 2.3])
+    blk = element.ElementBlocks(p, d, t)
+    assert blk.route == "separable"
+    B = blk.B
+    kk, jj, ii = _kji(p)
+    ends = lambda idx: (idx == p).astype(float) - (idx == 0).astype(float)
+    for e3 in (0, 1):
+        for e2 in (0, 1):
+            for e1 in (0, 1):
+                f1 = x[ii] if e1 else np.ones_like(x[ii])
+                f2 = x[jj] if e2 else np.ones_like(x[jj])
+                f3 = x[kk] if e3 else np.ones_like(x[kk])
+                Hu = np.zeros(len(ii))
+                if e1:
+                    Hu += d[1] * w[kk] * f3 * w[jj] * f2 * ends(ii)
+                if e2:
+                    Hu += d[2] * w[kk] * f3 * ends(jj) * w[ii] * f1
+                if e3:
+                    Hu += d[3] * ends(kk) * w[jj] * f2 * w[ii] * f1
+                got = blk.schur_apply((f1 * f2 * f3)[B])
+                assert np.abs(got - Hu[B]).max() <= 1e-12 * max(1.0, np.abs(Hu).max())
+
+
+def test_separable_schur_matrix_symmetric_p20():
+    """The column-block Schur complement of the separable route is symmetric
+    before symmetrisation (p = 20, lambda > 0)."""
+    p = 20
+    t = gll.tables(p)
+    blk = element.ElementBlocks(p, element.metric((0.05, 0.3, 1.0), 2.0), t)
+    nB = len(blk.B)
+    cols = np.random.default_rng(5).choice(nB, 40, replace=False)
+    E = np.zeros((nB, 40))
+    E[cols, np.arange(40)] = 1.0
+    S = blk.schur_apply(E)                 # columns cols of the Schur complement
+    # entry (cols[a], cols[b]) against (cols[b], cols[a]) for the sampled pairs
+    sub = S[cols]
+    assert np.abs(sub - sub.T).max() <= 1e-12 * np.abs(sub).max()
