@@ -1,23 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the condensed-Helmholtz BT solve on one MI355X.
 
-Workload (default): 16^3 uniform elements on the unit cube, GLL degree p = 8,
-lambda = 1e-3, homogeneous Dirichlet, one N(0,1) nodal right-hand side drawn
-from the seeded generator; FP64 throughout.  N = 129^3 = 2,146,689 nodes.
+Workload (default line): 24^3 uniform elements on the unit cube, GLL degree
+p = 12, lambda = 1, homogeneous Dirichlet, 16 N(0,1) nodal right-hand sides
+from the seeded generator (N = 289^3 = 24,137,569 nodes per RHS, N_s =
+5,737,825 skeleton nodes).
 
-One step = one full solve: condensed transformed right-hand side, BT conjugate
-gradients to ||r~|| <= 1e-10 ||F^~||, back-transform of the skeleton and
-recovery of the interior (all on the GPU; inputs resident in HBM).
+One step = one batched solve of the 16 right-hand sides to ||r~|| <= 1e-10
+||F^~|| each, in mixed precision: FP32 operator and inner BT conjugate
+gradients (FP64 dot products), FP64 iterative refinement (residual with the
+FP64 operator), then back-transform and interior recovery in FP64 (all on the
+GPU; inputs resident in HBM).  The same batch solved in plain FP64 is timed
+beside it over the same number of steps (mixed vs FP64 time to 1e-10).
 
-value = N * iterations / solve time  [GDOF/s]: total unknowns times CG
-iterations per second, i.e. the reciprocal of the time per DOF and iteration.
-The CG launch (one launch per step, or one persistent cooperative launch) is
-the one the library's autotuner picks for this problem.  The roofline is that
-of the dominant kernel of the timed solves, from its algorithmic bytes and the
-kernel time from HIP events the library records on the launch stream.  The
-line also reports the solve with each launch kind forced, the mixed-precision
-solve, the standalone apply kernel's rate and roofline, and the FP64 CPU
-oracle's apply rate on this workload.
+value = N * sum_r (operator applications of RHS r) / step time [GDOF/s]:
+the condensed-operator DOF applications per second sustained inside the
+solve, the reciprocal of the PCG time per DOF and iteration.  The roofline is
+that of the dominant kernel of the timed steps (the FP32 CG apply), from its
+algorithmic bytes and its kernel time from HIP events the library records on
+the launch stream during the timed steps.  The line also reports the FP64
+solve's CG apply roofline, the standalone applies, the one-launch-per-solve
+(persistent) CG, the 16^3, p = 8 single-RHS FP64 solve (extra keys), and the
+FP64 CPU oracle's condensed apply on the same mesh on all host cores and on
+one core.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -44,33 +49,6 @@ def cpu_model():
     except OSError:
         pass
     return "unknown"
-
-
-def cpu_baseline(wmesh, seconds=12.0):
-    """Time the FP64 CPU oracle's condensed apply (explicit Schur complements,
-    one GEMM per element class) on the same mesh, for about `seconds`."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
-
-    import workloads as W
-    from oracle import mesh as M
-    from oracle.operators import CondensedOperator
-
-    op = CondensedOperator(M.make_mesh(**wmesh))
-    u = W.random_skeleton_input(op.sizes["N"], k=1, seed=0)[0]
-    op.apply(u)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        op.apply(u)
-        reps += 1
-        dt = time.perf_counter() - t0
-        if dt >= seconds or reps >= 2000:
-            break
-    threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
-    return {"value": op.sizes["N"] * reps / dt / 1e9, "unit": "GDOF/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": "%d oracle condensed applies (explicit Schur complement, one DGEMM per element "
-                      "class; no CG vector work) on the same mesh, %.1f s, %s" % (reps, dt, cpu_model())}
 
 
 def _apply_rate(ctx, semcond, torch, k=1, reps=20):
@@ -269,8 +247,9 @@ def suite(args):
 # ---------------------------------------------------------------------------
 # HBM traffic of the dominant kernel from rocprofv3 counters
 # ---------------------------------------------------------------------------
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_config2_p8.md")
-DOMINANT = "k_apply_tpt<double, 7, true, true>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cg_apply_f32_config4_p12_k16.md")
+NI4 = 11  # interior nodes per direction at p = 12
+DOMINANT = "k_apply_tpt<float, %d, true, false>" % NI4
 KERNEL_SOURCES = ["apply.hip", "apply_element.h", "cg_device.h", "device_common.h", "kernels.h", "layout.h"]
 COPY_BYTES = 256 << 20
 
@@ -286,8 +265,8 @@ def kernel_sources_hash():
 
 def pmc_workload():
     """Dispatches the counter runs read: a plain device copy of COPY_BYTES
-    (calibration), one timed-workload FP64 solve (its CG applies are the
-    dominant kernel) and standalone applies."""
+    (calibration) and one mixed-precision solve of the default workload (its
+    FP32 CG applies are the dominant kernel)."""
     import torch
 
     import workloads as W
@@ -298,12 +277,15 @@ def pmc_workload():
     for _ in range(5):
         torch.mul(x, 1.0, out=y)  # a plain streaming kernel: reads and writes COPY_BYTES
     torch.cuda.synchronize()
-    wmesh, f = W.config2(k=1)
+    del x, y
+    wmesh, f = W.config4()
     ctx = semcond.Context(wmesh)
     ft = torch.tensor(f, device="cuda")
+    del f
     u = torch.zeros_like(ft)
-    ctx.solve(ft, out=u, tol=1e-10, persistent=False)
+    _, info = ctx.solve(ft, out=u, tol=1e-10, precision=semcond.PREC_MIXED_IR, persistent=False)
     torch.cuda.synchronize()
+    print("pmc workload: inner iterations per RHS", [i["iters"] for i in info], flush=True)
     ctx.close()
 
 
@@ -333,21 +315,22 @@ def pmc_summary(fetch_csv, write_csv, commands):
         return sum(big) / len(big)
 
     def dominant(rows):
-        # full applies only: launches queued after convergence exit at once and
-        # read a few KiB (below a tenth of the median)
+        # full applies only: launches in which every RHS has stopped exit at once
+        # and read a few KiB (below a tenth of the median)
         for name, lst in rows.items():
             if name.startswith("void semcond::" + DOMINANT):
                 vals = sorted(v for _, v in lst)
                 full = [v for v in vals if v >= 0.1 * vals[len(vals) // 2]]
-                return sum(full) / len(full), len(full)
+                return sum(full) / len(full), len(full), len(vals)
         raise KeyError(DOMINANT)
 
     ff = COPY_BYTES / (copy_value(fe) * 1024.0)
     fw = COPY_BYTES / (copy_value(wr) * 1024.0)
-    (fk, nf), (wk, nw) = dominant(fe), dominant(wr)
+    (fk, nf, naf), (wk, nw, naw) = dominant(fe), dominant(wr)
     fetch_b, write_b = fk * 1024.0 * ff, wk * 1024.0 * fw
     lines = [
-        "# HBM traffic of %s (bench.py workload, FP64 CG apply, MI355X)" % DOMINANT,
+        "# HBM traffic of %s (FP32 CG apply of the mixed-precision solve: 24^3 elements, p = 12, "
+        "k = 16 RHS; MI355X)" % DOMINANT,
         "",
         "Commands (from the repository root, on one MI355X):",
         "",
@@ -360,10 +343,10 @@ def pmc_summary(fetch_csv, write_csv, commands):
         "| calibration: FETCH_SIZE of a streaming kernel reading and writing %d MiB | %.0f KiB (factor %.4f) |" % (
             COPY_BYTES >> 20, copy_value(fe), ff),
         "| calibration: WRITE_SIZE of the same kernel | %.0f KiB (factor %.4f) |" % (copy_value(wr), fw),
-        "| dominant kernel FETCH_SIZE per full dispatch (%d dispatches) | %.1f KiB |" % (nf, fk),
-        "| dominant kernel WRITE_SIZE per full dispatch (%d dispatches) | %.1f KiB |" % (nw, wk),
-        "| scaled HBM read bytes per launch | %.0f |" % fetch_b,
-        "| scaled HBM write bytes per launch | %.0f |" % write_b,
+        "| dominant kernel FETCH_SIZE per full dispatch (%d of %d dispatches) | %.1f KiB |" % (nf, naf, fk),
+        "| dominant kernel WRITE_SIZE per full dispatch (%d of %d dispatches) | %.1f KiB |" % (nw, naw, wk),
+        "| scaled HBM read bytes per full launch | %.0f |" % fetch_b,
+        "| scaled HBM write bytes per full launch | %.0f |" % write_b,
         "",
         "traffic_bytes_per_launch: %.0f" % (fetch_b + write_b),
         "kernel_sources_sha256: %s" % kernel_sources_hash(),
@@ -387,19 +370,122 @@ def stored_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+def copy_bandwidth(torch):
+    """STREAM-style copy on this GPU (1 GiB read + 1 GiB written), GB/s."""
+    ca = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        cb.copy_(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * ca.numel() * 8 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del ca, cb
+    return gbs
+
+
+def cpu_baseline_config4(wmesh, seconds):
+    """The FP64 CPU oracle's condensed apply (explicit Schur complement of the
+    single element class, one DGEMM, index gather and scatter-add) of one RHS on
+    the default mesh: on all host cores, and on one core (BLAS limited to one
+    thread), each for about `seconds` (at least one apply)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    import workloads as W
+    from oracle import mesh as M
+    from oracle.operators import CondensedOperator
+
+    t0 = time.perf_counter()
+    op = CondensedOperator(M.make_mesh(**wmesh))
+    setup = time.perf_counter() - t0
+    u = W.random_skeleton_input(op.sizes["N"], k=1, seed=0)[0]
+    N = op.sizes["N"]
+
+    def run(limit):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            op.apply(u)
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= seconds or reps >= 200:
+                return reps, dt
+
+    threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    op.apply(u)
+    reps, dt = run(None)
+    with threadpool_limits(limits=1, user_api="blas"):
+        reps1, dt1 = run(1)
+    model = cpu_model()
+    full = {"value": N * reps / dt / 1e9, "unit": "GDOF/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d oracle condensed applies of one RHS (explicit Schur complement of the one element "
+                      "class, one DGEMM per apply, index gather and scatter-add; no CG vector work) on the "
+                      "24^3, p = 12 mesh, %.1f s on %d BLAS threads, %s; oracle set-up %.1f s not timed" % (
+                          reps, dt, threads, model, setup)}
+    one = {"value": N * reps1 / dt1 / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+           "sample": "%d oracle condensed applies of one RHS, same mesh, %.1f s with BLAS limited to one "
+                     "thread, %s" % (reps1, dt1, model)}
+    return full, one
+
+
+def config2_line(args, semcond, torch):
+    """The 16^3, p = 8, lambda = 1e-3 single-RHS FP64 solve (the earlier default
+    line), its standalone apply and the CG apply roofline, as extra keys."""
+    import workloads as W
+
+    wmesh, f = W.config2(k=1)
+    ctx = semcond.Context(wmesh)
+    ft = torch.tensor(f, device="cuda")
+    u = torch.zeros_like(ft)
+    N, Ns = ctx.N, ctx.N_s
+    for _ in range(2):
+        ctx.solve(ft, out=u, tol=args.tol, persistent=False)
+    reps = 10
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(reps):
+        _, info = ctx.solve(ft, out=u, tol=args.tol, persistent=False)
+        iters += info[0]["iters"]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ap_ms, ap_launches, _ = ctx.profile_read(semcond.KERNEL_APPLY)
+    ctx.profile_enable(False)
+    it = iters / reps
+    # CG apply: gathers p, r and P^-1 and writes q (4 N_s FP64) per full launch
+    full = int(round(it * reps))
+    cg_gbs = 4 * 8 * Ns * full / (ap_ms / 1e3) / 1e9
+    ks = _apply_rate(ctx, semcond, torch, k=1, reps=100)
+    out = {"workload": "BT solve to 1e-10, FP64: 16^3 uniform elements, p=8, lambda=1e-3, one N(0,1) RHS",
+           "N": N, "N_s": Ns, "iterations": it, "ms_per_solve": dt * 1e3,
+           "gdof_s": N * it / dt / 1e9, "ns_per_dof_iter": dt / (N * it) * 1e9,
+           "cg_apply": {"kernel": "k_apply_tpt<double,7,true,true>", "us_per_launch": ap_ms * 1e3 / ap_launches,
+                        "launches": ap_launches, "full_launches": full, "gbs": cg_gbs,
+                        "hbm_frac": cg_gbs / HBM_PEAK_GBS},
+           "apply": {"kernel": "k_apply_tpt<double,7,false,false>", "us": ks * 1e6, "gdof_s": N / ks / 1e9,
+                     "gbs": 2 * 8 * Ns / ks / 1e9, "hbm_frac": 2 * 8 * Ns / ks / 1e9 / HBM_PEAK_GBS}}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-config2", action="store_true")
+    ap.add_argument("--no-persistent", action="store_true", help="skip the one-launch-per-solve CG runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--suite", default="", help="extra measurements instead of the default line: "
-                    "any of 3 (p/AR sweep), 4 (16 RHS), 5 (differentiable solve), D (the paper's "
-                    "solver experiment with inhomogeneous Dirichlet values), S (its element-count "
-                    "scaling), e.g. --suite 345DS")
+                    "any of 3 (p/AR sweep), 4 (16 RHS, every launch kind), 5 (differentiable solve), "
+                    "D (the paper's solver experiment with inhomogeneous Dirichlet values), S (its "
+                    "element-count scaling), e.g. --suite 345DS")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the dispatches the rocprofv3 counter runs read")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -426,109 +512,103 @@ def main():
     import workloads as W
     from paper_1601_08179_amd import semcond
 
-    wmesh, f = W.config2(k=1)
+    wmesh, f = W.config4()
+    k = f.shape[0]
     ctx = semcond.Context(wmesh)
     ft = torch.tensor(f, device="cuda")
+    del f
     u = torch.zeros_like(ft)
     N, Ns = ctx.N, ctx.N_s
-
-    # CG launch choice for (k = 1, FP64): one launch per step or a persistent grid
-    tS, tG = ctx.autotune(k=1, dtype=torch.float64)
+    mixed = dict(precision=semcond.PREC_MIXED_IR, persistent=False)
+    fp64 = dict(precision=semcond.PREC_F64, persistent=False)
     for _ in range(args.warmup):
-        ctx.solve(ft, out=u, tol=args.tol)
+        ctx.solve(ft, out=u, tol=args.tol, **mixed)
+        ctx.solve(ft, out=u, tol=args.tol, **fp64)
     torch.cuda.synchronize()
 
-    # ---- timed region: K full solves with the tuned CG launch ------------------------
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = 0
-    for _ in range(args.steps):
-        _, info = ctx.solve(ft, out=u, tol=args.tol)
-        iters += info[0]["iters"]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    solve_s = (t1 - t0) / args.steps
-    it_per_solve = iters / args.steps
-    value = N * iters / (t1 - t0) / 1e9
-
-    # ---- kernel times of the same solves: HIP events around every apply / persistent
-    # CG launch on the launch stream (a separate pass: the events cost a few us each)
-    side_steps = max(3, args.steps // 4)
-    ctx.profile_enable(True)
-    for _ in range(side_steps):
-        ctx.solve(ft, out=u, tol=args.tol)
-    ap_ms, ap_launches, _ = ctx.profile_read(semcond.KERNEL_APPLY)
-    cg_ms, cg_launches, cg_iters = ctx.profile_read(semcond.KERNEL_PCG)
-    ctx.profile_enable(False)
-
-    # ---- the same solves with each launch kind forced --------------------------------
-
-    def timed(**kw):
-        ctx.solve(ft, out=u, tol=args.tol, **kw)
+    def timed(kw, kind):
+        """K solves; the apply launches of `kind` are bracketed by HIP events on
+        the launch stream during the timed solves."""
         torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(side_steps):
-            _, inf = ctx.solve(ft, out=u, tol=args.tol, **kw)
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        applies = 0
+        iters = []
+        for _ in range(args.steps):
+            _, info = ctx.solve(ft, out=u, tol=args.tol, **kw)
+            iters.append([i["iters"] for i in info])
+            applies += sum(i["iters"] + i["outer"] for i in info)
         torch.cuda.synchronize()
-        return (time.perf_counter() - ta) / side_steps, inf
+        dt = time.perf_counter() - t0
+        ms, launches, _ = ctx.profile_read(kind)
+        ctx.profile_enable(False)
+        return dt, applies, iters, info, ms, launches
 
-    step_s, _ = timed(persistent=False)
-    pers_s, _ = timed(persistent=True)
-    # FP32 inner CG + FP64 iterative refinement
-    mixed_s, minfo = timed(precision=semcond.PREC_MIXED_IR)
+    # ---- timed region: K mixed-precision batched solves ---------------------------
+    m_dt, m_applies, m_iters, m_info, m_ms, m_launches = timed(mixed, semcond.KERNEL_APPLY_F32)
+    # ---- the same K solves in plain FP64 -------------------------------------------
+    d_dt, d_applies, d_iters, d_info, d_ms, d_launches = timed(fp64, semcond.KERNEL_APPLY)
+    step_s = m_dt / args.steps
+    f64_s = d_dt / args.steps
+    value = N * m_applies / m_dt / 1e9
 
-    # ---- apply alone (transformed basis, back-to-back), kernel time from events ------
-    xs = torch.randn(Ns, dtype=torch.float64, device="cuda")
+    # Roofline of the dominant kernel (the CG apply): algorithmic bytes per RHS
+    # and application are 3 s N_s (gather of the direction's p and r, store of
+    # q; P^-1 is shared by the RHS and left out); the applications are the RHS'
+    # CG iterations (an RHS that has stopped is skipped in the launch).
+    rhs_its_m = sum(sum(x) for x in m_iters)
+    rhs_its_d = sum(sum(x) for x in d_iters)
+    bytes_m = 3 * 4 * Ns * rhs_its_m
+    bytes_d = 3 * 8 * Ns * rhs_its_d
+    ach_m = bytes_m / (m_ms / 1e3) / 1e9
+    ach_d = bytes_d / (d_ms / 1e3) / 1e9
+    copy_gbs = copy_bandwidth(torch)
+    traffic = stored_traffic()
+    # launches count every dispatch, also those in which some RHS have stopped (the
+    # time per launch is an average over them); the counter traffic is per full
+    # launch (all 16 RHS active), next to algorithmic_bytes_per_full_launch
+    roof = {"bound": "hbm", "achieved": ach_m, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_m / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per full launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": DOMINANT.replace(" ", ""), "launches": m_launches,
+            "kernel_us_per_launch": m_ms * 1e3 / max(m_launches, 1),
+            "algorithmic_bytes_per_launch": bytes_m / max(m_launches, 1),
+            "rhs_applications": rhs_its_m, "bytes_per_rhs_application": 3 * 4 * Ns,
+            "algorithmic_bytes_per_full_launch": 3 * 4 * Ns * k,
+            "copy_gbs_measured": copy_gbs, "frac_of_measured_copy": ach_m / copy_gbs}
+    roof64 = {"bound": "hbm", "achieved": ach_d, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_d / HBM_PEAK_GBS,
+              "kernel": "k_apply_tpt<double,%d,true,false>" % NI4, "launches": d_launches,
+              "kernel_us_per_launch": d_ms * 1e3 / max(d_launches, 1),
+              "algorithmic_bytes_per_launch": bytes_d / max(d_launches, 1),
+              "rhs_applications": rhs_its_d, "bytes_per_rhs_application": 3 * 8 * Ns}
+
+    # ---- standalone applies of all 16 RHS (transformed basis), HIP-event kernel time
+    ks64 = _apply_rate(ctx, semcond, torch, k=k, reps=10)
+    xs = torch.randn((Ns, k), dtype=torch.float32, device="cuda")
     ys = torch.empty_like(xs)
-    for _ in range(10):
-        ctx.apply(xs, out=ys)
-    torch.cuda.synchronize()
-    ctx.profile_enable(True)
-    for _ in range(args.apply_reps):
-        ctx.apply(xs, out=ys)
-    pa_ms, pa_launches, _ = ctx.profile_read(semcond.KERNEL_APPLY)
-    ctx.profile_enable(False)
-    kern_s = pa_ms / 1e3 / max(pa_launches, 1)
-    # the same apply with a cold last-level cache: 512 MiB written between launches
-    flush = torch.empty((512 << 20) // 8, dtype=torch.float64, device="cuda")
-    ctx.profile_enable(True)
-    for rep in range(20):
-        flush.fill_(float(rep))
-        ctx.apply(xs, out=ys)
-    pc_ms, pc_launches, _ = ctx.profile_read(semcond.KERNEL_APPLY)
-    ctx.profile_enable(False)
-    cold_s = pc_ms / 1e3 / max(pc_launches, 1)
-    # STREAM-style copy on this GPU (1 GiB read + 1 GiB written), next to the nominal peak
-    ca = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-    cb = torch.empty_like(ca)
     for _ in range(3):
-        cb.copy_(ca)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        cb.copy_(ca)
-    e1.record()
+        ctx.apply(xs, out=ys)
     torch.cuda.synchronize()
-    copy_gbs = 2 * ca.numel() * 8 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
-    del flush, ca, cb
+    ctx.profile_enable(True)
+    for _ in range(10):
+        ctx.apply(xs, out=ys)
+    ms32, n32, _ = ctx.profile_read(semcond.KERNEL_APPLY_F32)
+    ctx.profile_enable(False)
+    ks32 = ms32 / 1e3 / max(n32, 1)
+    del xs, ys
+    # ---- one persistent (cooperative, one launch per solve) CG run of each precision
+    pers = {}
+    for name, kw in () if args.no_persistent else (("f64", dict(precision=semcond.PREC_F64)),
+                                                   ("mixed", dict(precision=semcond.PREC_MIXED_IR))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, pinfo = ctx.solve(ft, out=u, tol=args.tol, persistent=True, **kw)
+        torch.cuda.synchronize()
+        pers[name + "_ms_per_rhs"] = (time.perf_counter() - t0) * 1e3 / k
+    ctx.close()
+    del ft, u
+    torch.cuda.empty_cache()
 
-    # Roofline of the dominant kernel of the timed solves.  Algorithmic FP64 bytes
-    # (k = 1): the CG apply gathers p, r and P^-1 (it forms the direction) and
-    # produces q: 4 N_s (its per-side slot stores are an implementation choice and
-    # show in the counter traffic, not here); the persistent CG per iteration
-    # moves 13 N_s (apply 4; step: reads r, q, P^-1, p, x and writes q, p, x, r).
-    if cg_ms >= ap_ms:
-        dom = {"kernel": "k_pcg_persistent<double,7,%d>" % tS, "ms": cg_ms, "launches": cg_launches,
-               "bytes": 13 * 8 * Ns * cg_iters, "traffic": None}
-    else:
-        # one full apply per CG iteration; the launches queued after convergence
-        # leave at once, their (small) time stays in the total
-        full = int(round(it_per_solve * side_steps))
-        dom = {"kernel": "k_apply_tpt<double,7,true,true>", "ms": ap_ms, "launches": full,
-               "bytes": 4 * 8 * Ns * full, "traffic": stored_traffic(), "early_exit_launches": ap_launches - full}
-    dom_achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
-    apply_bytes = 2 * 8 * Ns
-    apply_achieved = apply_bytes / kern_s / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -536,40 +616,42 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": solve_s * 1e3,
+        "ms_per_step": step_s * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 operator and inner CG, f64 refinement",
         "data": "synthetic",
-        "config": {"workload": "BT solve to 1e-10: 16^3 uniform elements, p=8, lambda=1e-3, unit cube, "
-                               "Dirichlet, one N(0,1) nodal RHS (seeded)",
-                   "p": 8, "n_e": ctx.n_e, "N": N, "N_s": Ns, "k": 1, "tol": args.tol,
+        "config": {"workload": "mixed-precision batched BT solve to 1e-10: 24^3 uniform elements, p=12, "
+                               "lambda=1, unit cube, Dirichlet, k=16 N(0,1) nodal RHS (seeded)",
+                   "p": 12, "n_e": 13824, "N": N, "N_s": Ns, "k": k, "tol": args.tol,
                    "parallelism": "single GPU"},
-        "iterations": it_per_solve,
-        "ns_per_dof_iter": solve_s / (N * it_per_solve) * 1e9,
-        "cg_launch": {"tuned": "stepwise" if tS == 0 else "persistent S=%d G=%d" % (tS, tG),
-                      "stepwise_ms_per_solve": step_s * 1e3, "persistent_ms_per_solve": pers_s * 1e3},
-        "mixed_ir": {"ms_per_solve": mixed_s * 1e3, "speedup_vs_fp64": solve_s / mixed_s,
-                     "inner_iterations": minfo[0]["iters"], "outer_steps": minfo[0]["outer"],
-                     "rel_res": minfo[0]["rel_res"]},
-        "roofline": {"bound": "hbm", "achieved": dom_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom_achieved / HBM_PEAK_GBS, "traffic": dom["traffic"],
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": dom["kernel"], "launches": dom["launches"],
-                     "bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
-                     "kernel_us_per_launch": dom["ms"] * 1e3 / max(dom["launches"], 1),
-                     "early_exit_launches": dom.get("early_exit_launches", 0),
-                     "copy_gbs_measured": copy_gbs, "frac_of_measured_copy": dom_achieved / copy_gbs},
-        "apply_roofline": {"bound": "hbm", "achieved": apply_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": apply_achieved / HBM_PEAK_GBS, "kernel": "k_apply_tpt<double,7,false,false>",
-                           "kernel_us": kern_s * 1e6, "gdof_s": N / kern_s / 1e9,
-                           "bytes_per_launch": apply_bytes, "cold_cache_kernel_us": cold_s * 1e6,
-                           "cold_cache_frac": apply_bytes / cold_s / 1e9 / HBM_PEAK_GBS},
+        "ms_per_rhs": step_s * 1e3 / k,
+        "ns_per_dof_iter": m_dt / (N * m_applies) * 1e9,
+        "mixed": {"inner_iterations_per_rhs": [i["iters"] for i in m_info],
+                  "outer_steps_per_rhs": [i["outer"] for i in m_info],
+                  "rel_res_max": max(i["rel_res"] for i in m_info)},
+        "f64": {"ms_per_step": f64_s * 1e3, "ms_per_rhs": f64_s * 1e3 / k,
+                "gdof_s": N * d_applies / d_dt / 1e9, "ns_per_dof_iter": d_dt / (N * d_applies) * 1e9,
+                "iterations_per_rhs": [i["iters"] for i in d_info],
+                "rel_res_max": max(i["rel_res"] for i in d_info)},
+        "mixed_speedup_vs_f64": f64_s / step_s,
+        "roofline": roof,
+        "roofline_f64_cg_apply": roof64,
+        "apply_k16": {"f64": {"kernel": "k_apply_tpt<double,%d,false,false>" % NI4, "us": ks64 * 1e6,
+                              "gdof_s": N * k / ks64 / 1e9, "gbs": 2 * 8 * Ns * k / ks64 / 1e9,
+                              "hbm_frac": 2 * 8 * Ns * k / ks64 / 1e9 / HBM_PEAK_GBS},
+                      "f32": {"kernel": "k_apply_tpt<float,%d,false,false>" % NI4, "us": ks32 * 1e6,
+                              "gdof_s": N * k / ks32 / 1e9, "gbs": 2 * 4 * Ns * k / ks32 / 1e9,
+                              "hbm_frac": 2 * 4 * Ns * k / ks32 / 1e9 / HBM_PEAK_GBS}},
+        "persistent_cg": pers,
     }
+    if not args.no_config2:
+        out["config2"] = config2_line(args, semcond, torch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wmesh, args.cpu_seconds)
-    ctx.close()
+        full, one = cpu_baseline_config4(wmesh, args.cpu_seconds)
+        out["cpu_baseline"] = full
+        out["cpu_baseline_1core"] = one
     print(json.dumps(out))
 
 

@@ -389,8 +389,9 @@ int semcond_autotune(semcond_ctx* ctx, int k, int dtype, const char* cache_path,
 
 /*
  * Kernel tracing.  While enabled, every launch of the condensed-apply kernel
- * (SEMCOND_KERNEL_APPLY: inside semcond_apply and the stepwise CG) and of the
- * persistent CG kernel (SEMCOND_KERNEL_PCG) is bracketed by two HIP events
+ * (inside semcond_apply and the stepwise CG; SEMCOND_KERNEL_APPLY for FP64
+ * operands, SEMCOND_KERNEL_APPLY_F32 for FP32) and of the persistent CG
+ * kernel (SEMCOND_KERNEL_PCG) is bracketed by two HIP events
  * recorded on the launch stream.  semcond_profile_enable resets the counters;
  * semcond_profile_read synchronises the recorded events and returns the summed
  * kernel time in milliseconds and the number of launches of `kernel` since the
@@ -399,6 +400,7 @@ int semcond_autotune(semcond_ctx* ctx, int k, int dtype, const char* cache_path,
  */
 #define SEMCOND_KERNEL_APPLY 0
 #define SEMCOND_KERNEL_PCG   1
+#define SEMCOND_KERNEL_APPLY_F32 2
 int semcond_profile_enable(semcond_ctx* ctx, int enable);
 int semcond_profile_read(semcond_ctx* ctx, int kernel, double* ms, int64_t* launches, int64_t* iters);
 

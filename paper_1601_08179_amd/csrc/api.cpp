@@ -82,8 +82,8 @@ struct semcond_ctx {
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
     std::vector<int> ev_kind;    // kernel id per pair
     size_t ev_used = 0;          // events recorded since the last read
-    double prof_ms[2] = {0.0, 0.0};
-    int64_t prof_launches[2] = {0, 0};
+    double prof_ms[3] = {0.0, 0.0, 0.0};       // by kernel id: FP64 apply, persistent CG, FP32 apply
+    int64_t prof_launches[3] = {0, 0, 0};
     int64_t prof_iters = 0;
     // deterministic assembly: every apply, condensation and CG loop sums the
     // element rows of shared nodes through per-side slots in a fixed order
@@ -307,7 +307,7 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, do
         a.face_slots = face_slots;
     }
     if (c->prof) {
-        int rc = profile_begin(c, SEMCOND_KERNEL_APPLY, st);
+        int rc = profile_begin(c, sizeof(T) == 4 ? SEMCOND_KERNEL_APPLY_F32 : SEMCOND_KERNEL_APPLY, st);
         if (rc) return rc;
         HIPCHK(c, launch_apply<T>(a, c->n_e, st));
         return profile_end(c, st);
@@ -977,15 +977,16 @@ int semcond_profile_enable(semcond_ctx* c, int enable) {
     int rc = profile_flush(c);
     if (rc) return rc;
     c->prof = enable != 0;
-    c->prof_ms[0] = c->prof_ms[1] = 0.0;
-    c->prof_launches[0] = c->prof_launches[1] = 0;
+    c->prof_ms[0] = c->prof_ms[1] = c->prof_ms[2] = 0.0;
+    c->prof_launches[0] = c->prof_launches[1] = c->prof_launches[2] = 0;
     c->prof_iters = 0;
     return SEMCOND_OK;
 }
 
 int semcond_profile_read(semcond_ctx* c, int kernel, double* ms, int64_t* launches, int64_t* iters) {
     if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
-    if (kernel != SEMCOND_KERNEL_APPLY && kernel != SEMCOND_KERNEL_PCG) return fail(c, SEMCOND_EINVAL, "bad kernel id");
+    if (kernel != SEMCOND_KERNEL_APPLY && kernel != SEMCOND_KERNEL_PCG && kernel != SEMCOND_KERNEL_APPLY_F32)
+        return fail(c, SEMCOND_EINVAL, "bad kernel id");
     int rc = profile_flush(c);
     if (rc) return rc;
     if (ms) *ms = c->prof_ms[kernel];

@@ -15,14 +15,14 @@ import weakref
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsemcond.so")
+LIB_PATH = os.environ.get("SEMCOND_LIBRARY") or os.path.join(HERE, "libsemcond.so")
 
 OK, ENOTCONV, EINVAL, ENOMEM, EDEVICE, EBREAKDOWN, ENONFINITE = 0, 1, -1, -2, -3, -4, -5
 F64, F32 = 0, 1
 PHYSICAL, TRANSFORMED = 0, 1
 COEF_TO_TRANSFORMED, COEF_TO_PHYSICAL, DUAL_TO_TRANSFORMED, DUAL_TO_PHYSICAL = 0, 1, 2, 3
 PREC_F64, PREC_F32, PREC_MIXED_IR = 0, 1, 2
-KERNEL_APPLY, KERNEL_PCG = 0, 1
+KERNEL_APPLY, KERNEL_PCG, KERNEL_APPLY_F32 = 0, 1, 2
 CG_STEPWISE, CG_PERSISTENT, CG_AUTO = 0, 1, -1
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
