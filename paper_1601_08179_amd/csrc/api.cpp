@@ -356,7 +356,7 @@ int scratch_for_cubes(semcond_ctx* c, int* grid, double** scratch) {
 }
 
 // fhat (FP64, transformed) = condensed RHS of nodal f.
-int condense_rhs64(semcond_ctx* c, const double* f, double* fhat, int k, hipStream_t st) {
+int condense_rhs64(semcond_ctx* c, const double* f, double* fhat, int k, hipStream_t st, SkelStride sk = {}) {
     int grid;
     double* scratch;
     int rc = scratch_for_cubes(c, &grid, &scratch);
@@ -374,7 +374,7 @@ int condense_rhs64(semcond_ctx* c, const double* f, double* fhat, int k, hipStre
     } else {
         HIPCHK(c, launch_fill<double>(fhat, c->N_s * k, 0.0, st));
     }
-    HIPCHK(c, launch_condense_rhs(c->geo, c->t64.tab, f, c->N, fhat, k, scratch, grid, slots, st));
+    HIPCHK(c, launch_condense_rhs(c->geo, c->t64.tab, f, c->N, fhat, k, scratch, grid, slots, st, sk));
     return SEMCOND_OK;
 }
 
@@ -1484,7 +1484,12 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
     CgWork w;
     rc = cg_state(c, k, 0, &w);
     if (rc) return rc;
-    rc = condense_rhs64(c, (const double*)f, b, k, st);
+    // Without prescribed Dirichlet values the condensed right-hand side is
+    // written RHS-major [k][N_s] straight away (the layout of the conjugate
+    // gradients), and the post-processing reads the solution in that layout.
+    const bool rmaj = k > 1 && !o.g_dirichlet;
+    const SkelStride rm{1, Ns};
+    rc = condense_rhs64(c, (const double*)f, b, k, st, rmaj ? rm : SkelStride{});
     if (rc) return rc;
     // Prescribed Dirichlet values: g~ = T^-1 g on the Dirichlet entities (zero
     // elsewhere; the transform keeps every entity to itself), and the lift
@@ -1508,7 +1513,7 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
         HIPCHK(c, launch_mask_nodes(c->L, q, k, KEEP_FREE, st));
     }
     // the conjugate gradients run on RHS-major vectors [k][N_s]
-    if (k > 1) {
+    if (k > 1 && !rmaj) {
         HIPCHK(c, launch_transpose<double>(b, p, Ns, k, st));
         std::swap(b, p);
     }
@@ -1636,25 +1641,34 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
         }
     }
 
-    // back to [N_s][k], the physical basis and the nodal array (Algorithm 4, second loop)
+    // the physical basis and the nodal array (Algorithm 4, second loop), from the
+    // RHS-major solution, or from its [N_s][k] copy with prescribed values
     double* xs = x;
-    if (k > 1) {
+    SkelStride xl{};
+    if (rmaj) {
+        xl = rm;
+    } else if (k > 1) {
         HIPCHK(c, launch_transpose<double>(x, q, k, Ns, st));
         xs = q;
     }
     if (gl) HIPCHK(c, launch_axpy(xs, gl, 1.0, (int64_t)nv, st));  // u~ = unknowns + g~
     const int keep = gl ? 1 : 0;
-    HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.S, xs, p, k, st));
-    HIPCHK(c, launch_skel_to_nodal(c->L, p, (double*)u, c->N, k, keep, st));
+    HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.S, xs, p, k, st, xl));
+    HIPCHK(c, launch_skel_to_nodal(c->L, p, (double*)u, c->N, k, keep, st, xl));
     if (o.recover_interior) {
         int grid;
         double* scratch;
         rc = scratch_for_cubes(c, &grid, &scratch);
         if (rc) return rc;
         HIPCHK(c, launch_recover_interior(c->geo, c->t64.tab, (const double*)f, c->N, xs, (double*)u, k, scratch,
-                                          grid, keep, st));
+                                          grid, keep, st, xl));
     }
-    if (o.skel_out) HIPCHK(c, hipMemcpyAsync(o.skel_out, xs, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (o.skel_out) {
+        if (rmaj)
+            HIPCHK(c, launch_transpose<double>(xs, (double*)o.skel_out, k, Ns, st));
+        else
+            HIPCHK(c, hipMemcpyAsync(o.skel_out, xs, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
     HIPCHK(c, hipStreamSynchronize(st));
     int worst = SEMCOND_OK;
     for (int i = 0; i < k; ++i) {

@@ -8,6 +8,18 @@
 
 namespace semcond {
 
+// Layout of a skeleton multivector of k RHS: value (node, r) at node * ns +
+// r * rs.  ns = 0 stands for node-major [N_s][k] (ns = k, rs = 1); RHS-major
+// [k][N_s] is ns = 1, rs = N_s.
+struct SkelStride {
+    uint32_t ns = 0;
+    int64_t rs = 0;
+};
+inline SkelStride skel_stride(SkelStride s, int k) {
+    if (s.ns == 0) return SkelStride{(uint32_t)k, 1};
+    return s;
+}
+
 // Per-RHS scalars of the conjugate gradients (device arrays of k entries).
 struct CgState {
     double* rho;     // r.z
@@ -104,7 +116,8 @@ hipError_t launch_apply_tpt(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t s
 // Basis change of skeleton arrays: per face out = A in A^T over the face's two
 // interior axes, per edge out = A in, vertices copied.  A is n_I x n_I row-major.
 template <typename T>
-hipError_t launch_transform(const Layout& L, const T* A, const T* in, T* out, int k, hipStream_t st);
+hipError_t launch_transform(const Layout& L, const T* A, const T* in, T* out, int k, hipStream_t st,
+                            SkelStride sk = {});
 
 // Assembly R from per-side slots (layout.h), RHS-major [k][qlen]: out(node, r)
 // at node * ns + r * rs, every node written.
@@ -128,10 +141,11 @@ hipError_t launch_precond_invert(const Layout& L, const double* diag, T* pinv, h
 // summed in a fixed order into fhat (every entry written); else fhat (zeroed
 // first) accumulates them with atomics.
 hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
-                               double* fhat, int k, double* scratch, int grid, double* slots, hipStream_t st);
+                               double* fhat, int k, double* scratch, int grid, double* slots, hipStream_t st,
+                               SkelStride sk = {});
 hipError_t launch_condense_rhs_body(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
                                     double* fhat, int k, double* scratch, int grid, double* slots, int64_t qlen,
-                                    hipStream_t st);
+                                    hipStream_t st, SkelStride sk = {});
 int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch);
 
 // Interior recovery (Algorithm 4, second loop): u_I = (S(x)S(x)S) D^-1 (F~_I - H~_IB u~_B),
@@ -140,12 +154,12 @@ int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch);
 // boundary values) instead of 0.
 hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
                                    const double* xskel, double* u, int k, double* scratch, int grid,
-                                   int keep_con, hipStream_t st);
+                                   int keep_con, hipStream_t st, SkelStride sk = {});
 
 // Skeleton <-> nodal copies (FP64).
 // keep_con: copy the values of Dirichlet nodes too (else they are written as 0).
 hipError_t launch_skel_to_nodal(const Layout& L, const double* skel, double* nodal, int64_t N, int k,
-                                int keep_con, hipStream_t st);
+                                int keep_con, hipStream_t st, SkelStride sk = {});
 // Zero the entries of free nodes (keep = constrained) or of Dirichlet nodes
 // (keep = free) of an [N_s][k] array.
 enum KeepNodes { KEEP_FREE = 0, KEEP_CONSTRAINED = 1 };

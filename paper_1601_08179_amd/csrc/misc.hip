@@ -21,7 +21,7 @@ namespace semcond {
 template <typename T>
 __global__ __launch_bounds__(1024) void k_transform_faces(Layout L, const T* __restrict__ A,
                                                           const T* __restrict__ in, T* __restrict__ out,
-                                                          int k, int fpb, int64_t nfaces) {
+                                                          int k, int fpb, int64_t nfaces, uint32_t ns, int64_t rs) {
     extern __shared__ unsigned char smem_raw[];
     T* X = reinterpret_cast<T*>(smem_raw);
     const int NI = L.NI, NI2 = NI * NI;
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(1024) void k_transform_faces(Layout L, const T* __r
     const int s1 = loc / NI, s2 = loc - (loc / NI) * NI;
     const int64_t node = face * NI2 + loc;  // faces are contiguous from oFx = 0
     for (int r = 0; r < k; ++r) {
-        if (valid) X[t] = in[node * k + r];
+        if (valid) X[t] = in[node * ns + r * rs];
         __syncthreads();
         if (valid) {  // along the fast axis: Y(s1, c) = sum_c' A[c][c'] X(s1, c')
             T acc = 0;
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(1024) void k_transform_faces(Layout L, const T* __r
         if (valid) {  // along the slow axis
             T acc = 0;
             for (int m = 0; m < NI; ++m) acc += A[s1 * NI + m] * Y[lf * NI2 + m * NI + s2];
-            out[node * k + r] = acc;
+            out[node * ns + r * rs] = acc;
         }
         __syncthreads();
     }
@@ -52,28 +52,33 @@ __global__ __launch_bounds__(1024) void k_transform_faces(Layout L, const T* __r
 
 template <typename T>
 __global__ void k_transform_edges(Layout L, const T* __restrict__ A, const T* __restrict__ in,
-                                  T* __restrict__ out, int k) {
+                                  T* __restrict__ out, int k, uint32_t ns, int64_t rs) {
     const int64_t nval = (L.Ns - L.oEx) * k;
     const int NI = L.NI;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nval;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t s = L.oEx + idx / k;
-        const int r = (int)(idx % k);
+        // consecutive threads on consecutive entries of the layout
+        const int64_t nv = L.Ns - L.oEx;
+        const bool nm = rs == 1;
+        const int64_t s = L.oEx + (nm ? idx / k : idx % nv);
+        const int r = (int)(nm ? idx % k : idx / nv);
         if (s >= L.oV) {
-            out[s * k + r] = in[s * k + r];
+            out[s * ns + r * rs] = in[s * ns + r * rs];
         } else {
             const int64_t t = s - L.oEx;
             const int64_t base = L.oEx + (t / NI) * NI;
             const int m = (int)(t % NI);
             T acc = 0;
-            for (int m2 = 0; m2 < NI; ++m2) acc += A[m * NI + m2] * in[(base + m2) * k + r];
-            out[s * k + r] = acc;
+            for (int m2 = 0; m2 < NI; ++m2) acc += A[m * NI + m2] * in[(base + m2) * ns + r * rs];
+            out[s * ns + r * rs] = acc;
         }
     }
 }
 
 template <typename T>
-hipError_t launch_transform(const Layout& L, const T* A, const T* in, T* out, int k, hipStream_t st) {
+hipError_t launch_transform(const Layout& L, const T* A, const T* in, T* out, int k, hipStream_t st,
+                            SkelStride sk) {
+    sk = skel_stride(sk, k);
     const int NI2 = L.NI * L.NI;
     const int64_t nfaces = L.oEx / NI2;
     int fpb = 1024 / NI2;
@@ -84,18 +89,18 @@ hipError_t launch_transform(const Layout& L, const T* A, const T* in, T* out, in
     size_t shm = 2 * (size_t)fpb * NI2 * sizeof(T);
     if (blocks > 0)
         hipLaunchKernelGGL(k_transform_faces<T>, dim3((unsigned)blocks), dim3(threads), shm, st, L, A, in,
-                           out, k, fpb, nfaces);
+                           out, k, fpb, nfaces, sk.ns, sk.rs);
     int64_t nval = (L.Ns - L.oEx) * k;
     int eb = (int)((nval + 255) / 256);
     if (eb > 65536) eb = 65536;
-    if (eb > 0) hipLaunchKernelGGL(k_transform_edges<T>, dim3(eb), dim3(256), 0, st, L, A, in, out, k);
+    if (eb > 0) hipLaunchKernelGGL(k_transform_edges<T>, dim3(eb), dim3(256), 0, st, L, A, in, out, k, sk.ns, sk.rs);
     return hipGetLastError();
 }
 
 template hipError_t launch_transform<double>(const Layout&, const double*, const double*, double*, int,
-                                             hipStream_t);
+                                             hipStream_t, SkelStride);
 template hipError_t launch_transform<float>(const Layout&, const float*, const float*, float*, int,
-                                            hipStream_t);
+                                            hipStream_t, SkelStride);
 
 // ---------------------------------------------------------------------------
 // Assembly R from per-side slots (layout.h): out(node, r) = the node's slots of
@@ -289,7 +294,8 @@ __device__ void cube_transformed_rhs(double* cube, const Geo& g, const DevTab<do
 
 __global__ __launch_bounds__(256) void k_condense_rhs(Geo g, DevTab<double> tab, const double* __restrict__ f,
                                                       int64_t N, double* __restrict__ fhat, int k, double* scratch,
-                                                      double* __restrict__ slots, int64_t qlen) {
+                                                      double* __restrict__ slots, int64_t qlen, uint32_t ns,
+                                                      int64_t rs) {
     extern __shared__ double cube_lds[];
     const Layout& L = g.L;
     const int p = L.p, n = p + 1, NI = L.NI, NI2 = NI * NI;
@@ -358,7 +364,7 @@ __global__ __launch_bounds__(256) void k_condense_rhs(Geo g, DevTab<double> tab,
                 if (slots)
                     slots[(int64_t)r * qlen + slot_addr(L, (uint32_t)(base + loc), entity_slot(ent))] = val;
                 else
-                    atomic_add(&fhat[(base + loc) * k + r], val);
+                    atomic_add(&fhat[(base + loc) * ns + r * rs], val);
             }
             __syncthreads();
         }
@@ -419,6 +425,74 @@ __device__ void rhs_lines(double* C, const double* A, int lo) {
     }
 }
 
+// ---- The same line transforms on the FP64 matrix cores (n_I >= 8) ---------
+// For one axis the n_I x n_I matrix M acts on the interior part of every line:
+// with the lines as rows, Y = X M^T is a (lines x n_I) by (n_I x n_I) product,
+// done in 16 x 16 x 4 FP64 MFMA steps: 16 lines per tile (M dimension), the
+// interior index in chunks of 4 (K), the output index (N, n_I <= 15 < 16).
+// Operand layout of v_mfma_f64_16x16x4f64 for lane l: A[l % 16][l / 16],
+// B[l / 16][l % 16]; result v of the double4 is D[l / 16 + 4 v][l % 16]
+// (checked on gfx950 with distinct row and column codes).
+// The waves of the workgroup take the tiles in turn; a tile reads and writes
+// only its own lines, so one barrier after the pass suffices.
+
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <int NI>
+constexpr bool rhs_mfma() { return NI >= 8; }
+
+// B operand of the line transform by M (row-major n_I x n_I): lane l holds
+// M[o][i], o = l % 16, i = 4 c + l / 16, for chunk c (0 outside the matrix).
+template <int NI>
+struct LineMat {
+    double b[(NI + 3) / 4];
+};
+
+template <int NI>
+__device__ inline void line_mat(LineMat<NI>& B, const double* __restrict__ M) {
+    const int lane = threadIdx.x & 63, o = lane & 15, i0 = lane >> 4;
+#pragma unroll
+    for (int c = 0; c < (NI + 3) / 4; ++c) {
+        const int i = 4 * c + i0;
+        B.b[c] = (o < NI && i < NI) ? M[o * NI + i] : 0.0;
+    }
+}
+
+template <int n, int AXIS>
+__device__ inline int line_base(int u, int v) {
+    return AXIS == 0 ? (u * n + v) * n : (AXIS == 1 ? u * n * n + v : u * n + v);
+}
+
+// x <- M x on the interior entries (1 .. n_I) of every line along AXIS whose
+// two fixed indices lie in [lo, n - lo).
+template <int NI, int AXIS>
+__device__ void rhs_lines_mfma(double* C, const LineMat<NI>& B, int lo) {
+    constexpr int n = NI + 2;
+    constexpr int st = AXIS == 0 ? 1 : (AXIS == 1 ? n : n * n);
+    constexpr int NC = (NI + 3) / 4;
+    const int m = n - 2 * lo, nl = m * m, ntile = (nl + 15) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    for (int tile = wave; tile < ntile; tile += nw) {
+        const int La = tile * 16 + row;
+        const bool va = La < nl;
+        const int ba = va ? line_base<n, AXIS>(La / m + lo, La % m + lo) : 0;
+        mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int i = 4 * c + kq;
+            const double a = (va && i < NI) ? C[ba + (1 + i) * st] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B.b[c], acc, 0, 0, 0);
+        }
+        // lane: output index o = row of lines tile*16 + kq + 4 v
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int L = tile * 16 + kq + 4 * v;
+            if (L < nl && row < NI) C[line_base<n, AXIS>(L / m + lo, L % m + lo) + (1 + row) * st] = acc[v];
+        }
+    }
+}
+
 // C(kk,jj,ii) = J w_ii w_jj w_kk f(node) of RHS r, then (S1 (x) S1 (x) S1)-type
 // transform by sm.A along the three axes (all lines).
 template <int NI>
@@ -433,19 +507,31 @@ __device__ void rhs_cube(RhsSmem<NI>& sm, const Geo& g, const double* __restrict
         sm.C[idx] = J * sm.w[ii] * sm.w[jj] * sm.w[kk] * f[(int64_t)r * N + node];
     }
     __syncthreads();
-    rhs_lines<NI, 0>(sm.C, sm.A, 0);
-    __syncthreads();
-    rhs_lines<NI, 1>(sm.C, sm.A, 0);
-    __syncthreads();
-    rhs_lines<NI, 2>(sm.C, sm.A, 0);
-    __syncthreads();
+    if constexpr (rhs_mfma<NI>()) {
+        LineMat<NI> B;
+        line_mat<NI>(B, sm.A);
+        rhs_lines_mfma<NI, 0>(sm.C, B, 0);
+        __syncthreads();
+        rhs_lines_mfma<NI, 1>(sm.C, B, 0);
+        __syncthreads();
+        rhs_lines_mfma<NI, 2>(sm.C, B, 0);
+        __syncthreads();
+    } else {
+        rhs_lines<NI, 0>(sm.C, sm.A, 0);
+        __syncthreads();
+        rhs_lines<NI, 1>(sm.C, sm.A, 0);
+        __syncthreads();
+        rhs_lines<NI, 2>(sm.C, sm.A, 0);
+        __syncthreads();
+    }
 }
 
 template <int NI>
 __global__ __launch_bounds__(kRhsThreads) void k_condense_rhs_t(Geo g, DevTab<double> tab,
                                                                 const double* __restrict__ f, int64_t N,
                                                                 double* __restrict__ fhat, int k,
-                                                                double* __restrict__ slots, int64_t qlen) {
+                                                                double* __restrict__ slots, int64_t qlen,
+                                                                uint32_t ns, int64_t rs) {
     constexpr int n = NI + 2, p = NI + 1, NI2 = NI * NI;
     constexpr int nslot = 6 * NI2 + 12 * NI + 8;
     __shared__ RhsSmem<NI> sm;
@@ -465,7 +551,7 @@ __global__ __launch_bounds__(kRhsThreads) void k_condense_rhs_t(Geo g, DevTab<do
         // interior: V = D^-1 F~_I
         for (int idx = threadIdx.x; idx < NI2 * NI; idx += blockDim.x) {
             const int i = idx % NI, j = (idx / NI) % NI, kk = idx / NI2;
-            C(1 + kk, 1 + j, 1 + i) /= d[0] + d[1] * sm.lam[i] + d[2] * sm.lam[j] + d[3] * sm.lam[kk];
+            C(1 + kk, 1 + j, 1 + i) *= recip<double>(d[0] + d[1] * sm.lam[i] + d[2] * sm.lam[j] + d[3] * sm.lam[kk]);
         }
         __syncthreads();
         for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
@@ -519,7 +605,7 @@ __global__ __launch_bounds__(kRhsThreads) void k_condense_rhs_t(Geo g, DevTab<do
             if (slots)
                 slots[(int64_t)r * qlen + slot_addr(L, (uint32_t)(base + loc), entity_slot(ent))] = val;
             else
-                atomic_add(&fhat[(base + loc) * k + r], val);
+                atomic_add(&fhat[(base + loc) * ns + r * rs], val);
         }
     }
 #undef C
@@ -529,7 +615,8 @@ template <int NI>
 __global__ __launch_bounds__(kRhsThreads) void k_recover_interior_t(Geo g, DevTab<double> tab,
                                                                     const double* __restrict__ f, int64_t N,
                                                                     const double* __restrict__ xs,
-                                                                    double* __restrict__ u, int k, int keep_con) {
+                                                                    double* __restrict__ u, int k, int keep_con,
+                                                                    uint32_t ns, int64_t rs) {
     constexpr int n = NI + 2, p = NI + 1, NI2 = NI * NI;
     __shared__ RhsSmem<NI> sm;
     __shared__ int64_t fb[6];
@@ -549,7 +636,7 @@ __global__ __launch_bounds__(kRhsThreads) void k_recover_interior_t(Geo g, DevTa
     }
     // forward transform by S^T first; S for the back transform afterwards
 #define C(kk, jj, ii) sm.C[((kk) * n + (jj)) * n + (ii)]
-#define UF(face, s1, s2) (fcon[face] ? 0.0 : xs[(fb[face] + (int64_t)(s1) * NI + (s2)) * k + r])
+#define UF(face, s1, s2) (fcon[face] ? 0.0 : xs[(fb[face] + (int64_t)(s1) * NI + (s2)) * ns + r * rs])
     {
         const int r = blockIdx.y;  // one workgroup per (element, right-hand side)
         __syncthreads();  // face bases and flags stored
@@ -562,16 +649,27 @@ __global__ __launch_bounds__(kRhsThreads) void k_recover_interior_t(Geo g, DevTa
                               d[2] * (sm.a[j] * UF(2, kk, i) + sm.b[j] * UF(3, kk, i)) +
                               d[3] * (sm.a[kk] * UF(4, j, i) + sm.b[kk] * UF(5, j, i));
             const double D = d[0] + d[1] * sm.lam[i] + d[2] * sm.lam[j] + d[3] * sm.lam[kk];
-            C(1 + kk, 1 + j, 1 + i) = (C(1 + kk, 1 + j, 1 + i) - uc) / D;
+            C(1 + kk, 1 + j, 1 + i) = (C(1 + kk, 1 + j, 1 + i) - uc) * recip<double>(D);
         }
         for (int t = threadIdx.x; t < NI * NI; t += blockDim.x) sm.A[t] = tab.S[t];  // read only after the barrier
         __syncthreads();
-        rhs_lines<NI, 0>(sm.C, sm.A, 1);
-        __syncthreads();
-        rhs_lines<NI, 1>(sm.C, sm.A, 1);
-        __syncthreads();
-        rhs_lines<NI, 2>(sm.C, sm.A, 1);
-        __syncthreads();
+        if constexpr (rhs_mfma<NI>()) {
+            LineMat<NI> B;
+            line_mat<NI>(B, sm.A);
+            rhs_lines_mfma<NI, 0>(sm.C, B, 1);
+            __syncthreads();
+            rhs_lines_mfma<NI, 1>(sm.C, B, 1);
+            __syncthreads();
+            rhs_lines_mfma<NI, 2>(sm.C, B, 1);
+            __syncthreads();
+        } else {
+            rhs_lines<NI, 0>(sm.C, sm.A, 1);
+            __syncthreads();
+            rhs_lines<NI, 1>(sm.C, sm.A, 1);
+            __syncthreads();
+            rhs_lines<NI, 2>(sm.C, sm.A, 1);
+            __syncthreads();
+        }
         for (int idx = threadIdx.x; idx < NI2 * NI; idx += blockDim.x) {
             const int i = idx % NI, j = (idx / NI) % NI, kk = idx / NI2;
             const int64_t node =
@@ -595,16 +693,19 @@ int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch) {
 #define RHS_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
 
 hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
-                               double* fhat, int k, double* scratch, int grid, double* slots, hipStream_t st) {
+                               double* fhat, int k, double* scratch, int grid, double* slots, hipStream_t st,
+                               SkelStride sk) {
+    sk = skel_stride(sk, k);
     const int64_t qlen = slot_len(g.L);
-    hipError_t e = launch_condense_rhs_body(g, tab, f, N, fhat, k, scratch, grid, slots, qlen, st);
+    hipError_t e = launch_condense_rhs_body(g, tab, f, N, fhat, k, scratch, grid, slots, qlen, st, sk);
     if (e != hipSuccess || !slots) return e;
-    return launch_slot_sum<double>(g.L, slots, qlen, fhat, k, (uint32_t)k, 1, st);
+    return launch_slot_sum<double>(g.L, slots, qlen, fhat, k, sk.ns, (uint32_t)sk.rs, st);
 }
 
 hipError_t launch_condense_rhs_body(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
                                     double* fhat, int k, double* scratch, int grid, double* slots, int64_t qlen,
-                                    hipStream_t st) {
+                                    hipStream_t st, SkelStride sk) {
+    sk = skel_stride(sk, k);
     if (g.L.NI <= 15) {
         const int64_t ne = (int64_t)g.L.n1 * g.L.n2 * g.L.n3;
         if (ne <= 0) return hipSuccess;
@@ -613,7 +714,7 @@ hipError_t launch_condense_rhs_body(const Geo& g, const DevTab<double>& tab, con
 #define X(NI)                                                                                                    \
     case NI:                                                                                                     \
         hipLaunchKernelGGL(k_condense_rhs_t<NI>, dim3((unsigned)ne, (unsigned)k), dim3(kRhsThreads), 0, st, g, tab, \
-                           f, N, fhat, k, slots, qlen);                                                          \
+                           f, N, fhat, k, slots, qlen, sk.ns, sk.rs);                                            \
         break;
             RHS_CASES(X)
 #undef X
@@ -622,7 +723,8 @@ hipError_t launch_condense_rhs_body(const Geo& g, const DevTab<double>& tab, con
     }
     const int n = g.L.p + 1;
     const size_t shm = scratch ? 0 : (size_t)n * n * n * sizeof(double);
-    hipLaunchKernelGGL(k_condense_rhs, dim3(grid), dim3(256), shm, st, g, tab, f, N, fhat, k, scratch, slots, qlen);
+    hipLaunchKernelGGL(k_condense_rhs, dim3(grid), dim3(256), shm, st, g, tab, f, N, fhat, k, scratch, slots, qlen,
+                       sk.ns, sk.rs);
     return hipGetLastError();
 }
 
@@ -636,7 +738,7 @@ hipError_t launch_condense_rhs_body(const Geo& g, const DevTab<double>& tab, con
 __global__ __launch_bounds__(256) void k_recover_interior(Geo g, DevTab<double> tab, const double* __restrict__ f,
                                                           int64_t N, const double* __restrict__ xs,
                                                           double* __restrict__ u, int k, double* scratch,
-                                                          int keep_con) {
+                                                          int keep_con, uint32_t ns, int64_t rs) {
     extern __shared__ double cube_lds[];
     __shared__ int64_t fb[6];
     __shared__ int fc[6];
@@ -658,7 +760,7 @@ __global__ __launch_bounds__(256) void k_recover_interior(Geo g, DevTab<double> 
         }
         for (int r = 0; r < k; ++r) {
             cube_transformed_rhs(cube, g, tab, tab.St, f, N, r, e1, e2, e3);
-#define UF(face, s1, s2) ((fc[face] && !keep_con) ? 0.0 : xs[(fb[face] + (int64_t)(s1) * NI + (s2)) * k + r])
+#define UF(face, s1, s2) ((fc[face] && !keep_con) ? 0.0 : xs[(fb[face] + (int64_t)(s1) * NI + (s2)) * ns + r * rs])
             for (int idx = threadIdx.x; idx < NI2 * NI; idx += blockDim.x) {
                 const int i = idx % NI, j = (idx / NI) % NI, kk = idx / NI2;
                 const double uc = d[1] * (tab.a[i] * UF(0, kk, j) + tab.b[i] * UF(1, kk, j)) +
@@ -689,7 +791,8 @@ __global__ __launch_bounds__(256) void k_recover_interior(Geo g, DevTab<double> 
 
 hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
                                    const double* xskel, double* u, int k, double* scratch, int grid,
-                                   int keep_con, hipStream_t st) {
+                                   int keep_con, hipStream_t st, SkelStride sk) {
+    sk = skel_stride(sk, k);
     if (g.L.NI <= 15) {
         const int64_t ne = (int64_t)g.L.n1 * g.L.n2 * g.L.n3;
         if (ne <= 0) return hipSuccess;
@@ -698,7 +801,7 @@ hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, cons
 #define X(NI)                                                                                                  \
     case NI:                                                                                                   \
         hipLaunchKernelGGL(k_recover_interior_t<NI>, dim3((unsigned)ne, (unsigned)k), dim3(kRhsThreads), 0, st, g,  \
-                           tab, f, N, xskel, u, k, keep_con);                                                   \
+                           tab, f, N, xskel, u, k, keep_con, sk.ns, sk.rs);                                     \
         break;
             RHS_CASES(X)
 #undef X
@@ -708,7 +811,7 @@ hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, cons
     const int n = g.L.p + 1;
     const size_t shm = scratch ? 0 : (size_t)n * n * n * sizeof(double);
     hipLaunchKernelGGL(k_recover_interior, dim3(grid), dim3(256), shm, st, g, tab, f, N, xskel, u, k, scratch,
-                       keep_con);
+                       keep_con, sk.ns, sk.rs);
     return hipGetLastError();
 }
 
@@ -724,11 +827,11 @@ __device__ inline int64_t skel_nodal_index(const Layout& L, int64_t s, bool* con
 }
 
 __global__ void k_skel_to_nodal(Layout L, const double* __restrict__ skel, double* __restrict__ nodal, int64_t N,
-                                int k, int keep_con) {
+                                int k, int keep_con, uint32_t ns, int64_t rs) {
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < L.Ns; s += (int64_t)gridDim.x * blockDim.x) {
         bool con;
         const int64_t g = skel_nodal_index(L, s, &con);
-        for (int r = 0; r < k; ++r) nodal[(int64_t)r * N + g] = (con && !keep_con) ? 0.0 : skel[s * k + r];
+        for (int r = 0; r < k; ++r) nodal[(int64_t)r * N + g] = (con && !keep_con) ? 0.0 : skel[s * ns + r * rs];
     }
 }
 
@@ -764,9 +867,10 @@ static int grid_for(int64_t n, int threads) {
 }
 
 hipError_t launch_skel_to_nodal(const Layout& L, const double* skel, double* nodal, int64_t N, int k,
-                                int keep_con, hipStream_t st) {
+                                int keep_con, hipStream_t st, SkelStride sk) {
+    sk = skel_stride(sk, k);
     hipLaunchKernelGGL(k_skel_to_nodal, dim3(grid_for(L.Ns, 256)), dim3(256), 0, st, L, skel, nodal, N, k,
-                       keep_con);
+                       keep_con, sk.ns, sk.rs);
     return hipGetLastError();
 }
 

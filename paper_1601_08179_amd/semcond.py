@@ -222,8 +222,10 @@ class Context:
             self._h = None
         _live.discard(self)
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound as a default: module globals may already be cleared when a
+        # context is collected during interpreter shutdown)
+        if _finalizing():
             return
         try:
             self.close()
