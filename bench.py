@@ -208,6 +208,52 @@ def suite(args):
             del ft, gt, u
             ctx.close()
             torch.cuda.empty_cache()
+    if "E" in args.suite:
+        # Operator experiment of Sec. 7: 8^3 uniform elements (n_e = 512), lambda =
+        # pi, p = 2..32, one RHS: TPT (transformed basis), TPC and MMC (physical
+        # basis) apply times from HIP events over repeated launches, and their
+        # precomputation times (context creation for TPT and TPC, plus the class
+        # matrices for MMC).
+        import math
+
+        def ev_time(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps / 1e3
+
+        for p in range(2, 33):
+            wm = W.mesh(p, (8, 8, 8), lam=math.pi)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx = semcond.Context(wm)
+            torch.cuda.synchronize()
+            setup_tpt = time.perf_counter() - t0
+            x = torch.randn(ctx.N_s, dtype=torch.float64, device="cuda")
+            y = torch.empty_like(x)
+            t_tpt = ev_time(lambda: ctx.apply(x, out=y), 50)
+            t_tpc = ev_time(lambda: ctx.apply_variant(x, semcond.VARIANT_TPC, out=y), 20)
+            rec = {"case": "operator experiment (Sec. 7): 8^3 elements, lambda=pi", "p": p, "n_e": 512,
+                   "N": ctx.N, "N_s": ctx.N_s, "tpt_us": t_tpt * 1e6, "tpc_us": t_tpc * 1e6,
+                   "tpc_over_tpt": t_tpc / t_tpt, "setup_tpt_ms": setup_tpt * 1e3}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.variant_setup(semcond.VARIANT_MMC)
+            torch.cuda.synchronize()
+            rec["setup_mmc_ms"] = (time.perf_counter() - t0) * 1e3
+            t_mmc = ev_time(lambda: ctx.apply_variant(x, semcond.VARIANT_MMC, out=y), 20)
+            rec["mmc_us"] = t_mmc * 1e6
+            rec["mmc_over_tpt"] = t_mmc / t_tpt
+            rec["mmc_over_tpc"] = t_mmc / t_tpc
+            emit(rec)
+            del x, y
+            ctx.close()
+            torch.cuda.empty_cache()
     if "5" in args.suite:
         wmesh, f, t = W.config5()
         ctx = semcond.Context(wmesh)
@@ -485,7 +531,8 @@ def main():
     ap.add_argument("--suite", default="", help="extra measurements instead of the default line: "
                     "any of 3 (p/AR sweep), 4 (16 RHS, every launch kind), 5 (differentiable solve), "
                     "D (the paper's solver experiment with inhomogeneous Dirichlet values), S (its "
-                    "element-count scaling), e.g. --suite 345DS")
+                    "element-count scaling), E (the operator experiment: TPT, TPC, MMC at p = 2..32), "
+                    "e.g. --suite 345DSE")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the dispatches the rocprofv3 counter runs read")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

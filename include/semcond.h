@@ -256,6 +256,30 @@ int semcond_apply(semcond_ctx* ctx, const void* u, void* v, int k, int dtype, in
 int semcond_apply_noalloc(semcond_ctx* ctx, const void* u, void* v, int k, int dtype, int basis,
                           void* stream);
 
+/*
+ * The two other evaluations of the condensed operator compared in Sec. 7
+ * (Fig. 4, operation-count table), for measurement and cross-checks; both
+ * give the same operator as semcond_apply in the physical basis, FP64.
+ *   SEMCOND_VARIANT_TPC: Algorithm 3 in the physical basis with the
+ *     tensor-product suboperators of Table 1 (primary part from the 1D
+ *     matrices; condensed part through the inner eigenspace with S^T M_II
+ *     face transforms), about 12 n_I^3 + 37 n_I^3 multiplications per element.
+ *   SEMCOND_VARIANT_MMC: Algorithm 2 with the primary part included: one
+ *     precomputed dense element matrix (the Schur complement on all n_B
+ *     boundary nodes) per class of elements with equal metric, applied by one
+ *     DGEMM per class (rocBLAS), 2 n_B^2 flops per element.
+ * semcond_variant_setup does the precomputation (MMC: the class matrices,
+ * n_classes n_B^2 doubles of device memory, EINVAL above 16 GiB; TPC:
+ * nothing) and must precede semcond_apply_variant for MMC; it synchronises
+ * the stream.  semcond_apply_variant: u, v device [N_s][k] FP64 in the
+ * physical basis, must not overlap; constrained slots of u are ignored and
+ * those of v written 0.  Stream-ordered.  Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+#define SEMCOND_VARIANT_TPC 1
+#define SEMCOND_VARIANT_MMC 2
+int semcond_variant_setup(semcond_ctx* ctx, int variant, void* stream);
+int semcond_apply_variant(semcond_ctx* ctx, const void* u, void* v, int k, int variant, void* stream);
+
 /* Basis change of skeleton arrays (direction: SEMCOND_COEF_TO_TRANSFORMED, ...).
  * in, out: device [N_s][k] of dtype, must not overlap. */
 int semcond_transform(semcond_ctx* ctx, const void* in, void* out, int k, int dtype,

@@ -19,6 +19,8 @@
 #include "pcg_persistent.h"
 #include "tables.h"
 
+#include <rocblas/rocblas.h>
+
 #include <chrono>
 #include <cstdio>
 #include <map>
@@ -92,6 +94,14 @@ struct semcond_ctx {
     // device address of the library's fixed apply workspace on this context's
     // device (semcond_apply_noalloc), looked up at create
     void* noalloc_ws = nullptr;
+    // MMC variant (semcond_variant_setup): one dense Schur complement per class
+    // of elements with equal metric, column-major n_B x n_B, elements in class
+    // order (col_of[e]), and the class ranges of that order
+    double* mmc_H = nullptr;
+    int* mmc_col = nullptr;
+    std::vector<int64_t> mmc_start, mmc_count;
+    rocblas_handle blas = nullptr;
+    Buffer ws_mmc;  // UL and VL, n_B x n_e k each
 };
 
 namespace {
@@ -923,6 +933,8 @@ int apply_public(semcond_ctx* c, const T* u, T* v, int k, int basis, T* ws, hipS
     return SEMCOND_OK;
 }
 
+int create_context(const semcond_mesh* m, void* stream, semcond_ctx** out, bool needs_definite);
+
 }  // namespace
 
 extern "C" {
@@ -968,6 +980,10 @@ int semcond_destroy(semcond_ctx* c) {
     for (hipEvent_t e : c->poll_ev)
         if (e) hipEventDestroy(e);
     for (hipEvent_t e : c->ev) hipEventDestroy(e);
+    hipFree(c->mmc_H);
+    hipFree(c->mmc_col);
+    hipFree(c->ws_mmc.ptr);
+    if (c->blas) rocblas_destroy_handle(c->blas);
     delete c;
     return SEMCOND_OK;
 }
@@ -996,6 +1012,17 @@ int semcond_profile_read(semcond_ctx* c, int kernel, double* ms, int64_t* launch
 }
 
 int semcond_create(const semcond_mesh* m, void* stream, semcond_ctx** out) {
+    return create_context(m, stream, out, true);
+}
+
+}  // extern "C"
+
+namespace {
+
+// semcond_create; without the check that a problem with lambda = 0
+// everywhere has a Dirichlet face (one-element contexts whose operator is
+// only applied, never solved: the MMC class matrices)
+int create_context(const semcond_mesh* m, void* stream, semcond_ctx** out, bool needs_definite) {
     if (!out) return fail(nullptr, SEMCOND_EINVAL, "out is NULL");
     *out = nullptr;
     if (!m) return fail(nullptr, SEMCOND_EINVAL, "mesh is NULL");
@@ -1010,7 +1037,8 @@ int semcond_create(const semcond_mesh* m, void* stream, semcond_ctx** out) {
     }
     if (ne > (int64_t(1) << 26)) return fail(nullptr, SEMCOND_EINVAL, "too many elements (max 2^26)");
     if (m->dirichlet_mask > 63u) return fail(nullptr, SEMCOND_EINVAL, "dirichlet_mask has bits above 5");
-    if (const char* msg = check_coefficients(ne, m->dirichlet_mask, m->lambda, m->lambda_e, m->dcoef_e))
+    if (const char* msg = check_coefficients(ne, needs_definite ? m->dirichlet_mask : 1u, m->lambda, m->lambda_e,
+                                             m->dcoef_e))
         return fail(nullptr, SEMCOND_EINVAL, msg);
 
     semcond_ctx* c = new (std::nothrow) semcond_ctx();
@@ -1092,6 +1120,10 @@ int semcond_create(const semcond_mesh* m, void* stream, semcond_ctx** out) {
     *out = c;
     return SEMCOND_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int semcond_sizes(const semcond_ctx* c, int64_t* N, int64_t* N_s, int64_t* N_free, int64_t* n_e) {
     if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
@@ -1683,6 +1715,160 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
     }
     if (worst != SEMCOND_OK) fail(c, worst, "solve did not converge for every right-hand side");
     return worst;
+}
+
+// ---------------------------------------------------------------------------
+// Operator variants of Sec. 7 (physical basis, FP64)
+// ---------------------------------------------------------------------------
+
+int semcond_variant_setup(semcond_ctx* c, int variant, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (variant == SEMCOND_VARIANT_TPC) return SEMCOND_OK;  // nothing beyond the 1D tables
+    if (variant != SEMCOND_VARIANT_MMC) return fail(c, SEMCOND_EINVAL, "unknown operator variant");
+    hipStream_t st = S(stream);
+    const int NI = c->L.NI;
+    const int64_t nB = 6 * (int64_t)NI * NI + 12 * NI + 8;
+    // element classes: equal metric coefficients (the device's own values)
+    std::vector<double> hd(4 * (size_t)c->n_e);
+    {
+        double* dd = nullptr;
+        HIPCHK(c, hipMalloc(&dd, hd.size() * sizeof(double)));
+        hipError_t e1 = launch_elem_metrics(c->geo, dd, st);
+        hipError_t e2 = e1 == hipSuccess ? hipMemcpyAsync(hd.data(), dd, hd.size() * sizeof(double),
+                                                          hipMemcpyDeviceToHost, st)
+                                         : e1;
+        hipError_t e3 = e2 == hipSuccess ? hipStreamSynchronize(st) : e2;
+        hipFree(dd);
+        HIPCHK(c, e3);
+    }
+    std::map<std::vector<double>, int> cls;
+    std::vector<int> cl(c->n_e);
+    std::vector<std::vector<double>> keys;
+    for (int64_t e = 0; e < c->n_e; ++e) {
+        std::vector<double> key(hd.begin() + 4 * e, hd.begin() + 4 * e + 4);
+        auto it = cls.find(key);
+        if (it == cls.end()) {
+            it = cls.emplace(key, (int)keys.size()).first;
+            keys.push_back(key);
+        }
+        cl[e] = it->second;
+    }
+    const int nc = (int)keys.size();
+    const double mbytes = (double)nc * nB * nB * sizeof(double);
+    if (mbytes > 16.0 * (1 << 30))
+        return fail(c, SEMCOND_EINVAL, "MMC: the element matrices of " + std::to_string(nc) + " classes would need " +
+                                           std::to_string(mbytes / (1 << 30)) + " GiB (limit 16)");
+    std::vector<int64_t> start(nc, 0), count(nc, 0);
+    for (int64_t e = 0; e < c->n_e; ++e) ++count[cl[e]];
+    for (int q = 1; q < nc; ++q) start[q] = start[q - 1] + count[q - 1];
+    std::vector<int> col(c->n_e);
+    {
+        std::vector<int64_t> next = start;
+        for (int64_t e = 0; e < c->n_e; ++e) col[e] = (int)next[cl[e]]++;
+    }
+    hipFree(c->mmc_H);
+    hipFree(c->mmc_col);
+    c->mmc_H = nullptr;
+    c->mmc_col = nullptr;
+    HIPCHK(c, hipMalloc(&c->mmc_H, (size_t)mbytes));
+    HIPCHK(c, hipMalloc(&c->mmc_col, col.size() * sizeof(int)));
+    HIPCHK(c, hipMemcpy(c->mmc_col, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice));
+    // Each class's matrix: the condensed operator of one element with that
+    // metric and no Dirichlet face, applied in the physical basis to the unit
+    // vectors of its n_B boundary nodes (a one-element skeleton lists them in
+    // the local slot order of the gather).
+    const int kc = (int)std::min<int64_t>(nB, 256);
+    double *dU = nullptr, *dV = nullptr;
+    HIPCHK(c, hipMalloc(&dU, (size_t)nB * kc * sizeof(double)));
+    HIPCHK(c, hipMalloc(&dV, (size_t)nB * kc * sizeof(double)));
+    std::vector<double> hU((size_t)nB * kc);
+    int rc = SEMCOND_OK;
+    for (int q = 0; q < nc && rc == SEMCOND_OK; ++q) {
+        double w2[1] = {2.0};
+        semcond_mesh m1{};
+        m1.p = c->p;
+        m1.n[0] = m1.n[1] = m1.n[2] = 1;
+        m1.widths[0] = m1.widths[1] = m1.widths[2] = w2;
+        m1.lambda = 0.0;
+        m1.lambda_e = nullptr;
+        m1.dcoef_e = keys[q].data();
+        m1.dirichlet_mask = 0;
+        semcond_ctx* one = nullptr;
+        rc = create_context(&m1, stream, &one, false);
+        if (rc) {
+            fail(c, rc, "MMC: element context: " + g_last_error);
+            break;
+        }
+        double* Hq = c->mmc_H + (size_t)q * nB * nB;
+        for (int64_t j0 = 0; j0 < nB && rc == SEMCOND_OK; j0 += kc) {
+            const int kk = (int)std::min<int64_t>(kc, nB - j0);
+            std::fill(hU.begin(), hU.end(), 0.0);
+            for (int t = 0; t < kk; ++t) hU[(size_t)(j0 + t) * kk + t] = 1.0;
+            hipError_t he = hipMemcpyAsync(dU, hU.data(), (size_t)nB * kk * sizeof(double), hipMemcpyHostToDevice, st);
+            if (he != hipSuccess) {
+                rc = fail(c, SEMCOND_EDEVICE, "MMC: upload failed");
+                break;
+            }
+            rc = semcond_apply(one, dU, dV, kk, SEMCOND_F64, SEMCOND_PHYSICAL, stream);
+            if (rc) {
+                fail(c, rc, "MMC: element apply: " + std::string(semcond_last_error(one)));
+                break;
+            }
+            he = launch_transpose<double>(dV, Hq + (size_t)j0 * nB, nB, kk, st);
+            if (he == hipSuccess) he = hipStreamSynchronize(st);
+            if (he != hipSuccess) rc = fail(c, SEMCOND_EDEVICE, "MMC: column copy failed");
+        }
+        semcond_destroy(one);
+    }
+    hipFree(dU);
+    hipFree(dV);
+    if (rc) return rc;
+    c->mmc_start = start;
+    c->mmc_count = count;
+    if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
+        c->blas = nullptr;
+        return fail(c, SEMCOND_EDEVICE, "rocblas_create_handle failed");
+    }
+    return SEMCOND_OK;
+}
+
+int semcond_apply_variant(semcond_ctx* c, const void* u, void* v, int k, int variant, void* stream) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (!u || !v) return fail(c, SEMCOND_EINVAL, "u and v must be device pointers");
+    if (u == v) return fail(c, SEMCOND_EINVAL, "u and v must not overlap");
+    int rc = check_k(c, k);
+    if (rc) return rc;
+    hipStream_t st = S(stream);
+    const int64_t Ns = c->N_s;
+    if (variant == SEMCOND_VARIANT_TPC) {
+        HIPCHK(c, launch_fill<double>((double*)v, Ns * k, 0.0, st));
+        HIPCHK(c, launch_apply_tpc(c->geo, c->t64.tab, c->t64.K, (const double*)u, (double*)v, k, st));
+        return SEMCOND_OK;
+    }
+    if (variant != SEMCOND_VARIANT_MMC) return fail(c, SEMCOND_EINVAL, "unknown operator variant");
+    if (!c->mmc_H) return fail(c, SEMCOND_EINVAL, "MMC: call semcond_variant_setup first");
+    const int NI = c->L.NI;
+    const int64_t nB = 6 * (int64_t)NI * NI + 12 * NI + 8;
+    const size_t cols = (size_t)c->n_e * k;
+    rc = grow(c, c->ws_mmc, 2 * nB * cols * sizeof(double));
+    if (rc) return rc;
+    double* UL = (double*)c->ws_mmc.ptr;
+    double* VL = UL + nB * cols;
+    HIPCHK(c, launch_mmc_gather(c->L, c->mmc_col, (const double*)u, UL, k, st));
+    if (rocblas_set_stream(c->blas, st) != rocblas_status_success)
+        return fail(c, SEMCOND_EDEVICE, "rocblas_set_stream failed");
+    const double one = 1.0, zero = 0.0;
+    for (size_t q = 0; q < c->mmc_start.size(); ++q) {
+        const int64_t c0 = c->mmc_start[q] * k, nq = c->mmc_count[q] * k;
+        if (nq == 0) continue;
+        if (rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)nB, (rocblas_int)nq,
+                          (rocblas_int)nB, &one, c->mmc_H + (size_t)q * nB * nB, (rocblas_int)nB, UL + c0 * nB,
+                          (rocblas_int)nB, &zero, VL + c0 * nB, (rocblas_int)nB) != rocblas_status_success)
+            return fail(c, SEMCOND_EDEVICE, "rocblas_dgemm failed");
+    }
+    HIPCHK(c, launch_fill<double>((double*)v, Ns * k, 0.0, st));
+    HIPCHK(c, launch_mmc_scatter(c->L, c->mmc_col, VL, (double*)v, k, st));
+    return SEMCOND_OK;
 }
 
 }  // extern "C"

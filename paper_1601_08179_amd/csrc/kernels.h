@@ -156,6 +156,17 @@ hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, cons
                                    const double* xskel, double* u, int k, double* scratch, int grid,
                                    int keep_con, hipStream_t st, SkelStride sk = {});
 
+// Operator variants of Sec. 7 (variants.hip), FP64, physical basis, skeleton
+// vectors [N_s][k]: TPC (Algorithm 3 with the suboperators of Table 1; v is
+// accumulated into, zero it first) and the gather / scatter around the MMC
+// class GEMMs (UL, VL column-major n_B x n_e k, column col_of[e] * k + r).
+size_t tpc_smem_bytes(int p);
+hipError_t launch_apply_tpc(const Geo& g, const DevTab<double>& tab, const double* K, const double* u, double* v,
+                            int k, hipStream_t st);
+hipError_t launch_elem_metrics(const Geo& g, double* d, hipStream_t st);
+hipError_t launch_mmc_gather(const Layout& L, const int* col_of, const double* u, double* UL, int k, hipStream_t st);
+hipError_t launch_mmc_scatter(const Layout& L, const int* col_of, const double* VL, double* v, int k, hipStream_t st);
+
 // Skeleton <-> nodal copies (FP64).
 // keep_con: copy the values of Dirichlet nodes too (else they are written as 0).
 hipError_t launch_skel_to_nodal(const Layout& L, const double* skel, double* nodal, int64_t N, int k,

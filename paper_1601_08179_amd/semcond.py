@@ -23,6 +23,7 @@ PHYSICAL, TRANSFORMED = 0, 1
 COEF_TO_TRANSFORMED, COEF_TO_PHYSICAL, DUAL_TO_TRANSFORMED, DUAL_TO_PHYSICAL = 0, 1, 2, 3
 PREC_F64, PREC_F32, PREC_MIXED_IR = 0, 1, 2
 KERNEL_APPLY, KERNEL_PCG, KERNEL_APPLY_F32 = 0, 1, 2
+VARIANT_TPC, VARIANT_MMC = 1, 2
 CG_STEPWISE, CG_PERSISTENT, CG_AUTO = 0, 1, -1
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -63,6 +64,9 @@ _SIGS = {
                                      ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "semcond_apply_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "semcond_variant_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "semcond_apply_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_void_p]),
     "semcond_transform": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "semcond_precond_diag": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
@@ -305,6 +309,24 @@ class Context:
             raise ValueError("out must match u")
         _check(_lib.semcond_apply(self._h, _dev(u, "u"), _dev(out, "out"), k, _dtype_code(u), basis,
                                   _stream(stream)), self._h)
+        return out
+
+    def variant_setup(self, variant, stream=None):
+        """Precomputation of an operator variant of Sec. 7 (MMC: element matrices)."""
+        _check(_lib.semcond_variant_setup(self._h, int(variant), _stream(stream)), self._h)
+
+    def apply_variant(self, u, variant, out=None, stream=None):
+        """TPC or MMC evaluation of the condensed operator, physical basis, FP64 [N_s] or [N_s][k]."""
+        import torch
+        k = self._k_skel(u, "u")
+        if u.dtype != torch.float64:
+            raise TypeError("u must be float64")
+        if out is None:
+            out = torch.empty_like(u)
+        if out.shape != u.shape or out.dtype != u.dtype:
+            raise ValueError("out must match u")
+        _check(_lib.semcond_apply_variant(self._h, _dev(u, "u"), _dev(out, "out"), k, int(variant),
+                                          _stream(stream)), self._h)
         return out
 
     def transform(self, x, direction, out=None, stream=None):
