@@ -153,6 +153,16 @@ typedef struct {
                             /*   per step.  Two solves of the same input on one device   */
                             /*   then return the same bits.  Default 0 (atomics: results */
                             /*   may differ in the last bits between runs)               */
+    int coarse;             /* 1: two-level preconditioner, the BT diagonal (Sec. 8) plus */
+                            /*   a coarse correction P A_0^-1 P^T on the trilinear        */
+                            /*   functions of the element mesh (values at the free        */
+                            /*   element vertices; A_0 the trilinear element matrices     */
+                            /*   with the element metrics, Cholesky-factored once per     */
+                            /*   context and metric), the two-level direction of the      */
+                            /*   multigrid outlook of Sec. 9: iteration counts no longer  */
+                            /*   grow with the element count.  One launch per CG step;    */
+                            /*   EINVAL above 32768 free vertices.  Default 0 (the paper's */
+                            /*   BT preconditioner)                                        */
 } semcond_solve_opts;
 
 #define SEMCOND_CG_STEPWISE   0

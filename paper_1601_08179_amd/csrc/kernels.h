@@ -37,6 +37,9 @@ struct CgState {
     double* rrb;
     int* stall;
     int window;
+    // Nullable, [k]: added to r.z in RED_INIT / RED_RZ (the coarse part
+    // r0 . A_0^-1 r0 of the two-level preconditioner)
+    const double* rz_extra = nullptr;
 };
 
 // Per-iteration view of the CG state for kernels that complete a reduction of
@@ -164,6 +167,19 @@ size_t tpc_smem_bytes(int p);
 hipError_t launch_apply_tpc(const Geo& g, const DevTab<double>& tab, const double* K, const double* u, double* v,
                             int k, hipStream_t st);
 hipError_t launch_elem_metrics(const Geo& g, double* d, hipStream_t st);
+
+// Two-level preconditioner (coarse.hip): vertex coarse space.  tw = [t_0; t_1]
+// (2 n_I doubles), vmap: vertex -> coarse unknown or -1, r0 [k][n0].
+template <typename T>
+hipError_t launch_coarse_restrict(const Layout& L, const double* tw, const int* vmap, int n0, const T* r, int k,
+                                  const int* act, double* r0, hipStream_t st);
+hipError_t launch_coarse_dot(const double* a, const double* b, int n0, int k, double* out, hipStream_t st);
+hipError_t launch_symmetrize_lower(double* A, int n, hipStream_t st);
+// z0 += Ainv r0 (symmetric Ainv, n0 x n0 column-major; r0, z0 [k][n0])
+hipError_t launch_coarse_gemv(const double* Ainv, int n0, const double* r0, int k, double* z0, hipStream_t st);
+template <typename T>
+hipError_t launch_coarse_pupd(const Layout& L, const double* tw, const int* vmap, int n0, const double* z0,
+                              const T* pinv, const T* r, T* p, int k, CgState s, hipStream_t st);
 hipError_t launch_mmc_gather(const Layout& L, const int* col_of, const double* u, double* UL, int k, hipStream_t st);
 hipError_t launch_mmc_scatter(const Layout& L, const int* col_of, const double* VL, double* v, int k, hipStream_t st);
 
@@ -235,11 +251,12 @@ hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int 
 // of stopped right-hand sides return at once.  With qs (nullable) q of edge and
 // vertex nodes (of all nodes with face_slots) is the slot sum of the apply's
 // per-side slots (qs + rhs * qlen, layout.h) and only the q entries that the
-// apply added into are cleared.
+// apply added into are cleared.  p_formed: p already holds the direction the
+// apply used (it is only read), instead of beta p + P^-1 r being formed here.
 template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s,
                           double* partials, const T* qs, int64_t qlen, const Layout& L, int face_slots,
-                          hipStream_t st);
+                          hipStream_t st, bool p_formed = false);
 // The same step with p.q completed by every block from the element energies
 // f.energy (RED_PQ on slot f.rho / f.act; blocks x = 0 store pq, alpha and a
 // breakdown); partials [2][fused_step_blocks(k)][k] of r.z and r.r for the next

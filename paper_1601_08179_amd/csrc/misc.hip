@@ -1100,7 +1100,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __re
     if (t < k) {
         const double t0 = acc[0], t1 = acc[1], t2 = acc[2];
         if (mode == RED_INIT || mode == RED_INIT_KEEP) {
-            const double rz = t0, rr = t1, b2 = t2;
+            const double rz = t0 + (s.rz_extra ? s.rz_extra[r] : 0.0), rr = t1, b2 = t2;
             s.rho[r] = rz;
             s.rr[r] = rr;
             s.bb[r] = b2;
@@ -1133,7 +1133,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __re
             }
             s.alpha[r] = alpha;
         } else {  // RED_RZ
-            const double rz = t0, rr = t1;
+            const double rz = t0 + (s.rz_extra ? s.rz_extra[r] : 0.0), rr = t1;
             double beta = 0.0;
             if (act) {
                 s.iters[r] = its + 1;
@@ -1185,7 +1185,7 @@ __device__ inline bool cg_q_clear(const Layout& L, int64_t n, int face_slots) {
     return !SLOTS || (!face_slots && n < L.oEx);
 }
 
-template <typename T, bool SLOTS>
+template <typename T, bool SLOTS, bool PFORMED = false>
 __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
                                                  T* __restrict__ q, const T* __restrict__ pinv, int64_t Ns, int k,
                                                  CgState s, double* __restrict__ partials, const T* __restrict__ qs,
@@ -1204,8 +1204,13 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
         const T qv = cg_q<T, SLOTS>(q, qs, qlen, L, rhs, idx, n, fsl);
         const T pn = pinv[n];
         if (cg_q_clear<SLOTS>(L, n, fsl)) q[idx] = (T)0;  // q is accumulated from zero by the next apply
-        const T pv = fmadd(beta, p[idx], pn * rv);  // the direction the apply used
-        p[idx] = pv;
+        T pv;
+        if constexpr (PFORMED) {
+            pv = p[idx];  // formed before the apply (two-level preconditioner)
+        } else {
+            pv = fmadd(beta, p[idx], pn * rv);  // the direction the apply used
+            p[idx] = pv;
+        }
         x[idx] += alpha * pv;
         rv -= alpha * qv;
         r[idx] = rv;
@@ -1218,7 +1223,16 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
 
 template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s, double* partials,
-                          const T* qs, int64_t qlen, const Layout& L, int face_slots, hipStream_t st) {
+                          const T* qs, int64_t qlen, const Layout& L, int face_slots, hipStream_t st, bool p_formed) {
+    if (p_formed) {
+        if (qs)
+            hipLaunchKernelGGL((k_cg_step<T, true, true>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q, pinv,
+                               Ns, k, s, partials, qs, qlen, L, face_slots);
+        else
+            hipLaunchKernelGGL((k_cg_step<T, false, true>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q, pinv,
+                               Ns, k, s, partials, qs, qlen, L, face_slots);
+        return hipGetLastError();
+    }
     if (qs)
         hipLaunchKernelGGL((k_cg_step<T, true>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q, pinv, Ns, k, s,
                            partials, qs, qlen, L, face_slots);
@@ -1228,9 +1242,9 @@ hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int
     return hipGetLastError();
 }
 template hipError_t launch_cg_step<double>(double*, double*, double*, double*, const double*, int64_t, int, CgState,
-                                           double*, const double*, int64_t, const Layout&, int, hipStream_t);
+                                           double*, const double*, int64_t, const Layout&, int, hipStream_t, bool);
 template hipError_t launch_cg_step<float>(float*, float*, float*, float*, const float*, int64_t, int, CgState, double*,
-                                          const float*, int64_t, const Layout&, int, hipStream_t);
+                                          const float*, int64_t, const Layout&, int, hipStream_t, bool);
 
 int fused_step_blocks(int k) { return std::max(1, 256 / k); }
 

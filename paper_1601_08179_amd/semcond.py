@@ -41,7 +41,7 @@ class SolveOpts(ctypes.Structure):
                 ("x0", ctypes.c_void_p), ("skel_out", ctypes.c_void_p),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("rhs_dual", ctypes.c_int),
                 ("persistent", ctypes.c_int), ("g_dirichlet", ctypes.c_void_p), ("ir_restart", ctypes.c_int),
-                ("deterministic", ctypes.c_int)]
+                ("deterministic", ctypes.c_int), ("coarse", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -461,10 +461,11 @@ class Context:
     def solve(self, f, out=None, tol=1e-10, max_iter=20000, precision=PREC_F64, check_every=8,
               recover_interior=True, x0=None, skel_out=None, inner_tol=3e-3, max_outer=30,
               rhs_dual=False, persistent=None, stream=None, raise_on_notconv=True, g=None, ir_restart=False,
-              deterministic=False):
+              deterministic=False, coarse=False):
         """Solve for nodal right-hand sides f (k, N) or (N,), FP64.  Returns (u, info).
         ir_restart (MIXED_IR): restart every FP32 inner CG from p = 0 instead of
         continuing its direction across refinement steps.
+        coarse: two-level preconditioner (BT diagonal plus the trilinear coarse correction).
         persistent: True (one persistent CG launch), False (one launch per step) or None
         (the autotuned choice, else one launch per step).  g: optional nodal array like f
         with the prescribed values on the Dirichlet faces (inhomogeneous conditions)."""
@@ -489,6 +490,7 @@ class Context:
         o.persistent = CG_AUTO if persistent is None else (CG_PERSISTENT if persistent else CG_STEPWISE)
         o.ir_restart = 1 if ir_restart else 0
         o.deterministic = 1 if deterministic else 0
+        o.coarse = 1 if coarse else 0
         if g is not None:
             if g.shape != f.shape or g.dtype != torch.float64:
                 raise ValueError("g must match f (shape, float64)")
