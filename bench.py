@@ -201,10 +201,20 @@ def suite(args):
             _, info = ctx.solve(ft, out=u, tol=1e-12, g=gt)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            emit({"case": "element-count scaling (Sec. 8): expansion factor 1, p=16, lambda=0", "n_e": n ** 3,
-                  "N": ctx.N, "iters": info[0]["iters"], "solve_ms": dt * 1e3,
-                  "ns_per_dof_iter": dt / (ctx.N * info[0]["iters"]) * 1e9,
-                  "max_rel_error_vs_exact": float(np.abs(u.cpu().numpy() - uex).max() / np.abs(uex).max())})
+            rec = {"case": "element-count scaling (Sec. 8): expansion factor 1, p=16, lambda=0", "n_e": n ** 3,
+                   "N": ctx.N, "iters": info[0]["iters"], "solve_ms": dt * 1e3,
+                   "ns_per_dof_iter": dt / (ctx.N * info[0]["iters"]) * 1e9,
+                   "max_rel_error_vs_exact": float(np.abs(u.cpu().numpy() - uex).max() / np.abs(uex).max())}
+            # the same solve with the two-level preconditioner (first call builds the coarse matrix)
+            ctx.solve(ft, out=u, tol=1e-12, g=gt, coarse=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info2 = ctx.solve(ft, out=u, tol=1e-12, g=gt, coarse=True)
+            torch.cuda.synchronize()
+            rec["two_level_iters"] = info2[0]["iters"]
+            rec["two_level_solve_ms"] = (time.perf_counter() - t0) * 1e3
+            rec["two_level_max_rel_error_vs_exact"] = float(np.abs(u.cpu().numpy() - uex).max() / np.abs(uex).max())
+            emit(rec)
             del ft, gt, u
             ctx.close()
             torch.cuda.empty_cache()
@@ -527,6 +537,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-config2", action="store_true")
     ap.add_argument("--no-persistent", action="store_true", help="skip the one-launch-per-solve CG runs")
+    ap.add_argument("--no-two-level", action="store_true", help="skip the two-level preconditioner runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--suite", default="", help="extra measurements instead of the default line: "
                     "any of 3 (p/AR sweep), 4 (16 RHS, every launch kind), 5 (differentiable solve), "
@@ -652,6 +663,30 @@ def main():
         _, pinfo = ctx.solve(ft, out=u, tol=args.tol, persistent=True, **kw)
         torch.cuda.synchronize()
         pers[name + "_ms_per_rhs"] = (time.perf_counter() - t0) * 1e3 / k
+    # ---- the two-level preconditioner (BT diagonal + trilinear coarse correction)
+    two = {}
+    if not args.no_two_level:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.solve(ft, out=u, tol=args.tol, precision=semcond.PREC_F64, persistent=False, coarse=True)
+        torch.cuda.synchronize()
+        two["first_solve_ms_incl_setup"] = (time.perf_counter() - t0) * 1e3
+        for name, prec in (("f64", semcond.PREC_F64), ("mixed", semcond.PREC_MIXED_IR)):
+            ctx.solve(ft, out=u, tol=args.tol, precision=prec, persistent=False, coarse=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                _, tinfo = ctx.solve(ft, out=u, tol=args.tol, precision=prec, persistent=False, coarse=True)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            two[name] = {"ms_per_step": dt * 1e3, "ms_per_rhs": dt * 1e3 / k,
+                         "iterations_per_rhs": [i["iters"] for i in tinfo],
+                         "outer_steps_per_rhs": [i["outer"] for i in tinfo],
+                         "rel_res_max": max(i["rel_res"] for i in tinfo)}
+        two["f64_speedup_vs_bt_f64"] = f64_s * 1e3 / two["f64"]["ms_per_step"]
+        two["mixed_speedup_vs_bt_f64"] = f64_s * 1e3 / two["mixed"]["ms_per_step"]
+        two["mixed_speedup_vs_bt_mixed"] = step_s * 1e3 / two["mixed"]["ms_per_step"]
     ctx.close()
     del ft, u
     torch.cuda.empty_cache()
@@ -692,6 +727,7 @@ def main():
                               "gdof_s": N * k / ks32 / 1e9, "gbs": 2 * 4 * Ns * k / ks32 / 1e9,
                               "hbm_frac": 2 * 4 * Ns * k / ks32 / 1e9 / HBM_PEAK_GBS}},
         "persistent_cg": pers,
+        "two_level": two,
     }
     if not args.no_config2:
         out["config2"] = config2_line(args, semcond, torch)
