@@ -25,6 +25,7 @@
 #include <chrono>
 #include <cstdio>
 #include <map>
+#include <unordered_map>
 
 using namespace semcond;
 
@@ -113,6 +114,14 @@ struct semcond_ctx {
     int* c_vmap = nullptr;
     double* c_tw = nullptr;
     Buffer ws_coarse;  // r0, z0 [k][n0], rz_extra [k]
+    // D^-1 of the fast diagonalisation per metric class for the FP32 cube
+    // applies (6 <= n_I <= 15 and at most kMaxDinvClasses classes; dinv_nc = 0:
+    // none, the applies recompute it), and the class of every element
+    int dinv_nc = 0;
+    int dinv_cap = 0;  // classes the table has room for
+    float* d_dinv32 = nullptr;
+    int* d_dcls = nullptr;
+    double* d_dclass = nullptr;  // [cap][4] metric coefficients of the classes
 };
 
 namespace {
@@ -260,6 +269,12 @@ ApplyArgs<T> apply_args(semcond_ctx* c) {
     a.k = 0;
     a.energy = nullptr;
     a.e_begin = 0;
+    if constexpr (sizeof(T) == 4) {
+        if (c->dinv_nc > 0) {
+            a.dinv = c->d_dinv32;
+            a.dcls = c->d_dcls;
+        }
+    }
     return a;
 }
 
@@ -657,6 +672,78 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
     return SEMCOND_OK;
 }
 
+// The element metric coefficients d_e as the kernels compute them, [n_e][4] on the host.
+int element_metrics_host(semcond_ctx* c, hipStream_t st, std::vector<double>& hd) {
+    hd.assign(4 * (size_t)c->n_e, 0.0);
+    double* dd = nullptr;
+    HIPCHK(c, hipMalloc(&dd, hd.size() * sizeof(double)));
+    hipError_t e1 = launch_elem_metrics(c->geo, dd, st);
+    hipError_t e2 =
+        e1 == hipSuccess ? hipMemcpyAsync(hd.data(), dd, hd.size() * sizeof(double), hipMemcpyDeviceToHost, st) : e1;
+    hipError_t e3 = e2 == hipSuccess ? hipStreamSynchronize(st) : e2;
+    hipFree(dd);
+    HIPCHK(c, e3);
+    return SEMCOND_OK;
+}
+
+// Metric classes (elements with bitwise equal d_e) and their D^-1 tables for
+// the FP32 cube applies.  Meshes with more classes than kMaxDinvClasses (for
+// example per-element lambda_e) keep recomputing D^-1 at every point: a table
+// per element would add n_I^3 values of traffic per element and RHS.
+constexpr int kMaxDinvClasses = 64;
+
+int build_dinv_tables(semcond_ctx* c, hipStream_t st) {
+    c->dinv_nc = 0;
+    const int NI = c->L.NI;
+    if (NI < 6 || NI > 15) return SEMCOND_OK;
+    std::vector<double> hd;
+    int rc = element_metrics_host(c, st, hd);
+    if (rc) return rc;
+    struct Key {
+        uint64_t w[4];
+        bool operator==(const Key& o) const { return std::memcmp(w, o.w, sizeof(w)) == 0; }
+    };
+    struct KeyHash {
+        size_t operator()(const Key& k) const {
+            uint64_t h = 1469598103934665603ull;
+            for (uint64_t x : k.w) h = (h ^ x) * 1099511628211ull;
+            return (size_t)h;
+        }
+    };
+    std::unordered_map<Key, int, KeyHash> cls;
+    std::vector<int> cl(c->n_e);
+    std::vector<double> coef;
+    for (int64_t e = 0; e < c->n_e; ++e) {
+        Key key;
+        std::memcpy(key.w, hd.data() + 4 * e, sizeof(key.w));
+        auto it = cls.find(key);
+        if (it == cls.end()) {
+            if ((int)cls.size() == kMaxDinvClasses) return SEMCOND_OK;  // too many: recompute
+            it = cls.emplace(key, (int)cls.size()).first;
+            coef.insert(coef.end(), hd.begin() + 4 * e, hd.begin() + 4 * e + 4);
+        }
+        cl[e] = it->second;
+    }
+    const int nc = (int)cls.size();
+    const size_t n3 = (size_t)NI * NI * NI;
+    if (nc > c->dinv_cap) {
+        hipFree(c->d_dinv32);
+        hipFree(c->d_dclass);
+        c->d_dinv32 = nullptr;
+        c->d_dclass = nullptr;
+        c->dinv_cap = 0;
+        HIPCHK(c, hipMalloc(&c->d_dinv32, nc * n3 * sizeof(float)));
+        HIPCHK(c, hipMalloc(&c->d_dclass, nc * 4 * sizeof(double)));
+        c->dinv_cap = nc;
+    }
+    if (!c->d_dcls) HIPCHK(c, hipMalloc(&c->d_dcls, c->n_e * sizeof(int)));
+    HIPCHK(c, hipMemcpy(c->d_dclass, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_dcls, cl.data(), cl.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, launch_dinv_table(c->t64.tab.lam, NI, c->d_dclass, nc, c->d_dinv32, st));
+    c->dinv_nc = nc;
+    return SEMCOND_OK;
+}
+
 // Upload lambda / lambda_e / dcoef_e (validated by the caller) and rebuild the
 // preconditioner diagonal and its inverses.
 int set_coefficients(semcond_ctx* c, double lambda, const double* lambda_e, const double* dcoef_e, hipStream_t st) {
@@ -682,7 +769,7 @@ int set_coefficients(semcond_ctx* c, double lambda, const double* lambda_e, cons
     HIPCHK(c, launch_precond_diag(c->geo, c->t64.tab, c->d_diag, (double*)c->ws_slots.ptr, st));
     HIPCHK(c, launch_precond_invert<double>(c->L, c->d_diag, c->d_pinv64, st));
     HIPCHK(c, launch_precond_invert<float>(c->L, c->d_diag, c->d_pinv32, st));
-    return SEMCOND_OK;
+    return build_dinv_tables(c, st);
 }
 
 // Validation shared by create and update: returns an error message or NULL.
@@ -852,17 +939,10 @@ int coarse_setup(semcond_ctx* c, hipStream_t st) {
         return fail(c, SEMCOND_EINVAL, "coarse space of " + std::to_string(n0) + " free vertices (limit " +
                                            std::to_string(kMaxCoarse) + ")");
     // element metrics as the kernels use them
-    std::vector<double> hd(4 * (size_t)c->n_e);
+    std::vector<double> hd;
     {
-        double* dd = nullptr;
-        HIPCHK(c, hipMalloc(&dd, hd.size() * sizeof(double)));
-        hipError_t e1 = launch_elem_metrics(c->geo, dd, st);
-        hipError_t e2 = e1 == hipSuccess ? hipMemcpyAsync(hd.data(), dd, hd.size() * sizeof(double),
-                                                          hipMemcpyDeviceToHost, st)
-                                         : e1;
-        hipError_t e3 = e2 == hipSuccess ? hipStreamSynchronize(st) : e2;
-        hipFree(dd);
-        HIPCHK(c, e3);
+        int rc = element_metrics_host(c, st, hd);
+        if (rc) return rc;
     }
     // trilinear element matrices d0 m(x)m(x)m + d1 m(x)m(x)k + d2 m(x)k(x)m +
     // d3 k(x)m(x)m with the 1D linear-element matrices on [-1, 1] (exact, the
@@ -1202,6 +1282,9 @@ int semcond_destroy(semcond_ctx* c) {
     hipFree(c->c_vmap);
     hipFree(c->c_tw);
     hipFree(c->ws_coarse.ptr);
+    hipFree(c->d_dinv32);
+    hipFree(c->d_dcls);
+    hipFree(c->d_dclass);
     if (c->blas) rocblas_destroy_handle(c->blas);
     delete c;
     return SEMCOND_OK;
@@ -1954,17 +2037,10 @@ int semcond_variant_setup(semcond_ctx* c, int variant, void* stream) {
     const int NI = c->L.NI;
     const int64_t nB = 6 * (int64_t)NI * NI + 12 * NI + 8;
     // element classes: equal metric coefficients (the device's own values)
-    std::vector<double> hd(4 * (size_t)c->n_e);
+    std::vector<double> hd;
     {
-        double* dd = nullptr;
-        HIPCHK(c, hipMalloc(&dd, hd.size() * sizeof(double)));
-        hipError_t e1 = launch_elem_metrics(c->geo, dd, st);
-        hipError_t e2 = e1 == hipSuccess ? hipMemcpyAsync(hd.data(), dd, hd.size() * sizeof(double),
-                                                          hipMemcpyDeviceToHost, st)
-                                         : e1;
-        hipError_t e3 = e2 == hipSuccess ? hipStreamSynchronize(st) : e2;
-        hipFree(dd);
-        HIPCHK(c, e3);
+        int rc = element_metrics_host(c, st, hd);
+        if (rc) return rc;
     }
     std::map<std::vector<double>, int> cls;
     std::vector<int> cl(c->n_e);

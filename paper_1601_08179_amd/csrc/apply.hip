@@ -23,10 +23,19 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
     return x * per + (x < rem ? x : rem) + i;
 }
 
+// Waves per SIMD the compiler is asked to fit: the FP32 cube kernels at
+// 9 <= n_I <= 11 hold 80-88 VGPRs, i.e. 5 waves; capping them at 80 (6 waves,
+// at most one spilled value) measured 5 % faster at p = 12 with 16 RHS.  FP64
+// kernels forced to more waves spill and ran slower, and so would the fused
+// CG kernels (FZ).
+template <typename T, int NI, bool FZ>
+constexpr int apply_waves() { return sizeof(T) == 4 && !FZ && NI >= 9 && NI <= 11 ? 6 : 1; }
+
 // FZ (with DIR): the previous CG step's r.z is completed in the kernel
 // (A.fz), a separate instantiation so that plain launches keep their registers.
 template <typename T, int NI, bool DIR, bool FZ>
-__global__ __launch_bounds__(apply_threads(NI)) void k_apply_tpt(ApplyArgs<T> A, int64_t n_elem) {
+__global__ __launch_bounds__(apply_threads(NI)) __attribute__((amdgpu_waves_per_eu(apply_waves<T, NI, FZ>())))
+void k_apply_tpt(ApplyArgs<T> A, int64_t n_elem) {
     constexpr int NT = apply_threads(NI);
     constexpr bool CUBE = NI <= 15;
     const double* beta = A.dir_beta;

@@ -12,7 +12,8 @@
 //  * face -> inner eigenspace maps H~_EF of Table 2, e.g. for face w
 //    d1 I(x)I(x)K~_I0, which are rank-one along the face normal;
 //  * the diagonal D = d0 + d1 Lambda_i + d2 Lambda_j + d3 Lambda_k (eq.
-//    hii_diagonal), inverted point-wise;
+//    hii_diagonal), inverted point-wise, or in FP32 read from a table of
+//    D^-1 per metric class (the paper stores D^-1 per element, Sec. 5);
 //  * eigenspace -> face maps H~_FE (Table 2), line reductions along the normal.
 // Together 13 n_I^3 multiplications per element for the condensed part
 // (Sec. 6) plus O(n_I^2) for the primary part (Table 4).
@@ -31,6 +32,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "cg_device.h"
 #include "device_common.h"
@@ -594,6 +597,22 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
         }
         Gathered<T, DIR> G;
         gather_issue<T, NI, DIR>(A, e, live, r, t, G);
+        // FP32: the thread's D^-1 column from its metric class's table (one
+        // class per workgroup: single-element groups only), loaded with the
+        // gather.  The table holds 1/D rounded once from FP64, which the FP32
+        // CG converges with measurably fewer iterations than with D inverted
+        // in FP32; FP64 keeps the point-wise inverse (measured faster there),
+        // and so do the fused CG kernels (FZ), whose registers are at a limit.
+        constexpr bool TAB = sizeof(T) == 4 && NE == 1 && !FZ;
+        const bool use_tab = TAB && A.dinv != nullptr;
+        T dvr[TAB ? NI : 1];
+        if constexpr (TAB) {
+            if (use_tab && fown) {
+                const T* dtab = A.dinv + (size_t)(A.dcls ? A.dcls[live ? e : 0] : 0) * (NI * NI2) + t;
+#pragma unroll
+                for (int kk = 0; kk < NI; ++kk) dvr[kk] = dtab[kk * NI2];
+            }
+        }
         T bt = DIR ? (T)beta[r] : (T)0;
         if constexpr (DIR && ONE && FZ) {
             {
@@ -633,21 +652,36 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
         const bool fcon[6] = {E.cx0, E.cx1, E.cy0, E.cy1, E.cz0, E.cz1};
 
         // ---- condensed part (Table 2): v = D^-1 sum_f H~_EF u_f on column (k, s1, s2);
-        // the b/t line reductions along k stay in registers
+        // the b/t line reductions along k stay in registers.
         T accb = 0, acct = 0;
         if (fown) {
             const T Dij = d0 + d1 * tl2 + d2 * tl1;
             const T wa = d1 * ta2, wb = d1 * tb2, sa = d2 * ta1, sb = d2 * tb1;
             const T ub = d3 * F[4 * NI2 + t], ut = d3 * F[5 * NI2 + t];
+            auto column = [&](auto use_table) __attribute__((always_inline)) {
 #pragma unroll
-            for (int kk = 0; kk < NI; ++kk) {
-                const T ak = ctA[kk], bk = ctB[kk];
-                const T uc = wa * F[kk * NI + s1] + wb * F[NI2 + kk * NI + s1] + sa * F[2 * NI2 + kk * NI + s2] +
-                             sb * F[3 * NI2 + kk * NI + s2] + ak * ub + bk * ut;
-                const T v = uc * recip<T>(Dij + d3 * ctL[kk]);
-                Wv[kk * NI2 + t] = v;
-                accb += ak * v;
-                acct += bk * v;
+                for (int kk = 0; kk < NI; ++kk) {
+                    const T ak = ctA[kk], bk = ctB[kk];
+                    const T uc = wa * F[kk * NI + s1] + wb * F[NI2 + kk * NI + s1] + sa * F[2 * NI2 + kk * NI + s2] +
+                                 sb * F[3 * NI2 + kk * NI + s2] + ak * ub + bk * ut;
+                    T dv;
+                    if constexpr (decltype(use_table)::value)
+                        dv = dvr[kk];
+                    else
+                        dv = recip<T>(Dij + d3 * ctL[kk]);
+                    const T v = uc * dv;
+                    Wv[kk * NI2 + t] = v;
+                    accb += ak * v;
+                    acct += bk * v;
+                }
+            };
+            if constexpr (TAB) {
+                if (use_tab)
+                    column(std::integral_constant<bool, true>{});
+                else
+                    column(std::integral_constant<bool, false>{});
+            } else {
+                column(std::integral_constant<bool, false>{});
             }
         }
         __syncthreads();
@@ -715,18 +749,33 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                 const int base1 = f1 * NI2 + (par == 0 ? em : em * NI);
                 const int base2 = f2 * NI2 + (par == 2 ? em * NI : em);
                 constexpr int st1_t[3] = {NI, 1, 1}, st2_t[3] = {NI, NI, 1};
-                // both coefficient rows, then the thread's pick (no per-term selects)
-                T l1a = 0, l1b = 0, l2a = 0, l2b = 0;
+                T l1 = 0, l2 = 0;
+                if constexpr (sizeof(T) == 4) {
+                    // each line sum with the coefficient row of the thread's
+                    // edge (a lane-dependent LDS address, read as a broadcast)
+                    const T* c1 = eb0 ? ctB : ctA;
+                    const T* c2 = eb1 ? ctB : ctA;
 #pragma unroll
-                for (int m2 = 0; m2 < NI; ++m2) {
-                    const T am = ctA[m2], bm = ctB[m2];
-                    const T x1 = F[base1 + m2 * st1_t[par]], x2 = F[base2 + m2 * st2_t[par]];
-                    l1a += am * x1;
-                    l1b += bm * x1;
-                    l2a += am * x2;
-                    l2b += bm * x2;
+                    for (int m2 = 0; m2 < NI; ++m2) {
+                        l1 += c1[m2] * F[base1 + m2 * st1_t[par]];
+                        l2 += c2[m2] * F[base2 + m2 * st2_t[par]];
+                    }
+                } else {
+                    // both coefficient rows from uniform addresses, then the
+                    // thread's pick (measured faster in FP64)
+                    T l1a = 0, l1b = 0, l2a = 0, l2b = 0;
+#pragma unroll
+                    for (int m2 = 0; m2 < NI; ++m2) {
+                        const T am = ctA[m2], bm = ctB[m2];
+                        const T x1 = F[base1 + m2 * st1_t[par]], x2 = F[base2 + m2 * st2_t[par]];
+                        l1a += am * x1;
+                        l1b += bm * x1;
+                        l2a += am * x2;
+                        l2b += bm * x2;
+                    }
+                    l1 = eb0 ? l1b : l1a;
+                    l2 = eb1 ? l2b : l2a;
                 }
-                const T l1 = eb0 ? l1b : l1a, l2 = eb1 ? l2b : l2a;
                 const int vlo = par == 0 ? 2 * eb0 + 4 * eb1 : (par == 1 ? eb0 + 4 * eb1 : eb0 + 2 * eb1);
                 const int vhi = vlo + (par == 0 ? 1 : (par == 1 ? 2 : 4));
                 const T ue = UE(q, em);
@@ -745,19 +794,34 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
         // ---- vertices
         if (vown) {
             const int q = t;
-            T sxa = 0, sxb = 0, sya = 0, syb = 0, sza = 0, szb = 0;
+            T sx = 0, sy = 0, sz = 0;
+            if constexpr (sizeof(T) == 4) {
+                const T* cx = vib ? ctB : ctA;
+                const T* cy = vjb ? ctB : ctA;
+                const T* cz = vkb ? ctB : ctA;
 #pragma unroll
-            for (int m2 = 0; m2 < NI; ++m2) {
-                const T am = ctA[m2], bm = ctB[m2];
-                const T x = UE(vjb + 2 * vkb, m2), y = UE(4 + vib + 2 * vkb, m2), z = UE(8 + vib + 2 * vjb, m2);
-                sxa += am * x;
-                sxb += bm * x;
-                sya += am * y;
-                syb += bm * y;
-                sza += am * z;
-                szb += bm * z;
+                for (int m2 = 0; m2 < NI; ++m2) {
+                    sx += cx[m2] * UE(vjb + 2 * vkb, m2);
+                    sy += cy[m2] * UE(4 + vib + 2 * vkb, m2);
+                    sz += cz[m2] * UE(8 + vib + 2 * vjb, m2);
+                }
+            } else {
+                T sxa = 0, sxb = 0, sya = 0, syb = 0, sza = 0, szb = 0;
+#pragma unroll
+                for (int m2 = 0; m2 < NI; ++m2) {
+                    const T am = ctA[m2], bm = ctB[m2];
+                    const T x = UE(vjb + 2 * vkb, m2), y = UE(4 + vib + 2 * vkb, m2), z = UE(8 + vib + 2 * vjb, m2);
+                    sxa += am * x;
+                    sxb += bm * x;
+                    sya += am * y;
+                    syb += bm * y;
+                    sza += am * z;
+                    szb += bm * z;
+                }
+                sx = vib ? sxb : sxa;
+                sy = vjb ? syb : sya;
+                sz = vkb ? szb : sza;
             }
-            const T sx = vib ? sxb : sxa, sy = vjb ? syb : sya, sz = vkb ? szb : sza;
             const T out = (d0 * m02 * m0 + (d1 + d2 + d3) * m02 * K00) * UV(q) +
                           m02 * K0p * (d1 * UV(q ^ 1) + d2 * UV(q ^ 2) + d3 * UV(q ^ 4)) +
                           m02 * (d1 * sx + d2 * sy + d3 * sz);

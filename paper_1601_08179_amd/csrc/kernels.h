@@ -109,12 +109,22 @@ struct ApplyArgs {
     T* slots = nullptr;
     int64_t qlen = 0;
     int face_slots = 0;
+    // Nullable (FP32, 6 <= n_I <= 15): D^-1 of the fast diagonalisation per
+    // metric class, [class][n_I^3] in (k, j, i) order, and the class of every
+    // element; without it D^-1 is recomputed at every eigenspace point.
+    const T* dinv = nullptr;
+    const int* dcls = nullptr;
 };
 
 constexpr int kMaxRhs = 256;  // right-hand sides per call
 
 template <typename T>
 hipError_t launch_apply_tpt(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t st);
+
+// D^-1 tables of nc metric classes (dclass: [nc][4] coefficients d_0..d_3):
+// out = 1 / (d_0 + d_1 Lambda_i + d_2 Lambda_j + d_3 Lambda_k), evaluated in
+// FP64 and rounded once to FP32, [nc][NI][NI][NI] in (k, j, i) order.
+hipError_t launch_dinv_table(const double* lam, int NI, const double* dclass, int nc, float* out, hipStream_t st);
 
 // Basis change of skeleton arrays: per face out = A in A^T over the face's two
 // interior axes, per edge out = A in, vertices copied.  A is n_I x n_I row-major.

@@ -232,6 +232,29 @@ hipError_t launch_precond_invert(const Layout& L, const double* diag, T* pinv, h
 template hipError_t launch_precond_invert<double>(const Layout&, const double*, double*, hipStream_t);
 template hipError_t launch_precond_invert<float>(const Layout&, const double*, float*, hipStream_t);
 
+// D of the fast diagonalisation (eq. hii_diagonal) at every interior point of
+// one metric class, inverted with a correctly rounded FP64 division and
+// rounded to FP32.
+__global__ void k_dinv_table(const double* __restrict__ lam, int NI, const double* __restrict__ dclass, int nc,
+                             float* __restrict__ out) {
+    const int64_t n3 = (int64_t)NI * NI * NI, total = n3 * nc;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = x / n3, r = x - c * n3;
+        const int kk = (int)(r / (NI * NI)), j = (int)((r / NI) % NI), i = (int)(r % NI);
+        const double* d = dclass + 4 * c;
+        const double D = __builtin_fma(d[3], lam[kk], __builtin_fma(d[2], lam[j], __builtin_fma(d[1], lam[i], d[0])));
+        out[x] = (float)(1.0 / D);
+    }
+}
+
+hipError_t launch_dinv_table(const double* lam, int NI, const double* dclass, int nc, float* out, hipStream_t st) {
+    const int64_t total = (int64_t)NI * NI * NI * nc;
+    int64_t b = (total + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b > 0) hipLaunchKernelGGL(k_dinv_table, dim3((unsigned)b), dim3(256), 0, st, lam, NI, dclass, nc, out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Element cube helpers: 1D transforms along the lines of a (p+1)^3 cube,
 // acting on the interior indices 1..n_I of each line.

@@ -42,6 +42,12 @@ MESHES = {
                                lam_e=np.exp(np.random.default_rng(3).uniform(np.log(0.1), np.log(100), 12))),
     "partial_dirichlet_p4": lambda: W.mesh(4, (3, 2, 2), lam=0.3, dirichlet=0b100110),
     "neumann_p6": lambda: W.mesh(6, (2, 2, 1), widths=[[0.3, 0.7], [0.5, 0.5], [0.25]], lam=2.0, dirichlet=0),
+    # 75 metric classes: more than the apply's D^-1 tables take, so the cube
+    # path recomputes D^-1 point by point (the meshes above with 6 <= n_I <= 15
+    # use the per-class tables)
+    "lam_e_p8_classes": lambda: W.mesh(
+        8, (5, 5, 3), widths=[W.geometric_widths(5, 4), W.geometric_widths(5, 4), W.geometric_widths(3, 4)],
+        lam=None, lam_e=np.exp(np.random.default_rng(8).uniform(np.log(0.1), np.log(100), 75)), dirichlet=0b011011),
     "p16_cube_limit": lambda: W.mesh(16, (2, 1, 1), lam=1.0, dirichlet=0b000001),
     "p17_planes": lambda: W.mesh(17, (2, 1, 1), widths=[[0.4, 0.6], [1.0], [0.5]], lam=1.5, dirichlet=0b000010),
 }

@@ -39,10 +39,13 @@ def test_apply_physical_fp64(lib, name):
     for r in range(2):
         e = rel_err(out[free, r], ref[g[free], r])
         assert e <= 1e-12, (name, r, e)
+        # entry by entry too: no single face, edge or vertex row may be off
+        m = np.max(np.abs(out[free, r] - ref[g[free], r])) / np.max(np.abs(ref[g[free], r]))
+        assert m <= 1e-12, (name, r, m)
     assert np.all(out[~free] == 0.0)
 
 
-@pytest.mark.parametrize("name", ["config1", "stretched3_p5", "p17_planes"])
+@pytest.mark.parametrize("name", ["config1", "stretched3_p5", "stretched3_p8", "lam_e_p8_classes", "p17_planes"])
 def test_apply_fp32_reported(lib, name):
     """FP32 operator vs FP64 oracle: reported, loosely bounded."""
     import torch
@@ -149,3 +152,26 @@ def test_apply_batched_equals_single_columns(lib, basis, dtype):
     for r in range(5):
         one = ctx.apply(u[:, r].contiguous(), basis=b).double().cpu().numpy()
         assert np.abs(out[:, r] - one).max() <= tol * np.abs(one).max(), (basis, dtype, r)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_dinv_table_matches_recompute(lib, dtype):
+    """The cube apply reads D^-1 from per-class tables when the mesh has few
+    metric classes and recomputes it otherwise: the same operator once with one
+    class per element width pair (25) and once with 75 classes (lambda_e = 1 + e
+    ulp, equal to 1 within 75 units in the last place) gives the same result to
+    rounding."""
+    import torch
+    from paper_1601_08179_amd import semcond
+    p, n = 10, (5, 5, 3)
+    ne = n[0] * n[1] * n[2]
+    widths = [W.geometric_widths(n[0], 8), W.geometric_widths(n[1], 3), W.uniform_widths(n[2])]
+    one = semcond.Context(W.mesh(p, n, widths=widths, lam=1.0, dirichlet=0b010101))
+    many = semcond.Context(W.mesh(p, n, widths=widths, lam=None,
+                                  lam_e=1.0 + np.arange(ne) * np.finfo(float).eps, dirichlet=0b010101))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    u = torch.as_tensor(np.random.default_rng(5).standard_normal((one.N_s, 3)), device="cuda", dtype=tdt)
+    a = one.apply(u).double().cpu().numpy()
+    b = many.apply(u).double().cpu().numpy()
+    tol = 1e-13 if dtype == "f64" else 2e-6
+    assert rel_err(a, b) <= tol, rel_err(a, b)
