@@ -330,6 +330,9 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, do
     a.energy = energy;
     if (dir_r) {
         if (!dir_beta) return fail(c, SEMCOND_EINVAL, "fused direction needs beta");
+        if (lay != RHS_MAJOR) return fail(c, SEMCOND_EINVAL, "fused direction needs RHS-major vectors");
+        if (slots && face_slots != cg_face_slots<T>())
+            return fail(c, SEMCOND_EINVAL, "CG applies keep face rows in slots exactly in FP32");
         a.dir_r = dir_r;
         a.dir_pinv = pinv<T>(c);
         a.dir_beta = dir_beta;

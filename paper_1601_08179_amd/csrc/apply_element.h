@@ -60,13 +60,16 @@ constexpr int apply_pack(int NI) { return apply_threads(NI) / apply_lanes(NI); }
 // R: the element's row value of a skeleton node, stored into the element's slot
 // of the node (qr, the right-hand side's slots, when set; faces only with
 // face_slots) or added into vr.
-template <bool SL = true, typename T>
+// NS1: a CG apply: node stride 1 (RHS-major vectors) and, with slots, face
+// rows in slots exactly in FP32 (the launcher checks both).
+template <bool SL = true, bool NS1 = false, typename T>
 __device__ inline void out_store(const ApplyArgs<T>& A, T* vr, T* qr, uint32_t node, int slot, T val,
                                  bool face = false) {
-    if (SL && qr && (!face || A.face_slots))
+    const bool fslots = NS1 ? sizeof(T) == 4 : A.face_slots != 0;
+    if (SL && qr && (!face || fslots))
         qr[slot_addr(A.g.L, node, slot)] = val;
     else
-        atomic_add(vr + node * A.ns, val);
+        atomic_add(vr + (NS1 ? node : node * A.ns), val);
 }
 
 // Shared memory of one element.
@@ -185,15 +188,16 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                 node[g] = keep[g] ? ebase[ent] + loc : 0;
             }
             T val[NG];
+            const uint32_t ns = DIR ? 1u : A.ns;  // CG directions are RHS-major
 #pragma unroll
-            for (int g = 0; g < NG; ++g) val[g] = (tid + g * NT < NSLOT) ? A.u[node[g] * A.ns + r * A.rs] : (T)0;
+            for (int g = 0; g < NG; ++g) val[g] = (tid + g * NT < NSLOT) ? A.u[node[g] * ns + r * A.rs] : (T)0;
             if constexpr (DIR) {
                 const T bt = (T)beta[r];
                 T rv[NG], pv[NG];
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
                     const bool in = tid + g * NT < NSLOT;
-                    rv[g] = in ? A.dir_r[node[g] * A.ns + r * A.rs] : (T)0;
+                    rv[g] = in ? A.dir_r[node[g] + r * A.rs] : (T)0;
                     pv[g] = in ? A.dir_pinv[node[g]] : (T)0;
                 }
 #pragma unroll
@@ -321,7 +325,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                               dfast * m0 * (ca[s2] * UE(efl, s1) + cb[s2] * UE(efh, s1)) +
                               dslow * m0 * (ca[s1] * UE(esl, s2) + cb[s1] * UE(esh, s2)) + cond;
                 if (!con && live) {
-                    out_store(A, vr, qr, fbase + (uint32_t)loc, 1 - (f & 1), out, true);
+                    out_store<true, DIR>(A, vr, qr, fbase + (uint32_t)loc, 1 - (f & 1), out, true);
                     en += (double)uf * (double)out;
                 }
             }
@@ -362,7 +366,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                 const T out = (dg0 + dpar * m02 * lam[m]) * ue + m0 * K0p * (do1 * UE(q ^ 1, m) + do2 * UE(q ^ 2, m)) +
                               dpar * m02 * (ca[m] * UV(vlo) + cb[m] * UV(vhi)) + m0 * (do1 * l1 + do2 * l2);
                 if (!econ[6 + q] && live) {
-                    out_store(A, vr, qr, (uint32_t)ebase[6 + q] + (uint32_t)m, (1 - b0) + 2 * (1 - b1), out);
+                    out_store<true, DIR>(A, vr, qr, (uint32_t)ebase[6 + q] + (uint32_t)m, (1 - b0) + 2 * (1 - b1), out);
                     en += (double)ue * (double)out;
                 }
             }
@@ -387,7 +391,7 @@ __device__ void apply_element_planes(const ApplyArgs<T>& A, int64_t e, ApplySmem
                           m02 * K0p * (d1 * UV(q ^ 1) + d2 * UV(q ^ 2) + d3 * UV(q ^ 4)) +
                           m02 * (d1 * sx + d2 * sy + d3 * sz);
             if (!econ[18 + q] && live) {
-                out_store(A, vr, qr, (uint32_t)ebase[18 + q], (1 - ib) + 2 * (1 - jb) + 4 * (1 - kb), out);
+                out_store<true, DIR>(A, vr, qr, (uint32_t)ebase[18 + q], (1 - ib) + 2 * (1 - jb) + 4 * (1 - kb), out);
                 en += (double)UV(q) * (double)out;
             }
         }
@@ -486,9 +490,11 @@ __device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live,
         rr = (T)0;
         pp = (T)0;
         if (on) {
-            u = A.u[node * A.ns + r * A.rs];
+            // CG directions (DIR) are RHS-major: node stride 1
+            const uint32_t off = (DIR ? node : node * A.ns) + r * A.rs;
+            u = A.u[off];
             if constexpr (DIR) {
-                rr = A.dir_r[node * A.ns + r * A.rs];
+                rr = A.dir_r[off];
                 pp = A.dir_pinv[node];
             }
         }
@@ -727,7 +733,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                               dfast * m0 * (ta2 * UE(efl_t[f], s1) + tb2 * UE(efh_t[f], s1)) +
                               dslow * m0 * (ta1 * UE(esl_t[f], s2) + tb1 * UE(esh_t[f], s2)) + cnd[f];
                 if (!fcon[f] && live) {
-                    out_store<SL>(A, vr, qr, E.fb[f] + (uint32_t)t, 1 - (f & 1), out, true);
+                    out_store<SL, DIR>(A, vr, qr, E.fb[f] + (uint32_t)t, 1 - (f & 1), out, true);
                     en += (double)uf * (double)out;
                 }
             }
@@ -753,8 +759,8 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                 if constexpr (sizeof(T) == 4) {
                     // each line sum with the coefficient row of the thread's
                     // edge (a lane-dependent LDS address, read as a broadcast)
-                    const T* c1 = eb0 ? ctB : ctA;
-                    const T* c2 = eb1 ? ctB : ctA;
+                    const T* c1 = ctA + NI * eb0;  // ctB = ctA + NI
+                    const T* c2 = ctA + NI * eb1;
 #pragma unroll
                     for (int m2 = 0; m2 < NI; ++m2) {
                         l1 += c1[m2] * F[base1 + m2 * st1_t[par]];
@@ -786,7 +792,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                 bool con;
                 edge_node<NI>(L, E, par, eb0, eb1, em, &node, &con);
                 if (!con && live) {
-                    out_store<SL>(A, vr, qr, node, (1 - eb0) + 2 * (1 - eb1), out);
+                    out_store<SL, DIR>(A, vr, qr, node, (1 - eb0) + 2 * (1 - eb1), out);
                     en += (double)ue * (double)out;
                 }
             }
@@ -796,9 +802,9 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
             const int q = t;
             T sx = 0, sy = 0, sz = 0;
             if constexpr (sizeof(T) == 4) {
-                const T* cx = vib ? ctB : ctA;
-                const T* cy = vjb ? ctB : ctA;
-                const T* cz = vkb ? ctB : ctA;
+                const T* cx = ctA + NI * vib;
+                const T* cy = ctA + NI * vjb;
+                const T* cz = ctA + NI * vkb;
 #pragma unroll
                 for (int m2 = 0; m2 < NI; ++m2) {
                     sx += cx[m2] * UE(vjb + 2 * vkb, m2);
@@ -829,7 +835,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
             bool con;
             vertex_node(L, E, vib, vjb, vkb, &node, &con);
             if (!con && live) {
-                out_store<SL>(A, vr, qr, node, (1 - vib) + 2 * (1 - vjb) + 4 * (1 - vkb), out);
+                out_store<SL, DIR>(A, vr, qr, node, (1 - vib) + 2 * (1 - vjb) + 4 * (1 - vkb), out);
                 en += (double)UV(q) * (double)out;
             }
         }
