@@ -755,33 +755,19 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                 const int base1 = f1 * NI2 + (par == 0 ? em : em * NI);
                 const int base2 = f2 * NI2 + (par == 2 ? em * NI : em);
                 constexpr int st1_t[3] = {NI, 1, 1}, st2_t[3] = {NI, NI, 1};
-                T l1 = 0, l2 = 0;
-                if constexpr (sizeof(T) == 4) {
-                    // each line sum with the coefficient row of the thread's
-                    // edge (a lane-dependent LDS address, read as a broadcast)
-                    const T* c1 = ctA + NI * eb0;  // ctB = ctA + NI
-                    const T* c2 = ctA + NI * eb1;
+                // both coefficient rows, then the thread's pick (no per-term selects;
+                // measured faster than one row read at a lane-dependent address)
+                T l1a = 0, l1b = 0, l2a = 0, l2b = 0;
 #pragma unroll
-                    for (int m2 = 0; m2 < NI; ++m2) {
-                        l1 += c1[m2] * F[base1 + m2 * st1_t[par]];
-                        l2 += c2[m2] * F[base2 + m2 * st2_t[par]];
-                    }
-                } else {
-                    // both coefficient rows from uniform addresses, then the
-                    // thread's pick (measured faster in FP64)
-                    T l1a = 0, l1b = 0, l2a = 0, l2b = 0;
-#pragma unroll
-                    for (int m2 = 0; m2 < NI; ++m2) {
-                        const T am = ctA[m2], bm = ctB[m2];
-                        const T x1 = F[base1 + m2 * st1_t[par]], x2 = F[base2 + m2 * st2_t[par]];
-                        l1a += am * x1;
-                        l1b += bm * x1;
-                        l2a += am * x2;
-                        l2b += bm * x2;
-                    }
-                    l1 = eb0 ? l1b : l1a;
-                    l2 = eb1 ? l2b : l2a;
+                for (int m2 = 0; m2 < NI; ++m2) {
+                    const T am = ctA[m2], bm = ctB[m2];
+                    const T x1 = F[base1 + m2 * st1_t[par]], x2 = F[base2 + m2 * st2_t[par]];
+                    l1a += am * x1;
+                    l1b += bm * x1;
+                    l2a += am * x2;
+                    l2b += bm * x2;
                 }
+                const T l1 = eb0 ? l1b : l1a, l2 = eb1 ? l2b : l2a;
                 const int vlo = par == 0 ? 2 * eb0 + 4 * eb1 : (par == 1 ? eb0 + 4 * eb1 : eb0 + 2 * eb1);
                 const int vhi = vlo + (par == 0 ? 1 : (par == 1 ? 2 : 4));
                 const T ue = UE(q, em);
@@ -800,34 +786,19 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
         // ---- vertices
         if (vown) {
             const int q = t;
-            T sx = 0, sy = 0, sz = 0;
-            if constexpr (sizeof(T) == 4) {
-                const T* cx = ctA + NI * vib;
-                const T* cy = ctA + NI * vjb;
-                const T* cz = ctA + NI * vkb;
+            T sxa = 0, sxb = 0, sya = 0, syb = 0, sza = 0, szb = 0;
 #pragma unroll
-                for (int m2 = 0; m2 < NI; ++m2) {
-                    sx += cx[m2] * UE(vjb + 2 * vkb, m2);
-                    sy += cy[m2] * UE(4 + vib + 2 * vkb, m2);
-                    sz += cz[m2] * UE(8 + vib + 2 * vjb, m2);
-                }
-            } else {
-                T sxa = 0, sxb = 0, sya = 0, syb = 0, sza = 0, szb = 0;
-#pragma unroll
-                for (int m2 = 0; m2 < NI; ++m2) {
-                    const T am = ctA[m2], bm = ctB[m2];
-                    const T x = UE(vjb + 2 * vkb, m2), y = UE(4 + vib + 2 * vkb, m2), z = UE(8 + vib + 2 * vjb, m2);
-                    sxa += am * x;
-                    sxb += bm * x;
-                    sya += am * y;
-                    syb += bm * y;
-                    sza += am * z;
-                    szb += bm * z;
-                }
-                sx = vib ? sxb : sxa;
-                sy = vjb ? syb : sya;
-                sz = vkb ? szb : sza;
+            for (int m2 = 0; m2 < NI; ++m2) {
+                const T am = ctA[m2], bm = ctB[m2];
+                const T x = UE(vjb + 2 * vkb, m2), y = UE(4 + vib + 2 * vkb, m2), z = UE(8 + vib + 2 * vjb, m2);
+                sxa += am * x;
+                sxb += bm * x;
+                sya += am * y;
+                syb += bm * y;
+                sza += am * z;
+                szb += bm * z;
             }
+            const T sx = vib ? sxb : sxa, sy = vjb ? syb : sya, sz = vkb ? szb : sza;
             const T out = (d0 * m02 * m0 + (d1 + d2 + d3) * m02 * K00) * UV(q) +
                           m02 * K0p * (d1 * UV(q ^ 1) + d2 * UV(q ^ 2) + d3 * UV(q ^ 4)) +
                           m02 * (d1 * sx + d2 * sy + d3 * sz);
