@@ -410,6 +410,30 @@ int semcond_element_grads_rhs(semcond_ctx* ctx, const void* u_nodal, const void*
                               int k, void* stream);
 
 /*
+ * Right-hand sides per workgroup of the batched right-hand-side condensation
+ * and interior recovery kernels (Algorithm 4, first and second loops; used for
+ * 8 <= p - 1 <= 12 and N < 2^32).  A workgroup takes one element and R
+ * right-hand sides, setting up the element's tables, addresses and D^-1 once.
+ * R > 0 fixes the batch for every k (capped at k) and R = -1 selects the
+ * per-item kernels (one workgroup per element and right-hand side); R = 0, the
+ * default, lets the library time the per-item kernels and R = 1, 2, 4, 8, 16
+ * (up to k) on the first condensation and the first recovery of each k of this
+ * context (synchronising the stream there) and keep the fastest.  Every
+ * batched R gives bitwise the same recovery, and the same condensation up to
+ * the order of its atomic additions (bitwise the same in deterministic mode);
+ * the per-item kernels differ from them by rounding.  Errors: EINVAL for R
+ * outside [-1, 256].
+ */
+int semcond_set_rhs_batch(semcond_ctx* ctx, int R);
+
+/*
+ * The batch sizes in use for k right-hand sides: R_condense, R_recover
+ * (nullable) receive R, 0 for the per-item kernels, -1 while not yet timed.
+ * Errors: EINVAL for k outside [1, 256].
+ */
+int semcond_get_rhs_batch(const semcond_ctx* ctx, int k, int* R_condense, int* R_recover);
+
+/*
  * Autotuner of the CG launch (k right-hand sides of scalar type dtype): times
  * one launch per step and the candidate persistent grids (workgroup count G,
  * element groups per workgroup S) for a few CG iterations on this context's

@@ -13,8 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsemcond.so")
 
-SOURCES = ["apply.hip", "pcg_persistent.hip", "misc.hip", "noalloc.hip", "variants.hip", "coarse.hip", "tables.cpp",
-           "api.cpp"]
+SOURCES = ["apply.hip", "pcg_persistent.hip", "misc.hip", "rhs_batched.hip", "noalloc.hip", "variants.hip", "coarse.hip",
+           "tables.cpp", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -122,6 +122,12 @@ struct semcond_ctx {
     float* d_dinv32 = nullptr;
     int* d_dcls = nullptr;
     double* d_dclass = nullptr;  // [cap][4] metric coefficients of the classes
+    // right-hand sides per workgroup of the batched condensation / recovery
+    // kernels: fixed by semcond_set_rhs_batch (> 0; -1: the per-item kernels),
+    // else timed per k on first use (rhs_tuned: k -> (condensation, recovery);
+    // 0 = per-item kernels)
+    int rhs_batch_fixed = 0;
+    std::map<int, std::pair<int, int>> rhs_tuned;
 };
 
 namespace {
@@ -394,27 +400,103 @@ int scratch_for_cubes(semcond_ctx* c, int* grid, double** scratch) {
     return SEMCOND_OK;
 }
 
+// Right-hand sides per workgroup of the batched condensation (kind 0) or
+// recovery (kind 1) for k right-hand sides: 0 = the per-item kernels, -1 = not
+// yet timed.
+int rhs_batch(const semcond_ctx* c, int k, int kind) {
+    if (!rhs_batched_supported(c->L, c->N) || c->rhs_batch_fixed < 0) return 0;
+    if (c->rhs_batch_fixed > 0) return std::min(c->rhs_batch_fixed, k);
+    auto it = c->rhs_tuned.find(k);
+    if (it == c->rhs_tuned.end()) return -1;
+    return kind ? it->second.second : it->second.first;
+}
+
+// Times run(R) for the candidate batch sizes (per-item kernels, 1, 2, 4, 8,
+// 16 up to k; two rounds, the faster of each) on stream st and returns the
+// fastest in *best.  run must be repeatable (the callers clear what it adds
+// into).
+template <class Run>
+int tune_rhs_batch(semcond_ctx* c, int k, hipStream_t st, Run&& run, int* best) {
+    std::vector<int> cand{0};
+    for (int R = 1; R <= 16 && R <= k; R *= 2) cand.push_back(R);
+    std::vector<float> ms(cand.size(), 1e30f);
+    hipEvent_t ev[2];
+    HIPCHK(c, hipEventCreate(&ev[0]));
+    HIPCHK(c, hipEventCreate(&ev[1]));
+    int rc = SEMCOND_OK;
+    for (int round = 0; round < 2 && !rc; ++round)
+        for (size_t i = 0; i < cand.size() && !rc; ++i) {
+            hipError_t e = hipEventRecord(ev[0], st);
+            if (e == hipSuccess) rc = run(cand[i]);
+            if (!rc && e == hipSuccess) e = hipEventRecord(ev[1], st);
+            if (!rc && e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float t = 0.0f;
+            if (!rc && e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+            if (!rc && e != hipSuccess) rc = fail(c, SEMCOND_EDEVICE, std::string("batch timing: ") + hipGetErrorString(e));
+            if (!rc) ms[i] = std::min(ms[i], t);
+        }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (rc) return rc;
+    *best = cand[std::min_element(ms.begin(), ms.end()) - ms.begin()];
+    return SEMCOND_OK;
+}
+
 // fhat (FP64, transformed) = condensed RHS of nodal f.
 int condense_rhs64(semcond_ctx* c, const double* f, double* fhat, int k, hipStream_t st, SkelStride sk = {}) {
     int grid;
     double* scratch;
     int rc = scratch_for_cubes(c, &grid, &scratch);
     if (rc) return rc;
-    double* slots = nullptr;
-    if (c->det_active) {
-        // deterministic: rows into per-side slots, summed in a fixed order
-        const int64_t qlen = slot_len(c->L);
-        if (qlen * (int64_t)k >= (int64_t(1) << 31))
-            return fail(c, SEMCOND_EINVAL, "deterministic condensation: slot workspace beyond 2^31 entries");
-        rc = grow(c, c->ws_slots, (size_t)qlen * k * sizeof(double));
+    // Rows go into per-side slots, summed in a fixed order afterwards, in
+    // deterministic mode; otherwise they are added with atomics (measured
+    // faster than slots with the batched kernels too: 2.6 against 2.7 ms plus
+    // 0.4 ms of slot sums and 0.3 ms of clearing at 24^3 elements, p = 12, 16 RHS).
+    const int64_t qlen = slot_len(c->L);
+    if (c->det_active && qlen * (int64_t)k >= (int64_t(1) << 31))
+        return fail(c, SEMCOND_EINVAL, "deterministic condensation: slot workspace beyond 2^31 entries");
+    auto run = [&](int R) -> int {
+        double* slots = nullptr;
+        if (c->det_active) {
+            int rc2 = grow(c, c->ws_slots, (size_t)qlen * k * sizeof(double));
+            if (rc2) return rc2;
+            slots = (double*)c->ws_slots.ptr;
+            HIPCHK(c, launch_fill<double>(slots, qlen * k, 0.0, st));
+        } else {
+            HIPCHK(c, launch_fill<double>(fhat, c->N_s * k, 0.0, st));
+        }
+        HIPCHK(c, launch_condense_rhs(c->geo, c->t64.tab, f, c->N, fhat, k, scratch, grid, slots, st, sk, R));
+        return SEMCOND_OK;
+    };
+    int R = rhs_batch(c, k, 0);
+    if (R < 0) {
+        rc = tune_rhs_batch(c, k, st, run, &R);
         if (rc) return rc;
-        slots = (double*)c->ws_slots.ptr;
-        HIPCHK(c, launch_fill<double>(slots, qlen * k, 0.0, st));
-    } else {
-        HIPCHK(c, launch_fill<double>(fhat, c->N_s * k, 0.0, st));
+        auto it = c->rhs_tuned.emplace(k, std::make_pair(-1, -1)).first;
+        it->second.first = R;
     }
-    HIPCHK(c, launch_condense_rhs(c->geo, c->t64.tab, f, c->N, fhat, k, scratch, grid, slots, st, sk));
-    return SEMCOND_OK;
+    return run(R);
+}
+
+// Interior recovery with the batch size of this context for k (timed on first use).
+int recover_interior64(semcond_ctx* c, const double* f, const double* xs, double* u, int k, int keep,
+                       hipStream_t st, SkelStride sk = {}) {
+    int grid;
+    double* scratch;
+    int rc = scratch_for_cubes(c, &grid, &scratch);
+    if (rc) return rc;
+    auto run = [&](int R) -> int {
+        HIPCHK(c, launch_recover_interior(c->geo, c->t64.tab, f, c->N, xs, u, k, scratch, grid, keep, st, sk, R));
+        return SEMCOND_OK;
+    };
+    int R = rhs_batch(c, k, 1);
+    if (R < 0) {
+        rc = tune_rhs_batch(c, k, st, run, &R);
+        if (rc) return rc;
+        auto it = c->rhs_tuned.emplace(k, std::make_pair(-1, -1)).first;
+        it->second.second = R;
+    }
+    return run(R);
 }
 
 struct CgWork {
@@ -1592,6 +1674,21 @@ int semcond_nodal_mass(semcond_ctx* c, void* mass, void* stream) {
     return SEMCOND_OK;
 }
 
+int semcond_set_rhs_batch(semcond_ctx* c, int R) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (R < -1 || R > kMaxRhs) return fail(c, SEMCOND_EINVAL, "R must be in [-1, 256]");
+    c->rhs_batch_fixed = R;
+    return SEMCOND_OK;
+}
+
+int semcond_get_rhs_batch(const semcond_ctx* c, int k, int* R_condense, int* R_recover) {
+    if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
+    if (k < 1 || k > kMaxRhs) return fail(const_cast<semcond_ctx*>(c), SEMCOND_EINVAL, "k must be in [1, 256]");
+    if (R_condense) *R_condense = rhs_batch(c, k, 0);
+    if (R_recover) *R_recover = rhs_batch(c, k, 1);
+    return SEMCOND_OK;
+}
+
 int semcond_autotune(semcond_ctx* c, int k, int dtype, const char* cache_path, int* S_out, int* G_out) {
     if (!c) return fail(nullptr, SEMCOND_EINVAL, "ctx is NULL");
     int rc = check_k(c, k);
@@ -1717,17 +1814,11 @@ int semcond_recover_interior(semcond_ctx* c, const void* f, const void* u_skel, 
     rc = grow(c, c->ws_vec, nv * sizeof(double));
     if (rc) return rc;
     double* phys = (double*)c->ws_vec.ptr;
-    int grid;
-    double* scratch;
-    rc = scratch_for_cubes(c, &grid, &scratch);
-    if (rc) return rc;
     // skeleton nodes: u = T u~ (Dirichlet entities keep the values given in u_skel);
     // interior nodes: u_I = (S(x)S(x)S) D^-1 (F~_I - H~_IB u~_B) (Algorithm 4, second loop)
     HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.S, (const double*)u_skel, phys, k, st));
     HIPCHK(c, launch_skel_to_nodal(c->L, phys, (double*)u, c->N, k, 1, st));
-    HIPCHK(c, launch_recover_interior(c->geo, c->t64.tab, (const double*)f, c->N, (const double*)u_skel, (double*)u,
-                                      k, scratch, grid, 1, st));
-    return SEMCOND_OK;
+    return recover_interior64(c, (const double*)f, (const double*)u_skel, (double*)u, k, 1, st);
 }
 
 int semcond_reserve(semcond_ctx* c, int k_max, int dtype) {
@@ -1999,12 +2090,8 @@ int semcond_solve(semcond_ctx* c, const void* f, void* u, int k, const semcond_s
     HIPCHK(c, launch_transform<double>(c->L, c->t64.tab.S, xs, p, k, st, xl));
     HIPCHK(c, launch_skel_to_nodal(c->L, p, (double*)u, c->N, k, keep, st, xl));
     if (o.recover_interior) {
-        int grid;
-        double* scratch;
-        rc = scratch_for_cubes(c, &grid, &scratch);
+        rc = recover_interior64(c, (const double*)f, xs, (double*)u, k, keep, st, xl);
         if (rc) return rc;
-        HIPCHK(c, launch_recover_interior(c->geo, c->t64.tab, (const double*)f, c->N, xs, (double*)u, k, scratch,
-                                          grid, keep, st, xl));
     }
     if (o.skel_out) {
         if (rmaj)

@@ -153,12 +153,15 @@ hipError_t launch_precond_invert(const Layout& L, const double* diag, T* pinv, h
 // slots (nullable, k * slot_len doubles, zeroed): rows stored per side and
 // summed in a fixed order into fhat (every entry written); else fhat (zeroed
 // first) accumulates them with atomics.
+// rhs_batch: right-hand sides per workgroup of the batched kernels
+// (rhs_batched.hip, 8 <= n_I <= 12); 0 keeps one workgroup per (element,
+// right-hand side) with the per-item kernels.
 hipError_t launch_condense_rhs(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
                                double* fhat, int k, double* scratch, int grid, double* slots, hipStream_t st,
-                               SkelStride sk = {});
+                               SkelStride sk = {}, int rhs_batch = 0);
 hipError_t launch_condense_rhs_body(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
                                     double* fhat, int k, double* scratch, int grid, double* slots, int64_t qlen,
-                                    hipStream_t st, SkelStride sk = {});
+                                    hipStream_t st, SkelStride sk = {}, int rhs_batch = 0);
 int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch);
 
 // Interior recovery (Algorithm 4, second loop): u_I = (S(x)S(x)S) D^-1 (F~_I - H~_IB u~_B),
@@ -167,7 +170,17 @@ int rhs_grid_for_scratch(int p, int64_t n_e, bool* needs_scratch);
 // boundary values) instead of 0.
 hipError_t launch_recover_interior(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
                                    const double* xskel, double* u, int k, double* scratch, int grid,
-                                   int keep_con, hipStream_t st, SkelStride sk = {});
+                                   int keep_con, hipStream_t st, SkelStride sk = {}, int rhs_batch = 0);
+
+// The batched kernels (R right-hand sides per workgroup), for the layouts
+// rhs_batched_supported accepts.
+bool rhs_batched_supported(const Layout& L, int64_t N);
+hipError_t launch_condense_rhs_mb(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
+                                  double* fhat, int k, int R, double* slots, int64_t qlen, hipStream_t st,
+                                  SkelStride sk);
+hipError_t launch_recover_interior_mb(const Geo& g, const DevTab<double>& tab, const double* f, int64_t N,
+                                      const double* xskel, double* u, int k, int R, int keep_con, hipStream_t st,
+                                      SkelStride sk);
 
 // Operator variants of Sec. 7 (variants.hip), FP64, physical basis, skeleton
 // vectors [N_s][k]: TPC (Algorithm 3 with the suboperators of Table 1; v is

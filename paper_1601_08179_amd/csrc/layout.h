@@ -176,67 +176,79 @@ __host__ __device__ inline void element_entity(const Layout& L, int e1, int e2, 
 }
 
 // Global GLL indices (I1,I2,I3) of skeleton node s, and whether it is
-// constrained.  Used by the nodal<->skeleton copies and the host coords table.
-__host__ __device__ inline void skeleton_node(const Layout& L, int64_t s, int* I1, int* I2, int* I3,
-                                              bool* con) {
+// constrained, with index arithmetic in type I (32-bit divisions are several
+// times cheaper on the GPU than 64-bit ones).
+template <typename I>
+__host__ __device__ inline void skeleton_node_t(const Layout& L, I s, int* I1, int* I2, int* I3, bool* con) {
     const int p = L.p, NI = L.NI;
-    const int64_t NI2 = (int64_t)NI * NI;
-    if (s < L.oFy) {
-        int64_t t = s - L.oFx, f = t / NI2, loc = t % NI2;
-        int k = (int)(loc / NI), j = (int)(loc % NI);
-        int fx = (int)(f % (L.n1 + 1));
-        int64_t r = f / (L.n1 + 1);
-        int e2 = (int)(r % L.n2), e3 = (int)(r / L.n2);
+    const I NI2 = (I)NI * NI;
+    if (s < (I)L.oFy) {
+        I t = s - (I)L.oFx, f = t / NI2, loc = t % NI2;
+        int k = (int)(loc / (I)NI), j = (int)(loc % (I)NI);
+        int fx = (int)(f % (I)(L.n1 + 1));
+        I r = f / (I)(L.n1 + 1);
+        int e2 = (int)(r % (I)L.n2), e3 = (int)(r / (I)L.n2);
         *I1 = fx * p; *I2 = e2 * p + 1 + j; *I3 = e3 * p + 1 + k;
         *con = xcon(L, fx);
-    } else if (s < L.oFz) {
-        int64_t t = s - L.oFy, f = t / NI2, loc = t % NI2;
-        int k = (int)(loc / NI), i = (int)(loc % NI);
-        int e1 = (int)(f % L.n1);
-        int64_t r = f / L.n1;
-        int fy = (int)(r % (L.n2 + 1)), e3 = (int)(r / (L.n2 + 1));
+    } else if (s < (I)L.oFz) {
+        I t = s - (I)L.oFy, f = t / NI2, loc = t % NI2;
+        int k = (int)(loc / (I)NI), i = (int)(loc % (I)NI);
+        int e1 = (int)(f % (I)L.n1);
+        I r = f / (I)L.n1;
+        int fy = (int)(r % (I)(L.n2 + 1)), e3 = (int)(r / (I)(L.n2 + 1));
         *I1 = e1 * p + 1 + i; *I2 = fy * p; *I3 = e3 * p + 1 + k;
         *con = ycon(L, fy);
-    } else if (s < L.oEx) {
-        int64_t t = s - L.oFz, f = t / NI2, loc = t % NI2;
-        int j = (int)(loc / NI), i = (int)(loc % NI);
-        int e1 = (int)(f % L.n1);
-        int64_t r = f / L.n1;
-        int e2 = (int)(r % L.n2), fz = (int)(r / L.n2);
+    } else if (s < (I)L.oEx) {
+        I t = s - (I)L.oFz, f = t / NI2, loc = t % NI2;
+        int j = (int)(loc / (I)NI), i = (int)(loc % (I)NI);
+        int e1 = (int)(f % (I)L.n1);
+        I r = f / (I)L.n1;
+        int e2 = (int)(r % (I)L.n2), fz = (int)(r / (I)L.n2);
         *I1 = e1 * p + 1 + i; *I2 = e2 * p + 1 + j; *I3 = fz * p;
         *con = zcon(L, fz);
-    } else if (s < L.oEy) {
-        int64_t t = s - L.oEx, f = t / NI;
-        int i = (int)(t % NI);
-        int e1 = (int)(f % L.n1);
-        int64_t r = f / L.n1;
-        int ey = (int)(r % (L.n2 + 1)), ez = (int)(r / (L.n2 + 1));
+    } else if (s < (I)L.oEy) {
+        I t = s - (I)L.oEx, f = t / (I)NI;
+        int i = (int)(t % (I)NI);
+        int e1 = (int)(f % (I)L.n1);
+        I r = f / (I)L.n1;
+        int ey = (int)(r % (I)(L.n2 + 1)), ez = (int)(r / (I)(L.n2 + 1));
         *I1 = e1 * p + 1 + i; *I2 = ey * p; *I3 = ez * p;
         *con = ycon(L, ey) || zcon(L, ez);
-    } else if (s < L.oEz) {
-        int64_t t = s - L.oEy, f = t / NI;
-        int j = (int)(t % NI);
-        int ex = (int)(f % (L.n1 + 1));
-        int64_t r = f / (L.n1 + 1);
-        int e2 = (int)(r % L.n2), ez = (int)(r / L.n2);
+    } else if (s < (I)L.oEz) {
+        I t = s - (I)L.oEy, f = t / (I)NI;
+        int j = (int)(t % (I)NI);
+        int ex = (int)(f % (I)(L.n1 + 1));
+        I r = f / (I)(L.n1 + 1);
+        int e2 = (int)(r % (I)L.n2), ez = (int)(r / (I)L.n2);
         *I1 = ex * p; *I2 = e2 * p + 1 + j; *I3 = ez * p;
         *con = xcon(L, ex) || zcon(L, ez);
-    } else if (s < L.oV) {
-        int64_t t = s - L.oEz, f = t / NI;
-        int k = (int)(t % NI);
-        int ex = (int)(f % (L.n1 + 1));
-        int64_t r = f / (L.n1 + 1);
-        int ey = (int)(r % (L.n2 + 1)), e3 = (int)(r / (L.n2 + 1));
+    } else if (s < (I)L.oV) {
+        I t = s - (I)L.oEz, f = t / (I)NI;
+        int k = (int)(t % (I)NI);
+        int ex = (int)(f % (I)(L.n1 + 1));
+        I r = f / (I)(L.n1 + 1);
+        int ey = (int)(r % (I)(L.n2 + 1)), e3 = (int)(r / (I)(L.n2 + 1));
         *I1 = ex * p; *I2 = ey * p; *I3 = e3 * p + 1 + k;
         *con = xcon(L, ex) || ycon(L, ey);
     } else {
-        int64_t t = s - L.oV;
-        int vx = (int)(t % (L.n1 + 1));
-        int64_t r = t / (L.n1 + 1);
-        int vy = (int)(r % (L.n2 + 1)), vz = (int)(r / (L.n2 + 1));
+        I t = s - (I)L.oV;
+        int vx = (int)(t % (I)(L.n1 + 1));
+        I r = t / (I)(L.n1 + 1);
+        int vy = (int)(r % (I)(L.n2 + 1)), vz = (int)(r / (I)(L.n2 + 1));
         *I1 = vx * p; *I2 = vy * p; *I3 = vz * p;
         *con = xcon(L, vx) || ycon(L, vy) || zcon(L, vz);
     }
+}
+
+// The same for any skeleton index (the nodal<->skeleton copies and the host
+// coords table): 32-bit arithmetic whenever the skeleton has fewer than 2^32
+// nodes.
+__host__ __device__ inline void skeleton_node(const Layout& L, int64_t s, int* I1, int* I2, int* I3,
+                                              bool* con) {
+    if (L.Ns <= (int64_t)0xFFFFFFFFu)
+        skeleton_node_t<uint32_t>(L, (uint32_t)s, I1, I2, I3, con);
+    else
+        skeleton_node_t<int64_t>(L, s, I1, I2, I3, con);
 }
 
 }  // namespace semcond

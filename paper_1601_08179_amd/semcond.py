@@ -89,6 +89,9 @@ _SIGS = {
                                              ctypes.c_int, ctypes.c_void_p]),
     "semcond_element_grads_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "semcond_set_rhs_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "semcond_get_rhs_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                             ctypes.POINTER(ctypes.c_int)]),
     "semcond_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_char_p,
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "semcond_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -407,6 +410,18 @@ class Context:
         _check(_lib.semcond_update_coefficients(self._h, 0.0 if lam is None else float(lam), le, dc,
                                                 _stream(stream)), self._h)
         self.coef_version += 1
+
+    def set_rhs_batch(self, R):
+        """Right-hand sides per workgroup of the batched condensation / recovery
+        (R > 0 fixed, -1: per-item kernels, 0: timed per k on first use)."""
+        _check(_lib.semcond_set_rhs_batch(self._h, int(R)), self._h)
+
+    def rhs_batch(self, k):
+        """(R_condense, R_recover) in use for k right-hand sides (0: per-item
+        kernels, -1: not yet timed)."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.semcond_get_rhs_batch(self._h, int(k), ctypes.byref(a), ctypes.byref(b)), self._h)
+        return a.value, b.value
 
     def autotune(self, k=1, dtype=None, cache_path=None):
         """Pick the CG launch by timing; returns (S, G): the persistent grid, or (0, 0) for one

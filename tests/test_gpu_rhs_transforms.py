@@ -27,10 +27,17 @@ def _t(a):
     return torch.as_tensor(np.ascontiguousarray(a), device="cuda", dtype=torch.float64)
 
 
+# right-hand sides per workgroup: timed (None), per-item kernels (-1), batches
+BATCHES = [None, -1, 1, 2]
+
+
+@pytest.mark.parametrize("batch", BATCHES)
 @pytest.mark.parametrize("name", list(RHS_MESHES))
-def test_condensed_rhs_matrix_cores(lib, name):
-    print("case", name, flush=True)
+def test_condensed_rhs_matrix_cores(lib, name, batch):
+    print("case", name, batch, flush=True)
     ctx, op, g, free = both(RHS_MESHES[name]())
+    if batch is not None:
+        ctx.set_rhs_batch(batch)
     f = W.random_skeleton_input(op.sizes["N"], k=3, seed=61)
     ref = op.condensed_rhs(f.T)
     fhat = ctx.transform(ctx.condense_rhs(_t(f)), lib.DUAL_TO_PHYSICAL).cpu().numpy()
@@ -40,12 +47,15 @@ def test_condensed_rhs_matrix_cores(lib, name):
     ctx.close()
 
 
+@pytest.mark.parametrize("batch", BATCHES)
 @pytest.mark.parametrize("name", list(RHS_MESHES))
-def test_recover_interior_matrix_cores(lib, name):
+def test_recover_interior_matrix_cores(lib, name, batch):
     """Given skeleton values (physical basis, free nodes), the interior the
     library recovers equals u_I = H_II^-1 (F_I - H_IB u_B) of the oracle."""
-    print("case", name, flush=True)
+    print("case", name, batch, flush=True)
     ctx, op, g, free = both(RHS_MESHES[name]())
+    if batch is not None:
+        ctx.set_rhs_batch(batch)
     f = W.random_skeleton_input(op.sizes["N"], k=2, seed=62)
     us = W.random_skeleton_input(op.sizes["N"], k=2, seed=63)
     phys = us[:, g].T.copy()
@@ -72,4 +82,35 @@ def test_solve_fp64_matrix_cores(lib, name):
         ref = op.recover_interior(f[r], op.solve_condensed(f[r]))
         assert info[r]["status"] == 0
         assert np.abs(u[r] - ref).max() <= 1e-10 * np.abs(ref).max(), (name, r, info[r])
+    ctx.close()
+
+
+@pytest.mark.parametrize("p", [9, 12, 13])
+def test_rhs_batches_agree(lib, p):
+    """The batched kernels give the same recovery for every R (bitwise) and,
+    in deterministic mode, the same condensation (bitwise); the per-item
+    kernels agree to rounding.  Seven right-hand sides: batches of 1, 3 (a
+    ragged last batch), 7 and 16 (capped at k)."""
+    import torch
+    from paper_1601_08179_amd import semcond
+    print("case p", p, flush=True)
+    ctx = semcond.Context(W.mesh(p, (3, 2, 2), widths=[W.geometric_widths(3, 6), [0.4, 0.6], [0.7, 0.3]],
+                                 lam=0.8, dirichlet=0b011001))
+    k = 7
+    rng = np.random.default_rng(70 + p)
+    f = _t(rng.standard_normal((k, ctx.N)))
+    ut = torch.as_tensor(rng.standard_normal((ctx.N_s, k)), device="cuda", dtype=torch.float64)
+    rec, cond = {}, {}
+    for R in (-1, 1, 3, 7, 16):
+        ctx.set_rhs_batch(R)
+        assert ctx.rhs_batch(k) == ((0, 0) if R < 0 else (min(R, k), min(R, k)))
+        rec[R] = ctx.recover_interior(f, ut).cpu().numpy()
+        ctx.set_deterministic(True)
+        cond[R] = ctx.condense_rhs(f).cpu().numpy()
+        ctx.set_deterministic(False)
+    for R in (3, 7, 16):
+        assert np.array_equal(rec[R], rec[1]), R
+        assert np.array_equal(cond[R], cond[1]), R
+    assert rel_err(rec[1], rec[-1]) <= 1e-13
+    assert rel_err(cond[1], cond[-1]) <= 1e-13
     ctx.close()
