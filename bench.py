@@ -426,6 +426,23 @@ def stored_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_cg_apply_f32_config4_p12_k16.md")
+
+
+def stored_valu_busy():
+    """Fraction of SIMD cycles issuing VALU instructions in the dominant kernel,
+    from the SQ counter summary, or None when absent or taken from other kernel
+    sources."""
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("valu_busy", "kernel_sources")))
+    if vals.get("kernel_sources_sha256", "").strip() != kernel_sources_hash():
+        return None
+    return float(vals["valu_busy"])
+
+
 def copy_bandwidth(torch):
     """STREAM-style copy on this GPU (1 GiB read + 1 GiB written), GB/s."""
     ca = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -635,6 +652,8 @@ def main():
     roof = {"bound": "hbm", "achieved": ach_m, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_m / HBM_PEAK_GBS,
             "traffic": traffic,
             "traffic_unit": "HBM bytes per full launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            # what the counters show limits it: the SIMDs' VALU issue (fraction of cycles)
+            "valu_busy": stored_valu_busy(),
             "kernel": DOMINANT.replace(" ", ""), "launches": m_launches,
             "kernel_us_per_launch": m_ms * 1e3 / max(m_launches, 1),
             "algorithmic_bytes_per_launch": bytes_m / max(m_launches, 1),
