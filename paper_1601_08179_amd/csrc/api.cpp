@@ -682,6 +682,14 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
         c->cg_epoch = (c->cg_epoch + 1) & 0x3FFFFFFF;
     }
     const int epoch2 = 2 * c->cg_epoch;
+    if (fused) {
+        // every flag starts as "active" in this loop's numbering: the first
+        // poll with check_every = 1 reads them before any kernel of this loop
+        // has written one, and a pinned buffer recycled from another context
+        // may hold that context's "stopped" value of the same number (no kernel
+        // writes them now: the previous solve ended with a synchronisation)
+        for (int i = 0; i < k; ++i) __atomic_store_n(c->h_flags + i, epoch2 + 1, __ATOMIC_RELEASE);
+    }
     auto none_active = [&](const int* h) {
         for (int i = 0; i < k; ++i)
             if (h[i]) return false;
