@@ -296,6 +296,15 @@ hipError_t launch_apply(const ApplyArgs<T>& a, int64_t n_elem, hipStream_t st) {
 // [k][N_s] (RHS-major, inside the conjugate gradients).
 enum VecLayout { NODE_MAJOR = 0, RHS_MAJOR = 1 };
 
+// The CG applies address one right-hand side's vectors and slots with 32-bit
+// byte offsets: N_s and the slot length times the value size below 2^32.
+template <typename T>
+bool cg_offsets_fit(const semcond_ctx* c) {
+    const uint64_t lim = uint64_t(1) << 32;
+    return (uint64_t)c->N_s * sizeof(T) < lim && (uint64_t)slot_len(c->L) * sizeof(T) < lim;
+}
+const char* const cg_offsets_msg = "conjugate gradients: skeleton beyond 32-bit byte offsets per right-hand side";
+
 // Whether the CG applies that use slots store face rows into slots as well
 // (else faces are added into q; edges and vertices use slots).  Measured on
 // MI355X: the FP32 loop is faster with face slots, the FP64 loop with face
@@ -337,6 +346,7 @@ int apply_transformed(semcond_ctx* c, const T* u, T* v, int k, VecLayout lay, do
     if (dir_r) {
         if (!dir_beta) return fail(c, SEMCOND_EINVAL, "fused direction needs beta");
         if (lay != RHS_MAJOR) return fail(c, SEMCOND_EINVAL, "fused direction needs RHS-major vectors");
+        if (!cg_offsets_fit<T>(c)) return fail(c, SEMCOND_EINVAL, cg_offsets_msg);
         if (slots && face_slots != cg_face_slots<T>())
             return fail(c, SEMCOND_EINVAL, "CG applies keep face rows in slots exactly in FP32");
         a.dir_r = dir_r;
@@ -915,6 +925,7 @@ int run_persistent(semcond_ctx* c, T* x, T* r, T* p, T* q, int k, double tol, in
     const int mg = persist_max_grid<T>(c->L.NI, S);
     if (!persist_supported(c->L.NI, S, k) || G < 1 || G > mg)
         return fail(c, SEMCOND_EINVAL, "persistent CG: configuration (S, G) not co-resident on this device");
+    if (!cg_offsets_fit<T>(c)) return fail(c, SEMCOND_EINVAL, cg_offsets_msg);
     const size_t part_bytes = (3 * (size_t)G * k * sizeof(double) + 255) / 256 * 256;
     const size_t need = part_bytes + kBarWords * sizeof(unsigned);
     int rc = grow(c, c->ws_persist, need);

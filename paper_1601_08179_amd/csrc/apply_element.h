@@ -66,10 +66,19 @@ template <bool SL = true, bool NS1 = false, typename T>
 __device__ inline void out_store(const ApplyArgs<T>& A, T* vr, T* qr, uint32_t node, int slot, T val,
                                  bool face = false) {
     const bool fslots = NS1 ? sizeof(T) == 4 : A.face_slots != 0;
-    if (SL && qr && (!face || fslots))
-        qr[slot_addr(A.g.L, node, slot)] = val;
-    else
-        atomic_add(vr + (NS1 ? node : node * A.ns), val);
+    if constexpr (NS1) {
+        // 32-bit byte offsets from the right-hand side's uniform bases (a
+        // slot offset is below 2 N_s + 6 (N_s - oV), N_s sizeof(T) < 2^31)
+        if (SL && qr && (!face || fslots))
+            *(T*)((char*)qr + slot_addr(A.g.L, node, slot) * (uint32_t)sizeof(T)) = val;
+        else
+            atomic_add((T*)((char*)vr + node * (uint32_t)sizeof(T)), val);
+    } else {
+        if (SL && qr && (!face || fslots))
+            qr[slot_addr(A.g.L, node, slot)] = val;
+        else
+            atomic_add(vr + node * A.ns, val);
+    }
 }
 
 // Shared memory of one element.
@@ -80,10 +89,12 @@ struct ApplySmem {
     static constexpr int NSLOT = NFACE + 12 * NI + 8;
     static constexpr bool CUBE = NI <= 15;
     static constexpr int NW = CUBE ? NI * NI2 : 2 * NI2;
+    // the 1D coefficients first: at small LDS addresses their pairs are read
+    // with immediate offsets from one zero base (ds_read2 offsets reach 255 elements)
+    T tl[3 * NI];            // Lambda, a, b
     T F[NSLOT];              // gathered u~: faces [6][NI2], edges [12][NI], vertices [8]
     T OF[CUBE ? 1 : NFACE];  // condensed part of the face outputs (plane mode)
     T Wv[NW];                // eigenspace v = D^-1 u (cube or two planes)
-    T tl[3 * NI];            // Lambda, a, b
     int64_t ebase[26];
     int econ[26];
     double red[apply_threads(NI) / 64];
@@ -466,7 +477,8 @@ __device__ inline void vertex_node(const Layout& L, const ElemEnt& E, int ib, in
 
 // One thread's gathered values of one (element, RHS): its face slot of the
 // six faces, its edge node in the three directions, its vertex.  With DIR
-// also r and P^-1 at the same nodes.  Constrained or absent slots hold 0.
+// also r and P^-1 at the same nodes.  Constrained slots hold 0 (DIR: zero
+// directions), slots the thread does not own an unspecified value.
 template <typename T, bool DIR>
 struct Gathered {
     T f[6], e[3], v;
@@ -485,23 +497,38 @@ __device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live,
     ElemEnt E;
     elem_entities(L, e1, e2, e3, E);
     const bool fcon[6] = {E.cx0, E.cx1, E.cy0, E.cy1, E.cz0, E.cz1};
-    auto load = [&](uint32_t node, bool on, T& u, T& rr, T& pp) {
-        u = (T)0;
-        rr = (T)0;
-        pp = (T)0;
-        if (on) {
-            // CG directions (DIR) are RHS-major: node stride 1
-            const uint32_t off = (DIR ? node : node * A.ns) + r * A.rs;
-            u = A.u[off];
-            if constexpr (DIR) {
-                rr = A.dir_r[off];
-                pp = A.dir_pinv[node];
+    // CG directions (DIR) are RHS-major (node stride 1): the right-hand side's
+    // vectors start at wave-uniform addresses and a node is a 32-bit byte
+    // offset from them (N_s sizeof(T) < 2^32, checked by the launcher), which
+    // the loads take as a vector offset from a scalar base.
+    const char* const ub = DIR ? (const char*)(A.u + (size_t)r * A.rs) : nullptr;
+    const char* const rb = DIR ? (const char*)(A.dir_r + (size_t)r * A.rs) : nullptr;
+    const char* const pb = DIR ? (const char*)A.dir_pinv : nullptr;
+    // own: the lane owns the node; con: the node is constrained.  A CG
+    // direction is zero at constrained nodes by itself (P^-1 and the previous
+    // direction are zero there: every direction is formed as beta p + P^-1 r
+    // from a zero start), so DIR lanes load every node they own and leave the
+    // others' values unset (never read: the commit writes owned nodes only);
+    // plain applies read constrained nodes as 0 unless read_con.
+    auto load = [&](uint32_t node, bool own, bool con, T& u, T& rr, T& pp) {
+        if constexpr (DIR) {
+            u = __builtin_nondeterministic_value(u);
+            rr = __builtin_nondeterministic_value(rr);
+            pp = __builtin_nondeterministic_value(pp);
+            if (own) {
+                const uint32_t bo = node * (uint32_t)sizeof(T);
+                u = *(const T*)(ub + bo);
+                rr = *(const T*)(rb + bo);
+                pp = *(const T*)(pb + bo);
             }
+        } else {
+            u = (T)0;
+            if (own && (!con || A.read_con)) u = A.u[node * A.ns + r * A.rs];
         }
     };
     const bool fown = live && t < NI2;
 #pragma unroll
-    for (int f = 0; f < 6; ++f) load(E.fb[f] + (uint32_t)t, fown && (!fcon[f] || A.read_con), G.f[f], G.rf[f], G.pf[f]);
+    for (int f = 0; f < 6; ++f) load(E.fb[f] + (uint32_t)t, fown, fcon[f], G.f[f], G.rf[f], G.pf[f]);
     const int eq = t / NI, em = t - (t / NI) * NI;
     const bool eown = live && t < 4 * NI;
 #pragma unroll
@@ -509,13 +536,13 @@ __device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live,
         uint32_t node;
         bool con;
         edge_node<NI>(L, E, par, eq & 1, (eq >> 1) & 1, em, &node, &con);
-        load(node, eown && (!con || A.read_con), G.e[par], G.re[par], G.pe[par]);
+        load(node, eown, con, G.e[par], G.re[par], G.pe[par]);
     }
     {
         uint32_t node;
         bool con;
         vertex_node(L, E, t & 1, (t >> 1) & 1, (t >> 2) & 1, &node, &con);
-        load(node, live && t < 8 && (!con || A.read_con), G.v, G.rv, G.pv);
+        load(node, live && t < 8, con, G.v, G.rv, G.pv);
     }
 }
 

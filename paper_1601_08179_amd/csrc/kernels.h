@@ -91,6 +91,8 @@ struct ApplyArgs {
     // Fused CG direction (all null for a plain apply): when dir_r is set the
     // operand is p = beta_r u + pinv r, formed at the gather with fmadd, where
     // u holds the previous direction and beta the per-RHS coefficients [k].
+    // Such applies take RHS-major vectors (ns = 1) and address them, and the
+    // slots, with 32-bit byte offsets (N_s and qlen times sizeof(T) < 2^32).
     const T* dir_r = nullptr;
     const T* dir_pinv = nullptr;
     const double* dir_beta = nullptr;
