@@ -768,6 +768,20 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
         // ---- edges, one direction per round: edge q = 4 par + b0 + 2 b1; the face
         // couplings are line sums of the two bordering faces.
         if (eown) {
+            // FP32: the thread's two coefficient rows (c^eb0, c^eb1: the same
+            // edge bits in every direction), picked once for the three rounds;
+            // FP64 sums both rows and picks (measured 11 % faster there: the
+            // picked rows hold 44 more VGPRs through the rounds)
+            constexpr bool ROWS = sizeof(T) == 4;
+            T c1r[ROWS ? NI : 1], c2r[ROWS ? NI : 1];
+            if constexpr (ROWS) {
+#pragma unroll
+                for (int m2 = 0; m2 < NI; ++m2) {
+                    const T am = ctA[m2], bm = ctB[m2];
+                    c1r[m2] = eb0 ? bm : am;
+                    c2r[m2] = eb1 ? bm : am;
+                }
+            }
 #pragma unroll
             for (int par = 0; par < 3; ++par) {
                 const T dpar = par == 0 ? d1 : (par == 1 ? d2 : d3);
@@ -782,19 +796,27 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                 const int base1 = f1 * NI2 + (par == 0 ? em : em * NI);
                 const int base2 = f2 * NI2 + (par == 2 ? em * NI : em);
                 constexpr int st1_t[3] = {NI, 1, 1}, st2_t[3] = {NI, NI, 1};
-                // both coefficient rows, then the thread's pick (no per-term selects;
-                // measured faster than one row read at a lane-dependent address)
-                T l1a = 0, l1b = 0, l2a = 0, l2b = 0;
+                T l1 = 0, l2 = 0;
+                if constexpr (ROWS) {
 #pragma unroll
-                for (int m2 = 0; m2 < NI; ++m2) {
-                    const T am = ctA[m2], bm = ctB[m2];
-                    const T x1 = F[base1 + m2 * st1_t[par]], x2 = F[base2 + m2 * st2_t[par]];
-                    l1a += am * x1;
-                    l1b += bm * x1;
-                    l2a += am * x2;
-                    l2b += bm * x2;
+                    for (int m2 = 0; m2 < NI; ++m2) {
+                        l1 += c1r[m2] * F[base1 + m2 * st1_t[par]];
+                        l2 += c2r[m2] * F[base2 + m2 * st2_t[par]];
+                    }
+                } else {
+                    T l1a = 0, l1b = 0, l2a = 0, l2b = 0;
+#pragma unroll
+                    for (int m2 = 0; m2 < NI; ++m2) {
+                        const T am = ctA[m2], bm = ctB[m2];
+                        const T x1 = F[base1 + m2 * st1_t[par]], x2 = F[base2 + m2 * st2_t[par]];
+                        l1a += am * x1;
+                        l1b += bm * x1;
+                        l2a += am * x2;
+                        l2b += bm * x2;
+                    }
+                    l1 = eb0 ? l1b : l1a;
+                    l2 = eb1 ? l2b : l2a;
                 }
-                const T l1 = eb0 ? l1b : l1a, l2 = eb1 ? l2b : l2a;
                 const int vlo = par == 0 ? 2 * eb0 + 4 * eb1 : (par == 1 ? eb0 + 4 * eb1 : eb0 + 2 * eb1);
                 const int vhi = vlo + (par == 0 ? 1 : (par == 1 ? 2 : 4));
                 const T ue = UE(q, em);
@@ -810,22 +832,56 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                 }
             }
         }
-        // ---- vertices
+        // ---- vertices: the couplings to the three edges through a vertex are
+        // line sums along those edges.  In FP32 with a whole wave at hand the
+        // 24 sums (8 vertices x 3 directions) run on 24 lanes and every vertex
+        // lane collects its three; otherwise (FP64: measured faster; packed
+        // elements, n_I <= 5) each vertex lane sums all three.
+        constexpr bool VLANES = sizeof(T) == 4 && NE == 1 && NT >= 64;
+        T vsum = 0;
+        if constexpr (VLANES) {
+            if (t < 24) {
+                const int dir = t >> 3, v = t & 7;
+                const int ib = v & 1, jb = (v >> 1) & 1, kb = v >> 2;
+                const int line = dir == 0 ? jb + 2 * kb : (dir == 1 ? 4 + ib + 2 * kb : 8 + ib + 2 * jb);
+                const int bit = dir == 0 ? ib : (dir == 1 ? jb : kb);
+#pragma unroll
+                for (int m2 = 0; m2 < NI; ++m2) {
+                    const T am = ctA[m2], bm = ctB[m2];
+                    vsum += (bit ? bm : am) * UE(line, m2);
+                }
+            }
+        }
+        T vsx = 0, vsy = 0, vsz = 0;
+        if constexpr (VLANES) {
+            vsx = __shfl(vsum, t & 7, 64);
+            vsy = __shfl(vsum, (t & 7) + 8, 64);
+            vsz = __shfl(vsum, (t & 7) + 16, 64);
+        }
         if (vown) {
             const int q = t;
-            T sxa = 0, sxb = 0, sya = 0, syb = 0, sza = 0, szb = 0;
+            T sx, sy, sz;
+            if constexpr (VLANES) {
+                sx = vsx;
+                sy = vsy;
+                sz = vsz;
+            } else {
+                T sxa = 0, sxb = 0, sya = 0, syb = 0, sza = 0, szb = 0;
 #pragma unroll
-            for (int m2 = 0; m2 < NI; ++m2) {
-                const T am = ctA[m2], bm = ctB[m2];
-                const T x = UE(vjb + 2 * vkb, m2), y = UE(4 + vib + 2 * vkb, m2), z = UE(8 + vib + 2 * vjb, m2);
-                sxa += am * x;
-                sxb += bm * x;
-                sya += am * y;
-                syb += bm * y;
-                sza += am * z;
-                szb += bm * z;
+                for (int m2 = 0; m2 < NI; ++m2) {
+                    const T am = ctA[m2], bm = ctB[m2];
+                    const T x = UE(vjb + 2 * vkb, m2), y = UE(4 + vib + 2 * vkb, m2), z = UE(8 + vib + 2 * vjb, m2);
+                    sxa += am * x;
+                    sxb += bm * x;
+                    sya += am * y;
+                    syb += bm * y;
+                    sza += am * z;
+                    szb += bm * z;
+                }
+                sx = vib ? sxb : sxa;
+                sy = vjb ? syb : sya;
+                sz = vkb ? szb : sza;
             }
-            const T sx = vib ? sxb : sxa, sy = vjb ? syb : sya, sz = vkb ? szb : sza;
             const T out = (d0 * m02 * m0 + (d1 + d2 + d3) * m02 * K00) * UV(q) +
                           m02 * K0p * (d1 * UV(q ^ 1) + d2 * UV(q ^ 2) + d3 * UV(q ^ 4)) +
                           m02 * (d1 * sx + d2 * sy + d3 * sz);
