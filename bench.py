@@ -144,7 +144,7 @@ def suite(args):
         # Solver experiment of Sec. 8: manufactured u (stiffness 5) on (0, 2 pi)^3,
         # lambda = 0, 8^3 elements with expansion factor alpha, inhomogeneous
         # Dirichlet values u_ex, stop at a 1e-12 residual reduction.  For alpha = 2
-        # the paper's BT iteration counts follow from Table 3 as solution time per
+        # the paper's BT iteration counts follow from its iteration-times table (Sec. 8) as solution time per
         # DOF / iteration time per DOF (upper bounds: the solution time includes
         # the precomputation).
         table3 = {8: (4.25, 25.6), 12: (3.73, 20.3), 16: (3.47, 17.7), 20: (3.31, 16.1), 24: (3.09, 14.4),

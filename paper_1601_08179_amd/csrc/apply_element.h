@@ -16,7 +16,7 @@
 //    D^-1 per metric class (the paper stores D^-1 per element, Sec. 5);
 //  * eigenspace -> face maps H~_FE (Table 2), line reductions along the normal.
 // Together 13 n_I^3 multiplications per element for the condensed part
-// (Sec. 6) plus O(n_I^2) for the primary part (Table 4).
+// (Sec. 6) plus O(n_I^2) for the primary part (Sec. 7, the operator-complexity table).
 //
 // GPU mapping: one workgroup per element.  The element's 6 faces, 12 edges and
 // 8 vertices are gathered (R^T, index arithmetic on the skeleton layout) into

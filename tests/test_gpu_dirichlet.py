@@ -88,7 +88,8 @@ def test_initial_guess_dirichlet_entries_ignored(lib):
 def test_solver_experiment_iteration_counts(lib, p, paper_iters):
     """Sec. 8's solver test with expansion factor 2 (aspect ratio 128): the BT
     iteration count to a 1e-12 residual reduction matches the count implied by
-    Table 3 (solution time per DOF / iteration time per DOF) within 3."""
+    the paper's iteration-times table (Sec. 8: solution time per DOF / iteration
+    time per DOF) within 3."""
     import torch
     wm = W.solver_experiment_mesh(p, 2.0)
     X = _coords(wm)
