@@ -513,6 +513,7 @@ struct CgWork {
     CgState s;
     double* partials;  // [3][vec_blocks(k)][k] (room for [3][kVecBlocks][k])
     double* energy;    // [n_e][k]
+    double* epart;     // [kEnergyBlocks][k]: first-stage sums of the energies
     double* rho1;      // second slots of rho, active and the stagnation state
     int* act1;         // (fused loop, odd iterations)
     double* rrb1;
@@ -526,7 +527,8 @@ int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
     const size_t ni = 6 * (size_t)k;      // active iters status, active slot 1, stall (2 slots)
     const size_t np = 3 * (size_t)kVecBlocks * k;
     const size_t ne = (size_t)c->n_e * k;
-    const size_t one = ((nd + np + ne) * sizeof(double) + ni * sizeof(int) + 255) / 256 * 256;
+    const size_t nep = (size_t)kEnergyBlocks * k;
+    const size_t one = ((nd + np + ne + nep) * sizeof(double) + ni * sizeof(int) + 255) / 256 * 256;
     int rc = grow(c, c->ws_state, 2 * one);
     if (rc) return rc;
     double* d = (double*)((char*)c->ws_state.ptr + slot * one);
@@ -543,7 +545,8 @@ int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
     w->s.window = 0;
     w->partials = d + nd;
     w->energy = w->partials + np;
-    int* ip = (int*)(w->energy + ne);
+    w->epart = w->energy + ne;
+    int* ip = (int*)(w->epart + nep);
     w->s.active = ip;
     w->s.iters = ip + k;
     w->s.status = ip + 2 * k;
@@ -747,7 +750,7 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
             int rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, r, w.s.beta, 0, nullptr,
                                           w.s.active, Q);
             if (rc) return rc;
-            HIPCHK(c, launch_cg_reduce(w.energy, c->n_e, 1, k, w.s, RED_PQ, st));
+            HIPCHK(c, launch_energy_pq(w.energy, c->n_e, k, w.epart, w.s, st));
             HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, Q, qlen, c->L,
                                         cg_face_slots<T>(), st));
             HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 2, k, w.s, RED_RZ, st));
@@ -1207,7 +1210,7 @@ int run_cg_coarse(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, dou
         rc = apply_transformed<T>(c, p, q, k, RHS_MAJOR, w.energy, st, true, nullptr, nullptr, 0, nullptr, w.s.active,
                                   Q);
         if (rc) return rc;
-        HIPCHK(c, launch_cg_reduce(w.energy, c->n_e, 1, k, w.s, RED_PQ, st));
+        HIPCHK(c, launch_energy_pq(w.energy, c->n_e, k, w.epart, w.s, st));
         HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, Q, qlen, c->L, cg_face_slots<T>(),
                                     st, true));
         rc = coarse_solve<T>(c, r, k, w.s.active, r0, z0, rz_extra, st);

@@ -270,6 +270,11 @@ hipError_t launch_cg_init(const T* b, T* q0, const T* pinv, T* r, T* p, int64_t 
 enum ReduceMode { RED_INIT = 0, RED_PQ = 1, RED_RZ = 2, RED_INIT_KEEP = 3 };
 hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int k, CgState s, int mode,
                             hipStream_t st);
+// p.q of every RHS from the element energies [n_e][k] in two fixed-order
+// stages (block partials into epart [kEnergyBlocks][k], then k_cg_reduce in
+// mode RED_PQ), the same result for every run.
+constexpr int kEnergyBlocks = 256;
+hipError_t launch_energy_pq(const double* energy, int64_t n_e, int k, double* epart, CgState s, hipStream_t st);
 // One CG step on active right-hand sides, with q = H~^ p already formed:
 // p = fmadd(beta, p, pinv r) (the direction the apply used), x += alpha p,
 // r -= alpha q; then q = 0 and partials[0] r.z (z = pinv r), [1] r.r.  Blocks
