@@ -523,7 +523,7 @@ struct CgWork {
 // Device state layout inside ws_state: two independent CG states (slot 0 for
 // the CG iteration, slot 1 for the outer refinement loop of MIXED_IR).
 int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
-    const size_t nd = 9 * (size_t)k + 1;  // rho pq alpha beta rr bb (6k), rho slot 1, rrb (2 slots), tol2
+    const size_t nd = 10 * (size_t)k + 1;  // rho pq alpha beta rr bb (6k), rho slot 1, rrb (2 slots), tol2, xa
     const size_t ni = 6 * (size_t)k;      // active iters status, active slot 1, stall (2 slots)
     const size_t np = 3 * (size_t)kVecBlocks * k;
     const size_t ne = (size_t)c->n_e * k;
@@ -542,6 +542,7 @@ int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
     w->s.rrb = d + 7 * k;
     w->rrb1 = d + 8 * k;
     w->s.tol2 = d + 9 * k;
+    w->s.xa = d + 9 * k + 1;
     w->s.window = 0;
     w->partials = d + nd;
     w->energy = w->partials + np;
@@ -751,12 +752,17 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
                                           w.s.active, Q);
             if (rc) return rc;
             HIPCHK(c, launch_energy_pq(w.energy, c->n_e, k, w.epart, w.s, st));
+            // x is read and written at odd steps only (both steps' updates at
+            // once): the even step's length waits in xa, its direction in p
+            const bool defer = (it & 1) == 0;
             HIPCHK(c, launch_cg_step<T>(x, r, p, q, pinv<T>(c), Ns, k, w.s, w.partials, Q, qlen, c->L,
-                                        cg_face_slots<T>(), st));
-            HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 2, k, w.s, RED_RZ, st));
+                                        cg_face_slots<T>(), st, false, defer ? CG_X_DEFER : CG_X_FLUSH));
+            HIPCHK(c, launch_cg_reduce(w.partials, vec_blocks(k), 2, k, w.s, defer ? RED_RZ_DEFER : RED_RZ, st));
         }
         n_it = it + 1;
     }
+    // right-hand sides whose last step deferred its update (xa != 0)
+    if (!fused && n_it > 0) HIPCHK(c, launch_cg_x_flush<T>(x, p, Ns, k, w.s, st));
     if (fused && n_it > 0) {
         // the last step's r.z reduction, then the state back in slot 0
         const bool odd = ((n_it - 1) & 1) != 0;

@@ -40,6 +40,9 @@ struct CgState {
     // Nullable, [k]: added to r.z in RED_INIT / RED_RZ (the coarse part
     // r0 . A_0^-1 r0 of the two-level preconditioner)
     const double* rz_extra = nullptr;
+    // [k]: the step length whose x update a deferring step left pending (its
+    // direction is still in p), 0 if none; set by RED_INIT* and RED_RZ*
+    double* xa = nullptr;
 };
 
 // Per-iteration view of the CG state for kernels that complete a reduction of
@@ -266,8 +269,10 @@ hipError_t launch_cg_init(const T* b, T* q0, const T* pinv, T* r, T* p, int64_t 
 // Reduce [nparts][k] partials of `nq` quantities; mode selects the CG step logic.
 // RED_INIT_KEEP is RED_INIT for a CG that continues the direction p left by a
 // previous solve (cg_init with keep_p): beta = r.z / rho, rho being the r.z that
-// formed that solve's last direction (kept when it converged).
-enum ReduceMode { RED_INIT = 0, RED_PQ = 1, RED_RZ = 2, RED_INIT_KEEP = 3 };
+// formed that solve's last direction (kept when it converged).  RED_RZ_DEFER
+// is RED_RZ after a step that deferred its x update (CG_X_DEFER): the step
+// length is kept in xa for the next step or for launch_cg_x_flush.
+enum ReduceMode { RED_INIT = 0, RED_PQ = 1, RED_RZ = 2, RED_INIT_KEEP = 3, RED_RZ_DEFER = 4 };
 hipError_t launch_cg_reduce(const double* partials, int64_t nparts, int nq, int k, CgState s, int mode,
                             hipStream_t st);
 // p.q of every RHS from the element energies [n_e][k] in two fixed-order
@@ -283,10 +288,19 @@ hipError_t launch_energy_pq(const double* energy, int64_t n_e, int k, double* ep
 // per-side slots (qs + rhs * qlen, layout.h) and only the q entries that the
 // apply added into are cleared.  p_formed: p already holds the direction the
 // apply used (it is only read), instead of beta p + P^-1 r being formed here.
+// x_mode (with p formed here): CG_X_NOW updates x; CG_X_DEFER leaves x alone
+// (x is then read and written every other step: x += xa p_old + alpha p at the
+// next, CG_X_FLUSH, step, xa being the deferring step's length).  A solve whose
+// last step deferred ends with launch_cg_x_flush.
+enum CgXMode { CG_X_NOW = 0, CG_X_DEFER = 1, CG_X_FLUSH = 2 };
 template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s,
                           double* partials, const T* qs, int64_t qlen, const Layout& L, int face_slots,
-                          hipStream_t st, bool p_formed = false);
+                          hipStream_t st, bool p_formed = false, int x_mode = CG_X_NOW);
+// x += s.xa p for the right-hand sides with a pending update (xa != 0), then
+// xa = 0: the end of a solve whose steps deferred x updates.
+template <typename T>
+hipError_t launch_cg_x_flush(T* x, const T* p, int64_t Ns, int k, CgState s, hipStream_t st);
 // The same step with p.q completed by every block from the element energies
 // f.energy (RED_PQ on slot f.rho / f.act; blocks x = 0 store pq, alpha and a
 // breakdown); partials [2][fused_step_blocks(k)][k] of r.z and r.r for the next

@@ -898,18 +898,20 @@ __global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __re
     const int t = threadIdx.x, r = t % k, j = t / k, npb = blockDim.x / k;
     constexpr int U = 16;
     // per-RHS state read before anything is written, so that no load waits on a store
+    const bool rz_mode = mode == RED_RZ || mode == RED_RZ_DEFER;
     int act = 0, its = 0, stall = 0;
-    double rho = 0.0, bb = 0.0, tol2 = 0.0, rrb = 0.0;
+    double rho = 0.0, bb = 0.0, tol2 = 0.0, rrb = 0.0, alpha_now = 0.0;
     if (t < k) {
         act = s.active[t];
         its = s.iters[t];
         rho = s.rho[t];
         bb = s.bb[t];
         tol2 = s.tol2[0];
-        if (mode == RED_RZ) {
+        if (rz_mode) {
             rrb = s.rrb[t];
             stall = s.stall[t];
         }
+        if (mode == RED_RZ_DEFER) alpha_now = s.alpha[t];
     }
     double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t m0 = j; m0 < nparts; m0 += (int64_t)U * npb) {
@@ -984,6 +986,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __re
             s.active[r] = bad ? 0 : ((rr > tol2 * b2) ? 1 : 0);
             s.rrb[r] = rr;
             s.stall[r] = 0;
+            if (s.xa) s.xa[r] = 0.0;
         } else if (mode == RED_PQ) {
             const double pq = t0;
             s.pq[r] = pq;
@@ -1000,11 +1003,13 @@ __global__ __launch_bounds__(kReduceThreads) void k_cg_reduce(const double* __re
                 }
             }
             s.alpha[r] = alpha;
-        } else {  // RED_RZ
+        } else {  // RED_RZ, RED_RZ_DEFER
             const double rz = t0 + (s.rz_extra ? s.rz_extra[r] : 0.0), rr = t1;
             double beta = 0.0;
             if (act) {
                 s.iters[r] = its + 1;
+                // a deferring step leaves alpha p to the next step or the flush
+                if (s.xa) s.xa[r] = mode == RED_RZ_DEFER ? alpha_now : 0.0;
                 s.rr[r] = rr;
                 if (!isfinite(rr) || !isfinite(rz)) {
                     s.status[r] = -5;
@@ -1089,11 +1094,12 @@ __device__ inline bool cg_q_clear(const Layout& L, int64_t n, int face_slots) {
     return !SLOTS || (!face_slots && n < L.oEx);
 }
 
-template <typename T, bool SLOTS, bool PFORMED = false>
+template <typename T, bool SLOTS, bool PFORMED = false, int XM = CG_X_NOW>
 __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
                                                  T* __restrict__ q, const T* __restrict__ pinv, int64_t Ns, int k,
                                                  CgState s, double* __restrict__ partials, const T* __restrict__ qs,
                                                  int64_t qlen, Layout L, int fsl) {
+    static_assert(XM == CG_X_NOW || !PFORMED, "deferred x updates need the previous direction, which p_formed overwrites");
     const int rhs = blockIdx.y;
     const int64_t off = (int64_t)rhs * Ns, stride = (int64_t)gridDim.x * blockDim.x;
     const T alpha = (T)s.alpha[rhs];
@@ -1101,6 +1107,8 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
     // A stopped right-hand side keeps x, r and p; its q is not read again (the
     // apply skips it) and its partial sums are ignored.
     if (s.active[rhs] == 0) return;
+    // the length of the previous (deferring) step, whose direction p holds
+    const T xa = XM == CG_X_FLUSH ? (T)s.xa[rhs] : (T)0;
     double acc[2] = {0.0, 0.0};
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < Ns; n += stride) {
         const int64_t idx = off + n;
@@ -1111,11 +1119,14 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
         T pv;
         if constexpr (PFORMED) {
             pv = p[idx];  // formed before the apply (two-level preconditioner)
+            x[idx] += alpha * pv;
         } else {
-            pv = fmadd(beta, p[idx], pn * rv);  // the direction the apply used
+            const T pold = p[idx];
+            pv = fmadd(beta, pold, pn * rv);  // the direction the apply used
             p[idx] = pv;
+            if constexpr (XM == CG_X_NOW) x[idx] += alpha * pv;
+            if constexpr (XM == CG_X_FLUSH) x[idx] += fmadd(xa, pold, alpha * pv);
         }
-        x[idx] += alpha * pv;
         rv -= alpha * qv;
         r[idx] = rv;
         const T z = pn * rv;
@@ -1125,9 +1136,27 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ x, T* __restric
     block_partials<2>(acc, k, partials);
 }
 
+template <typename T, int XM>
+hipError_t launch_cg_step_x(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s, double* partials,
+                            const T* qs, int64_t qlen, const Layout& L, int face_slots, hipStream_t st) {
+    if (qs)
+        hipLaunchKernelGGL((k_cg_step<T, true, false, XM>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q,
+                           pinv, Ns, k, s, partials, qs, qlen, L, face_slots);
+    else
+        hipLaunchKernelGGL((k_cg_step<T, false, false, XM>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q,
+                           pinv, Ns, k, s, partials, qs, qlen, L, face_slots);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s, double* partials,
-                          const T* qs, int64_t qlen, const Layout& L, int face_slots, hipStream_t st, bool p_formed) {
+                          const T* qs, int64_t qlen, const Layout& L, int face_slots, hipStream_t st, bool p_formed,
+                          int x_mode) {
+    if (x_mode != CG_X_NOW && (p_formed || !s.xa)) return hipErrorInvalidValue;
+    if (x_mode == CG_X_DEFER)
+        return launch_cg_step_x<T, CG_X_DEFER>(x, r, p, q, pinv, Ns, k, s, partials, qs, qlen, L, face_slots, st);
+    if (x_mode == CG_X_FLUSH)
+        return launch_cg_step_x<T, CG_X_FLUSH>(x, r, p, q, pinv, Ns, k, s, partials, qs, qlen, L, face_slots, st);
     if (p_formed) {
         if (qs)
             hipLaunchKernelGGL((k_cg_step<T, true, true>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, r, p, q, pinv,
@@ -1146,9 +1175,37 @@ hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int
     return hipGetLastError();
 }
 template hipError_t launch_cg_step<double>(double*, double*, double*, double*, const double*, int64_t, int, CgState,
-                                           double*, const double*, int64_t, const Layout&, int, hipStream_t, bool);
+                                           double*, const double*, int64_t, const Layout&, int, hipStream_t, bool,
+                                           int);
 template hipError_t launch_cg_step<float>(float*, float*, float*, float*, const float*, int64_t, int, CgState, double*,
-                                          const float*, int64_t, const Layout&, int, hipStream_t, bool);
+                                          const float*, int64_t, const Layout&, int, hipStream_t, bool, int);
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_x_flush(T* __restrict__ x, const T* __restrict__ p, int64_t Ns,
+                                                    const double* __restrict__ xa) {
+    const int rhs = blockIdx.y;
+    const T a = (T)xa[rhs];
+    if (a == (T)0) return;
+    const int64_t off = (int64_t)rhs * Ns, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < Ns; n += stride) x[off + n] += a * p[off + n];
+}
+
+// Clears xa in a second launch: every block of a RHS reads it before any clears it.
+__global__ void k_cg_xa_clear(double* __restrict__ xa, int k) {
+    if ((int)threadIdx.x < k) xa[threadIdx.x] = 0.0;
+}
+
+template <typename T>
+hipError_t launch_cg_x_flush(T* x, const T* p, int64_t Ns, int k, CgState s, hipStream_t st) {
+    if (!s.xa || k < 1 || k > kMaxRhs) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_cg_x_flush<T>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, p, Ns, s.xa);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cg_xa_clear, dim3(1), dim3(k), 0, st, s.xa, k);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_x_flush<double>(double*, const double*, int64_t, int, CgState, hipStream_t);
+template hipError_t launch_cg_x_flush<float>(float*, const float*, int64_t, int, CgState, hipStream_t);
 
 int fused_step_blocks(int k) { return std::max(1, 256 / k); }
 
