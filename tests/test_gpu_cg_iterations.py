@@ -78,3 +78,49 @@ def test_fused_loop_polls_every_iteration_after_another_context(lib):
         its.append(info[0]["iters"])
         ctx.close()
     assert len(set(its)) == 1, its
+
+
+def _oracle_bt_iterate(At, bt, n):
+    """x after n iterations of the same diagonally preconditioned CG (x0 = 0)."""
+    d = np.diag(At).copy()
+    x = np.zeros_like(bt)
+    r = bt.copy()
+    z = r / d
+    p = z.copy()
+    rho = r @ z
+    for _ in range(n):
+        q = At @ p
+        alpha = rho / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        z = r / d
+        rho_new = r @ z
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    return x
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 6])
+def test_stepwise_iterate_after_n_steps(lib, n):
+    """The loop with separate reductions (deterministic mode takes it) updates
+    x at every other step and adds a pending update at the end of the solve:
+    after n = 1, 2, 5, 6 iterations (odd and even counts) each of three RHS
+    holds the oracle CG's n-th iterate."""
+    import torch
+    print("case n", n, flush=True)
+    ctx, op, g, free = both(MESHES["stretched3_p5"]())
+    A, fs, T = oracle_transform(op)
+    f = W.random_skeleton_input(op.sizes["N"], k=3, seed=93)
+    skel = torch.zeros((ctx.N_s, 3), dtype=torch.float64, device="cuda")
+    _, info = ctx.solve(torch.as_tensor(f, device="cuda"), tol=1e-14, max_iter=n, skel_out=skel,
+                        raise_on_notconv=False, deterministic=True)
+    phys = ctx.transform(skel, lib.COEF_TO_PHYSICAL).cpu().numpy()
+    pos = {int(v): i for i, v in enumerate(fs)}
+    rows = np.array([pos[int(v)] for v in g[free]])
+    for r in range(3):
+        assert info[r]["iters"] == n, info[r]
+        b = op.condensed_rhs(f[r])[fs]
+        x = T @ _oracle_bt_iterate(T.T @ A @ T, T.T @ b, n)
+        got = phys[free, r]
+        assert np.linalg.norm(got - x[rows]) <= 1e-11 * np.linalg.norm(x), (r, n)
+    ctx.close()
