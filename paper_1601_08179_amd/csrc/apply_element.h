@@ -486,8 +486,9 @@ struct Gathered {
     T pf[6], pe[3], pv;
 };
 
-// Issue the loads of item (e, r); nothing is waited for here.
-template <typename T, int NI, bool DIR>
+// Issue the loads of item (e, r); nothing is waited for here.  Edge node
+// (edge te / n_I, node te mod n_I) is lane te + ESHIFT's.
+template <typename T, int NI, bool DIR, int ESHIFT = 0>
 __device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live, uint32_t r, int t,
                                     Gathered<T, DIR>& G) {
     constexpr int NI2 = NI * NI;
@@ -538,8 +539,9 @@ __device__ inline void gather_issue(const ApplyArgs<T>& A, int64_t e, bool live,
     const bool fown = live && t < NI2;
 #pragma unroll
     for (int f = 0; f < 6; ++f) load(E.fb[f] + (uint32_t)t, fown, fcon[f], G.f[f], G.rf[f], G.pf[f]);
-    const int eq = t / NI, em = t - (t / NI) * NI;
-    const bool eown = live && t < 4 * NI;
+    const int te = t - ESHIFT, tq = te >= 0 ? te : 0;
+    const int eq = tq / NI, em = tq - (tq / NI) * NI;
+    const bool eown = live && te >= 0 && te < 4 * NI;
 #pragma unroll
     for (int par = 0; par < 3; ++par) {
         uint32_t node;
@@ -588,10 +590,19 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
     const T m0 = A.tab.m0, K00 = A.tab.K00, K0p = A.tab.K0p, m02 = m0 * m0;
 
     // per-thread position and 1D coefficients of the face slot (s1 slow, s2 fast),
-    // edge node and vertex: the same for every element
-    const bool fown = t < NI2, eown = t < 4 * NI, vown = t < 8;
+    // edge node and vertex: the same for every element.  With several waves
+    // the edge nodes go to the last wave (lanes NT - 64 ..), which holds the
+    // fewest face slots, and the vertices stay in the first: the waves' row
+    // work is then closer to even (they meet at the energy barrier).  Measured
+    // faster in FP32 (CG apply at n_I = 11, 16 RHS: 4.6 %), in the fused FP64
+    // CG kernels and in FP64 at n_I = 15; slower in the other FP64 kernels at
+    // n_I = 11 (4-6 %), whose edge rounds sum both coefficient rows.
+    static_assert(4 * NI <= 64, "the edge nodes of one direction fit one wave");
+    constexpr int ESHIFT = NE == 1 && NT >= 128 && (sizeof(T) == 4 || FZ || NI >= 14) ? NT - 64 : 0;
+    const int te = t - ESHIFT, tq = te >= 0 ? te : 0;
+    const bool fown = t < NI2, eown = te >= 0 && te < 4 * NI, vown = t < 8;
     const int s1 = t / NI, s2 = t - (t / NI) * NI;
-    const int eq = t / NI, em = s2;                      // edge qq = b0 + 2 b1, node m
+    const int eq = tq / NI, em = tq - (tq / NI) * NI;  // edge qq = b0 + 2 b1, node m
     const int eb0 = eq & 1, eb1 = (eq >> 1) & 1;
     const int vib = t & 1, vjb = (t >> 1) & 1, vkb = (t >> 2) & 1;
     T ta1 = 0, tb1 = 0, tl1 = 0, ta2 = 0, tb2 = 0, tl2 = 0;
@@ -638,7 +649,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
             }
         }
         Gathered<T, DIR> G;
-        gather_issue<T, NI, DIR>(A, e, live, r, t, G);
+        gather_issue<T, NI, DIR, ESHIFT>(A, e, live, r, t, G);
         // FP32: the thread's D^-1 column from its metric class's table (one
         // class per workgroup: single-element groups only), loaded with the
         // gather.  The table holds 1/D rounded once from FP64, which the FP32
@@ -678,7 +689,7 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
             }
             if (eown) {
 #pragma unroll
-                for (int par = 0; par < 3; ++par) F[NFACE + par * 4 * NI + t] = val(G.e[par], G.re[par], G.pe[par]);
+                for (int par = 0; par < 3; ++par) F[NFACE + par * 4 * NI + te] = val(G.e[par], G.re[par], G.pe[par]);
             }
             if (vown) UV(t) = val(G.v, G.rv, G.pv);
         }
@@ -777,6 +788,14 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
         // ---- edges, one direction per round: edge q = 4 par + b0 + 2 b1; the face
         // couplings are line sums of the two bordering faces.
         if (eown) {
+            // the 1D coefficients at the edge node m: ta2, tb2, tl2 where the
+            // edge and face lanes coincide, else from the LDS copy
+            T tae = ta2, tbe = tb2, tle = tl2;
+            if constexpr (ESHIFT > 0) {
+                tae = ctA[em];
+                tbe = ctB[em];
+                tle = ctL[em];
+            }
             // FP32: the thread's two coefficient rows (c^eb0, c^eb1: the same
             // edge bits in every direction), picked once for the three rounds;
             // FP64 sums both rows and picks (measured 11 % faster there: the
@@ -829,9 +848,8 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
                 const int vlo = par == 0 ? 2 * eb0 + 4 * eb1 : (par == 1 ? eb0 + 4 * eb1 : eb0 + 2 * eb1);
                 const int vhi = vlo + (par == 0 ? 1 : (par == 1 ? 2 : 4));
                 const T ue = UE(q, em);
-                // tl2, ta2, tb2 are the 1D coefficients at the edge node m = s2
-                const T out = (dg0 + dpar * m02 * tl2) * ue + m0 * K0p * (do1 * UE(q ^ 1, em) + do2 * UE(q ^ 2, em)) +
-                              dpar * m02 * (ta2 * UV(vlo) + tb2 * UV(vhi)) + m0 * (do1 * l1 + do2 * l2);
+                const T out = (dg0 + dpar * m02 * tle) * ue + m0 * K0p * (do1 * UE(q ^ 1, em) + do2 * UE(q ^ 2, em)) +
+                              dpar * m02 * (tae * UV(vlo) + tbe * UV(vhi)) + m0 * (do1 * l1 + do2 * l2);
                 uint32_t node;
                 bool con;
                 edge_node<NI>(L, E, par, eb0, eb1, em, &node, &con);
