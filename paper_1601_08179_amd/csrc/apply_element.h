@@ -463,7 +463,7 @@ __device__ inline void edge_node(const Layout& L, const ElemEnt& E, int par, int
     const uint32_t n1 = (uint32_t)L.n1, n2 = (uint32_t)L.n2;
     const uint32_t s0 = par == 0 ? n1 * NI : (uint32_t)NI;
     const uint32_t s1 = par == 0 ? (n2 + 1) * n1 * NI : (par == 1 ? n2 * (n1 + 1) * NI : (n1 + 1) * NI);
-    *node = E.eb[par] + b0 * s0 + b1 * s1 + m;
+    *node = E.eb[par] + (b0 ? s0 : 0u) + (b1 ? s1 : 0u) + m;
     const bool c0 = par == 0 ? (b0 ? E.cy1 : E.cy0) : (b0 ? E.cx1 : E.cx0);
     const bool c1 = par == 2 ? (b1 ? E.cy1 : E.cy0) : (b1 ? E.cz1 : E.cz0);
     *con = c0 || c1;
@@ -471,7 +471,7 @@ __device__ inline void edge_node(const Layout& L, const ElemEnt& E, int par, int
 __device__ inline void vertex_node(const Layout& L, const ElemEnt& E, int ib, int jb, int kb, uint32_t* node,
                                    bool* con) {
     const uint32_t n1 = (uint32_t)L.n1, n2 = (uint32_t)L.n2;
-    *node = E.vb + ib + jb * (n1 + 1) + kb * (n2 + 1) * (n1 + 1);
+    *node = E.vb + ib + (jb ? n1 + 1 : 0u) + (kb ? (n2 + 1) * (n1 + 1) : 0u);
     *con = (ib ? E.cx1 : E.cx0) || (jb ? E.cy1 : E.cy0) || (kb ? E.cz1 : E.cz0);
 }
 

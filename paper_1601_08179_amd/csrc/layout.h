@@ -88,9 +88,10 @@ __host__ __device__ inline int64_t slot_len(const Layout& L) {
 // Offset of (node, slot) within one right-hand side (slot_len < 2^31).
 __host__ __device__ inline uint32_t slot_addr(const Layout& L, uint32_t node, int slot) {
     const uint32_t Ns = (uint32_t)L.Ns, oEx = (uint32_t)L.oEx, oV = (uint32_t)L.oV;
-    if (slot < 2) return (uint32_t)slot * Ns + node;
+    // (selects instead of lane-by-uniform products where the slot is a bit)
+    if (slot < 2) return (slot ? Ns : 0u) + node;
     const uint32_t nE = oV - oEx;
-    if (node < oV) return 2 * Ns + (uint32_t)(slot - 2) * nE + (node - oEx);
+    if (node < oV) return 2 * Ns + (slot == 3 ? nE : 0u) + (node - oEx);
     return 2 * Ns + 2 * nE + (uint32_t)(slot - 2) * (Ns - oV) + (node - oV);
 }
 // Slot of element entity `id` (the numbering of element_entity below) for the
