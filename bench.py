@@ -84,6 +84,11 @@ def suite(args):
     def emit(d):
         print(json.dumps(d), flush=True)
 
+    if "2" in args.suite:
+        # the 16^3, p = 8 single-RHS FP64 line alone (its kernel trace)
+        d = config2_line(args, semcond, torch)
+        d["case"] = "config2: 16^3 elements, p=8, one RHS, FP64"
+        emit(d)
     if "3" in args.suite:
         for p in (2, 4, 8, 16, 32):
             for ar in (1, 8, 32, 128):
@@ -567,7 +572,8 @@ def main():
     ap.add_argument("--no-two-level", action="store_true", help="skip the two-level preconditioner runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--suite", default="", help="extra measurements instead of the default line: "
-                    "any of 3 (p/AR sweep), 4 (16 RHS, every launch kind), 5 (differentiable solve), "
+                    "any of 2 (the 16^3, p = 8 single-RHS FP64 solve alone), 3 (p/AR sweep), 4 (16 RHS, "
+                    "every launch kind), 5 (differentiable solve), "
                     "D (the paper's solver experiment with inhomogeneous Dirichlet values), S (its "
                     "element-count scaling), E (the operator experiment: TPT, TPC, MMC at p = 2..32), "
                     "e.g. --suite 345DSE")
