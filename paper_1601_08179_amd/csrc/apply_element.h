@@ -595,10 +595,14 @@ __device__ void apply_elements_cube(const ApplyArgs<T>& A, int64_t e0, int64_t s
     // fewest face slots, and the vertices stay in the first: the waves' row
     // work is then closer to even (they meet at the energy barrier).  Measured
     // faster in FP32 (CG apply at n_I = 11, 16 RHS: 4.6 %), in the fused FP64
-    // CG kernels and in FP64 at n_I = 15; slower in the other FP64 kernels at
-    // n_I = 11 (4-6 %), whose edge rounds sum both coefficient rows.
+    // CG kernels, in the other FP64 CG applies except at n_I = 11 (16-RHS
+    // solves 2.5-4 % faster at n_I = 9, 10, 12, 13) and in the plain FP64
+    // applies at n_I >= 12; slower in the plain FP64 applies at n_I = 9..11
+    // and in the FP64 CG apply at n_I = 11 (3-5 %), whose edge rounds sum both
+    // coefficient rows.
     static_assert(4 * NI <= 64, "the edge nodes of one direction fit one wave");
-    constexpr int ESHIFT = NE == 1 && NT >= 128 && (sizeof(T) == 4 || FZ || NI >= 14) ? NT - 64 : 0;
+    constexpr int ESHIFT =
+        NE == 1 && NT >= 128 && (sizeof(T) == 4 || FZ || (NI != 11 && (DIR || NI >= 12))) ? NT - 64 : 0;
     const int te = t - ESHIFT, tq = te >= 0 ? te : 0;
     const bool fown = t < NI2, eown = te >= 0 && te < 4 * NI, vown = t < 8;
     const int s1 = t / NI, s2 = t - (t / NI) * NI;
