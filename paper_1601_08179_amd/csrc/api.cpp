@@ -518,12 +518,14 @@ struct CgWork {
     int* act1;         // (fused loop, odd iterations)
     double* rrb1;
     int* stall1;
+    double* alpha1;    // second alpha slot (fused loop, odd iterations)
 };
 
 // Device state layout inside ws_state: two independent CG states (slot 0 for
 // the CG iteration, slot 1 for the outer refinement loop of MIXED_IR).
 int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
-    const size_t nd = 10 * (size_t)k + 1;  // rho pq alpha beta rr bb (6k), rho slot 1, rrb (2 slots), tol2, xa
+    const size_t nd = 11 * (size_t)k + 1;  // rho pq alpha beta rr bb (6k), rho slot 1, rrb (2 slots), tol2, xa,
+                                           // alpha slot 1
     const size_t ni = 6 * (size_t)k;      // active iters status, active slot 1, stall (2 slots)
     const size_t np = 3 * (size_t)kVecBlocks * k;
     const size_t ne = (size_t)c->n_e * k;
@@ -543,6 +545,7 @@ int cg_state(semcond_ctx* c, int k, int slot, CgWork* w) {
     w->rrb1 = d + 8 * k;
     w->s.tol2 = d + 9 * k;
     w->s.xa = d + 9 * k + 1;
+    w->alpha1 = d + 10 * k + 1;
     w->s.window = 0;
     w->partials = d + nd;
     w->energy = w->partials + np;
@@ -618,7 +621,12 @@ CgFuse fuse_view(const CgWork& w, int k, int ph, int64_t n_e) {
     f.bb = w.s.bb;
     f.tol2 = w.s.tol2;
     f.pq = w.s.pq;
-    f.alpha = w.s.alpha;
+    // x is read and written at odd iterations only (both steps' updates at
+    // once); an even iteration's alpha waits in slot 0 for the next step, or
+    // for the flush at the end of the loop
+    f.alpha = ph ? w.alpha1 : w.s.alpha;
+    f.alpha_prev = ph ? w.s.alpha : w.alpha1;
+    f.x_mode = ph ? CG_X_FLUSH : CG_X_DEFER;
     f.rrb_prev = rrb[1 - ph];
     f.rrb = rrb[ph];
     f.stall_prev = stall[1 - ph];
@@ -780,6 +788,9 @@ int run_cg(semcond_ctx* c, const T* b, T* x, T* r, T* p, T* q, int k, double tol
             HIPCHK(c, hipMemcpyAsync(w.s.rrb, w.rrb1, k * sizeof(double), hipMemcpyDeviceToDevice, st));
             HIPCHK(c, hipMemcpyAsync(w.s.stall, w.stall1, k * sizeof(int), hipMemcpyDeviceToDevice, st));
         }
+        // right-hand sides whose last step (of even index: an odd step count)
+        // deferred its x update; its alpha is in slot 0, its direction in p
+        HIPCHK(c, launch_cg_x_flush_parity<T>(x, p, Ns, k, w.s.iters, w.s.alpha, st));
     }
     return SEMCOND_OK;
 }

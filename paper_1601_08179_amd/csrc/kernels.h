@@ -67,7 +67,11 @@ struct CgFuse {
     const double* bb;
     const double* tol2;
     double* pq;
+    // alpha has two slots too: the step stores this iteration's into alpha and
+    // reads the previous iteration's from alpha_prev (x_mode CG_X_FLUSH)
     double* alpha;
+    const double* alpha_prev;
+    int x_mode;  // the step's CgXMode
     // stagnation state with the same two slots as rho (see CgState)
     const double* rrb_prev;
     double* rrb;
@@ -297,6 +301,12 @@ template <typename T>
 hipError_t launch_cg_step(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, CgState s,
                           double* partials, const T* qs, int64_t qlen, const Layout& L, int face_slots,
                           hipStream_t st, bool p_formed = false, int x_mode = CG_X_NOW);
+// x += alpha0 p for the right-hand sides whose step count iters is odd (their
+// last step, of even index, deferred its update; alpha0: the even iterations'
+// alpha slot): the end of a fused loop.
+template <typename T>
+hipError_t launch_cg_x_flush_parity(T* x, const T* p, int64_t Ns, int k, const int* iters, const double* alpha0,
+                                    hipStream_t st);
 // x += s.xa p for the right-hand sides with a pending update (xa != 0), then
 // xa = 0: the end of a solve whose steps deferred x updates.
 template <typename T>
@@ -304,7 +314,9 @@ hipError_t launch_cg_x_flush(T* x, const T* p, int64_t Ns, int k, CgState s, hip
 // The same step with p.q completed by every block from the element energies
 // f.energy (RED_PQ on slot f.rho / f.act; blocks x = 0 store pq, alpha and a
 // breakdown); partials [2][fused_step_blocks(k)][k] of r.z and r.r for the next
-// apply's fused completion.
+// apply's fused completion.  f.x_mode as launch_cg_step's x_mode, with the
+// deferring step's length in f.alpha_prev at the flushing step; a loop whose
+// even iterations defer ends with launch_cg_x_flush_parity.
 constexpr int kFusedStepThreads = 1024;
 int fused_step_blocks(int k);
 template <typename T>

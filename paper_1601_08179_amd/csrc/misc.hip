@@ -1205,6 +1205,29 @@ hipError_t launch_cg_x_flush(T* x, const T* p, int64_t Ns, int k, CgState s, hip
     return hipGetLastError();
 }
 template hipError_t launch_cg_x_flush<double>(double*, const double*, int64_t, int, CgState, hipStream_t);
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_x_flush_parity(T* __restrict__ x, const T* __restrict__ p, int64_t Ns,
+                                                           const int* __restrict__ iters,
+                                                           const double* __restrict__ alpha0) {
+    const int rhs = blockIdx.y;
+    if ((iters[rhs] & 1) == 0) return;
+    const T a = (T)alpha0[rhs];
+    const int64_t off = (int64_t)rhs * Ns, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < Ns; n += stride) x[off + n] += a * p[off + n];
+}
+
+template <typename T>
+hipError_t launch_cg_x_flush_parity(T* x, const T* p, int64_t Ns, int k, const int* iters, const double* alpha0,
+                                    hipStream_t st) {
+    if (!iters || !alpha0 || k < 1 || k > kMaxRhs) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_cg_x_flush_parity<T>), dim3(vec_blocks(k), k), dim3(256), 0, st, x, p, Ns, iters, alpha0);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_x_flush_parity<double>(double*, const double*, int64_t, int, const int*, const double*,
+                                                     hipStream_t);
+template hipError_t launch_cg_x_flush_parity<float>(float*, const float*, int64_t, int, const int*, const double*,
+                                                    hipStream_t);
 template hipError_t launch_cg_x_flush<float>(float*, const float*, int64_t, int, CgState, hipStream_t);
 
 int fused_step_blocks(int k) { return std::max(1, 256 / k); }
@@ -1213,7 +1236,7 @@ int fused_step_blocks(int k) { return std::max(1, 256 / k); }
 // (blocks of kFusedStepThreads threads, fused_step_blocks(k) per RHS: few
 // blocks, so that each apply workgroup's later reduction of their partials
 // stays small).
-template <typename T, bool SLOTS>
+template <typename T, bool SLOTS, int XM>
 __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restrict__ x, T* __restrict__ r,
                                                                      T* __restrict__ p, T* __restrict__ q,
                                                                      const T* __restrict__ pinv, int64_t Ns, int k,
@@ -1232,13 +1255,16 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
     // a stopped RHS keeps x, r and p; its q and partial sums are not read again
     if (!act) return;
     const T beta = (T)f.beta[rhs];
+    // the previous (deferring) step's length: its slot is not written in this launch
+    const T xa = XM == CG_X_FLUSH ? (T)f.alpha_prev[rhs] : (T)0;
     double acc[2] = {0.0, 0.0};
-    auto node = [&](int64_t n, T rv, T qv, T pn, T pold, T xv) __attribute__((always_inline)) {
+    auto node = [&](int64_t n, T rv, T qv, T pn, T pold) __attribute__((always_inline)) {
         const int64_t idx = off + n;
         if (cg_q_clear<SLOTS>(L, n, fsl)) q[idx] = (T)0;  // q is accumulated from zero by the next apply
         const T pv = fmadd(beta, pold, pn * rv);  // the direction the apply used
         p[idx] = pv;
-        x[idx] = xv + alpha * pv;
+        if constexpr (XM == CG_X_NOW) x[idx] += alpha * pv;
+        if constexpr (XM == CG_X_FLUSH) x[idx] += fmadd(xa, pold, alpha * pv);
         rv -= alpha * qv;
         r[idx] = rv;
         const T z = pn * rv;
@@ -1247,7 +1273,7 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
     };
     for (int64_t n = (int64_t)blockIdx.x * NT + threadIdx.x; n < Ns; n += stride) {
         const int64_t idx = off + n;
-        node(n, r[idx], cg_q<T, SLOTS>(q, qs, qlen, L, rhs, idx, n, fsl), pinv[n], p[idx], x[idx]);
+        node(n, r[idx], cg_q<T, SLOTS>(q, qs, qlen, L, rhs, idx, n, fsl), pinv[n], p[idx]);
     }
 #pragma unroll
     for (int qq = 0; qq < 2; ++qq) acc[qq] = wave_sum(acc[qq]);
@@ -1264,17 +1290,32 @@ __global__ __launch_bounds__(kFusedStepThreads) void k_cg_step_fused(T* __restri
     }
 }
 
+template <typename T, int XM>
+hipError_t launch_cg_step_fused_x(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, const CgFuse& f,
+                                  double* partials, const T* qs, int64_t qlen, const Layout& L, int face_slots,
+                                  hipStream_t st) {
+    if (qs)
+        hipLaunchKernelGGL((k_cg_step_fused<T, true, XM>), dim3(fused_step_blocks(k), k), dim3(kFusedStepThreads), 0,
+                           st, x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L, face_slots);
+    else
+        hipLaunchKernelGGL((k_cg_step_fused<T, false, XM>), dim3(fused_step_blocks(k), k), dim3(kFusedStepThreads), 0,
+                           st, x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L, face_slots);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_cg_step_fused(T* x, T* r, T* p, T* q, const T* pinv, int64_t Ns, int k, const CgFuse& f,
                                 double* partials, const T* qs, int64_t qlen, const Layout& L, int face_slots,
                                 hipStream_t st) {
-    if (qs)
-        hipLaunchKernelGGL((k_cg_step_fused<T, true>), dim3(fused_step_blocks(k), k), dim3(kFusedStepThreads), 0, st,
-                           x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L, face_slots);
-    else
-        hipLaunchKernelGGL((k_cg_step_fused<T, false>), dim3(fused_step_blocks(k), k), dim3(kFusedStepThreads), 0, st,
-                           x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L, face_slots);
-    return hipGetLastError();
+    if (f.x_mode == CG_X_DEFER)
+        return launch_cg_step_fused_x<T, CG_X_DEFER>(x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L, face_slots,
+                                                     st);
+    if (f.x_mode == CG_X_FLUSH) {
+        if (!f.alpha_prev) return hipErrorInvalidValue;
+        return launch_cg_step_fused_x<T, CG_X_FLUSH>(x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L, face_slots,
+                                                     st);
+    }
+    return launch_cg_step_fused_x<T, CG_X_NOW>(x, r, p, q, pinv, Ns, k, f, partials, qs, qlen, L, face_slots, st);
 }
 template hipError_t launch_cg_step_fused<double>(double*, double*, double*, double*, const double*, int64_t, int,
                                                  const CgFuse&, double*, const double*, int64_t, const Layout&, int,

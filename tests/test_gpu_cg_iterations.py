@@ -100,20 +100,22 @@ def _oracle_bt_iterate(At, bt, n):
     return x
 
 
+@pytest.mark.parametrize("det", [True, False])
 @pytest.mark.parametrize("n", [1, 2, 5, 6])
-def test_stepwise_iterate_after_n_steps(lib, n):
-    """The loop with separate reductions (deterministic mode takes it) updates
-    x at every other step and adds a pending update at the end of the solve:
+def test_stepwise_iterate_after_n_steps(lib, n, det):
+    """Both one-launch-per-step loops (deterministic mode takes the one with
+    separate reductions; this small mesh otherwise runs the fused loop) update
+    x at every other step and add a pending update at the end of the solve:
     after n = 1, 2, 5, 6 iterations (odd and even counts) each of three RHS
     holds the oracle CG's n-th iterate."""
     import torch
-    print("case n", n, flush=True)
+    print("case n", n, "deterministic", det, flush=True)
     ctx, op, g, free = both(MESHES["stretched3_p5"]())
     A, fs, T = oracle_transform(op)
     f = W.random_skeleton_input(op.sizes["N"], k=3, seed=93)
     skel = torch.zeros((ctx.N_s, 3), dtype=torch.float64, device="cuda")
     _, info = ctx.solve(torch.as_tensor(f, device="cuda"), tol=1e-14, max_iter=n, skel_out=skel,
-                        raise_on_notconv=False, deterministic=True)
+                        raise_on_notconv=False, deterministic=det, persistent=False)
     phys = ctx.transform(skel, lib.COEF_TO_PHYSICAL).cpu().numpy()
     pos = {int(v): i for i, v in enumerate(fs)}
     rows = np.array([pos[int(v)] for v in g[free]])
