@@ -588,8 +588,8 @@ def main():
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_command)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only; multi-GPU runs are not part of this build "
-              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only: the solver runs on a single GPU and has no "
+              "multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.suite:
         suite(args)
